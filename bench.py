@@ -1,0 +1,207 @@
+"""Benchmark of the steady BTE transport path on one MI355X.
+
+A step is one full iteration of the hot path over the whole workload:
+lagged boundary inflow, the transport sweep of every (band, direction)
+system, the FP64 band x direction reductions, the FP64 synthetic diffusion
+correction and the FP64 residual.  value = cell*band*direction updates per
+second over the timed steps (inputs resident in HBM).
+
+Default workload: the 3D non-gray box (24^3 = 13,824 hex cells, 16 bands,
+128 directions), FP32-stored sweeps with FP64 reductions, synthetic scheme.
+
+Also reported on the same line:
+  roofline      the sweep kernel's algorithmic bytes per launch / its mean
+                HIP-event duration in the timed region, against 8 TB/s;
+  cpu_baseline  the oracle on this host's cores for a bounded number of
+                iterations of the same workload;
+  converge      time-to-converge of the mixed and the FP64 path (same
+                stopping rule), with their error against the stored oracle
+                reference when one exists.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell·band·dir updates/s & time-to-converge (mixed vs FP64 @1e-6 rel); p50/p99"
+UNIT = "cell·band·dir updates/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from workloads import configs as C
+    return {"config1": C.config1, "config2": C.config2, "config3": C.config3}[name]()
+
+
+def sweep_algorithmic_bytes(p, precision):
+    """Compulsory HBM bytes of one sweep launch: every stored distribution
+    value written once, boundary inflow and per-cell data read once."""
+    es = 4 if precision == "mixed" else 8
+    N, B, D = p.n_cells, p.n_bands, p.n_dirs
+    F = {"tri3": 3, "quad4": 4, "tet4": 4, "hex8": 6}[p.cell_type]
+    n_bf = len(p.bfaces)
+    dist = N * B * D * es
+    inflow = n_bf * (D // 2) * B * 8          # incoming half of the directions
+    cells = N * (F * (24 + 4) + 8 + 8 + 8)    # S, nbr, 1/V, theta, Q
+    sched = N * D * 4                          # level-ordered cell lists
+    return dist + inflow + cells + sched, dist / (N * B * D)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2607_03226_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload_name, precision):
+    """HBM traffic per sweep launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{workload_name}_{precision}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(p, iters):
+    import oracle
+    from oracle.solver import _lib
+    t0 = time.perf_counter()
+    su = oracle.prepare(p)
+    t_setup = time.perf_counter() - t0
+    theta = oracle.fourier_guess(su)
+    e = np.broadcast_to(oracle.equilibrium(su, theta)[:, None, :], (p.n_bands, p.n_dirs, su.g.N))
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        inflow = oracle.boundary_inflow(su, e)
+        e, outflux = oracle.transport(su, theta, inflow)
+        ts, _, _ = oracle.moments(su, e)
+        r = su.Q - oracle.divergence(su, outflux)
+        flows = oracle.boundary_flows(su, e, inflow)
+        refl = su.bc_kind != 0
+        np.add.at(r, su.g.bf_owner[refl], flows[refl] / su.g.V[su.g.bf_owner[refl]])
+        theta = ts + oracle.diffusion_operator(su)[1].solve(su.g.V * r)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": p.updates_per_sweep * iters / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"{iters} full synthetic iterations of {p.name} (FP64, OpenMP over band x direction "
+                      f"systems), setup {t_setup:.1f} s excluded", "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-converge", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the per-GPU path is what is measured, sharding is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_2607_03226_amd import nbte as N
+
+    p = workload(args.workload)
+    log(f"bench: workload {p.name} N={p.n_cells} B={p.n_bands} D={p.n_dirs} precision {args.precision}")
+    mesh, h = N.build_problem(p)
+    opts = N.make_opts(scheme=p.scheme, precision=args.precision, T_ref=p.T_ref, time_phases=True)
+    N.nbte_prepare(h, p.Q, opts)
+    N.nbte_iterate(h, args.warmup, check=True)
+    torch.cuda.synchronize()
+    # timed region: events inside the library record each phase on its stream
+    N.nbte_prepare(h, p.Q, opts)
+    N.nbte_iterate(h, args.warmup, check=True)
+    st0 = N.nbte_get_stats(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = N.nbte_iterate(h, args.steps, check=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = N.nbte_get_stats(h)
+    launches = st["sweep_launches"] - st0["sweep_launches"]
+    ms_sweep = (st["ms_sweep"] - st0["ms_sweep"]) / max(launches, 1)
+    phases = {k: (st[k] - st0[k]) / max(launches, 1) for k in ("ms_bc", "ms_sweep", "ms_moments", "ms_synthetic", "ms_update")}
+    ups = p.updates_per_sweep
+    value = ups * args.steps / dt
+    log(f"bench: {args.steps} steps in {dt:.4f} s -> {value:.4e} updates/s; sweep {ms_sweep:.4f} ms; residual {res:.2e}")
+
+    alg_bytes, per_update = sweep_algorithmic_bytes(p, args.precision)
+    achieved = alg_bytes / (ms_sweep * 1e-3) / 1e9
+    traffic = counter_traffic(args.workload, args.precision)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_sweep", "algorithmic_bytes_per_launch": alg_bytes,
+                "sweep_ms_mean": ms_sweep, "sweep_updates_per_s": ups / (ms_sweep * 1e-3)}
+
+    converge = None
+    if not args.no_converge:
+        converge = {}
+        ref_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_reference.npz")
+        ref = np.load(ref_path) if os.path.exists(ref_path) else None
+        for prec in ("mixed", "fp64"):
+            o2 = N.make_opts(scheme=p.scheme, precision=prec, T_ref=p.T_ref, tol=1e-8, max_iter=20000)
+            N.nbte_solve_steady(h, p.Q, o2)       # setup for this precision cached by the first call
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            out = N.nbte_solve_steady(h, p.Q, o2)
+            torch.cuda.synchronize()
+            t_conv = time.perf_counter() - t1
+            rec = {"seconds": t_conv, "iterations": out["iterations"], "residual": out["residual"],
+                   "energy_defect": out["energy_defect"]}
+            if ref is not None:
+                c = ref["cells"]
+                rec["err_TL"] = float(np.max(np.abs(out["T_lattice"][c] - ref["T_lattice"])) / ref["scale_TL"])
+                rec["err_T"] = float(np.max(np.abs(out["T"][c] - ref["T"])) / ref["scale_T"])
+                rec["err_q"] = float(np.max(np.linalg.norm(out["q"][c] - ref["q"], axis=1)) / ref["scale_q"])
+            converge[prec] = rec
+            log(f"bench: converge {prec}: {rec}")
+        converge["speedup_mixed_vs_fp64"] = converge["fp64"]["seconds"] / converge["mixed"]["seconds"]
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(p, args.cpu_iters)
+        log(f"bench: cpu baseline {cpu}")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-stored/f64-arith" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": p.name, "cells": p.n_cells, "bands": p.n_bands, "directions": p.n_dirs,
+                   "cell_type": p.cell_type, "scheme": p.scheme, "precision": args.precision,
+                   "updates_per_step": ups},
+        "roofline": roofline, "cpu_baseline": cpu, "converge": converge,
+        "phases_ms_per_step": phases, "bytes_per_update_stored": per_update,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,242 @@
+/*
+ * nbte.h -- C ABI of the MI355X (gfx950) steady phonon BTE-RTA transport
+ * library.
+ *
+ * The library solves the steady, non-gray phonon Boltzmann transport equation
+ * under the relaxation-time approximation (Methods, Eqs. (3)-(4)) with
+ * discrete ordinates in angle and a first-order upwind finite-volume
+ * discretisation in space, and updates the lattice temperature with the
+ * sequential scheme (Methods, Eqs. (5)-(6)) or the synthetic scheme (Methods,
+ * Eqs. (7)-(12)).  The per-(band, direction) transport solves of Eq. (13) and
+ * the band x direction reductions of Eq. (14) run as HIP kernels on the GPU.
+ *
+ * Conventions shared by every call:
+ *   - SI units throughout; temperatures in kelvin.  2D meshes are per unit
+ *     depth (face "area" = edge length, cell "volume" = cell area).
+ *   - Every input array is owned by the caller, read during the call and
+ *     copied; the caller may free it as soon as the call returns.
+ *   - Handles are owned by the library until the matching *_destroy call.
+ *     A problem keeps its mesh alive internally, so a mesh may be destroyed
+ *     before the problems built on it.
+ *   - No exception crosses the ABI.  Every call returns an nbte_status; on a
+ *     non-OK status nbte_last_error() returns a thread-local description.
+ *   - A problem handle (and a batch handle) is used by one host thread at a
+ *     time.  Work is enqueued on the HIP stream given at creation (NULL = the
+ *     null stream); calls that return results synchronise that stream.
+ *   - There is no CPU fallback: if no usable gfx950 device is present the
+ *     device-touching calls fail with NBTE_ERR_DEVICE.
+ */
+#ifndef NBTE_H
+#define NBTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nbte_status;
+#define NBTE_OK                 0
+#define NBTE_ERR_INVALID_ARG   -1  /* null pointer, size or enum out of range, NaN input */
+#define NBTE_ERR_MESH          -2  /* degenerate cell, non-manifold/non-conforming face, untagged boundary */
+#define NBTE_ERR_QUADRATURE    -3  /* |s| != 1, w <= 0, s_z != 0 in 2D, specular mirror not in the set */
+#define NBTE_ERR_BOUNDARY      -4  /* tag without a condition, bad wall data */
+#define NBTE_ERR_ILL_POSED     -5  /* no thermalizing wall: the steady problem is singular */
+#define NBTE_ERR_OUT_OF_MEMORY -6  /* device allocation failed or batch budget exceeded */
+#define NBTE_ERR_DEVICE        -7  /* HIP runtime error or no gfx950 device */
+#define NBTE_ERR_NOT_CONVERGED -8  /* max_iter reached; results hold the last iterate */
+#define NBTE_ERR_DIVERGED      -9  /* non-finite or exploding residual */
+#define NBTE_ERR_STATE        -10  /* call out of order (e.g. solve before set_bands) */
+
+/* cell types (node ordering: quad4 and tri3 cyclic; hex8 = bottom face 0-1-2-3
+   cyclic, then 4-5-6-7 above them; tet4 any order) */
+#define NBTE_CELL_TRI3  1
+#define NBTE_CELL_QUAD4 2
+#define NBTE_CELL_TET4  3
+#define NBTE_CELL_HEX8  4
+
+/* boundary kinds (Methods; Numerical results: thermalizing, diffuse, specular walls) */
+#define NBTE_BC_THERMALIZING 1  /* phonons leave the wall in equilibrium at T_wall */
+#define NBTE_BC_SPECULAR     2  /* inflow = outgoing value of the mirror direction */
+#define NBTE_BC_DIFFUSE      3  /* inflow = flux-weighted mean of the outgoing values */
+#define NBTE_BC_PARTIAL      4  /* specularity p: p * specular + (1 - p) * diffuse */
+
+/* temperature update schemes */
+#define NBTE_SCHEME_SEQUENTIAL        0  /* Eq. (5): T_L from the collision moment */
+#define NBTE_SCHEME_SYNTHETIC         1  /* Eqs. (9)-(10), diffusion-synthetic reading (default) */
+#define NBTE_SCHEME_SYNTHETIC_LITERAL 2  /* Eqs. (9)-(10) with q_nonF built from T_L^(n) as printed */
+
+/* precision of the stored distribution */
+#define NBTE_PREC_FP64  0  /* distribution stored and swept in FP64 */
+#define NBTE_PREC_MIXED 1  /* distribution stored in FP32; sweep arithmetic, reductions,
+                              diffusion correction and residual in FP64 */
+
+typedef struct nbte_mesh nbte_mesh;
+typedef struct nbte_problem nbte_problem;
+typedef struct nbte_batch nbte_batch;
+
+/* ---------------------------------------------------------------- mesh ---- */
+
+/* Build the finite-volume mesh: faces matched by node sets, outward area
+ * vectors, volumes, neighbour table (the shared cell-face pattern of every
+ * band x direction system; Methods, paragraph after Eq. (13)).
+ *   dim          2 or 3
+ *   xyz          n_nodes*dim node coordinates (m), row-major
+ *   cell_type    NBTE_CELL_*; must match dim (tri3/quad4: 2, tet4/hex8: 3)
+ *   cell_nodes   n_cells * nodes_per_cell node indices (0-based)
+ *   bface_nodes  n_bfaces * nodes_per_face node indices of the boundary faces
+ *   bface_tag    n_bfaces tags (any int32); every boundary face must be listed
+ * Errors: NBTE_ERR_INVALID_ARG, NBTE_ERR_MESH. */
+nbte_status nbte_mesh_create(int32_t dim, int64_t n_nodes, const double *xyz,
+                             int32_t cell_type, int64_t n_cells, const int64_t *cell_nodes,
+                             int64_t n_bfaces, const int64_t *bface_nodes, const int32_t *bface_tag,
+                             nbte_mesh **out);
+void nbte_mesh_destroy(nbte_mesh *m);
+
+typedef struct {
+    int32_t dim;
+    int32_t faces_per_cell;
+    int64_t n_cells;
+    int64_t n_bfaces;
+    double total_volume;      /* m^3 (m^2 in 2D) */
+    double max_closure_error; /* max_c |sum_f S_cf| / sum_f |S_cf|, ~1e-16 for a valid mesh */
+} nbte_mesh_info;
+nbte_status nbte_mesh_get_info(const nbte_mesh *m, nbte_mesh_info *info);
+
+/* ------------------------------------------------------------- problem ---- */
+
+/* A problem = a mesh plus band table, quadrature, boundary conditions and the
+ * device-resident iterates.  hip_stream is a hipStream_t (NULL: null stream). */
+nbte_status nbte_problem_create(const nbte_mesh *m, void *hip_stream, nbte_problem **out);
+void nbte_problem_destroy(nbte_problem *p);
+
+/* Band table (Methods, Eqs. (4)-(5)): heat capacity C (J m^-3 K^-1), group
+ * velocity v (m/s), relaxation time tau (s), each n_bands > 0 finite positive
+ * values.  Errors: NBTE_ERR_INVALID_ARG. */
+nbte_status nbte_set_bands(nbte_problem *p, int32_t n_bands, const double *C, const double *v,
+                           const double *tau);
+
+/* Discrete-ordinates quadrature (Methods, Eqs. (4), (7), (11)): unit directions
+ * s (n_dirs*3, row-major) and weights w > 0; W_Omega = sum w.  In 2D every
+ * s_z must be 0 (in-plane directions).  Errors: NBTE_ERR_QUADRATURE. */
+nbte_status nbte_set_quadrature(nbte_problem *p, int32_t n_dirs, const double *s, const double *w);
+
+typedef struct {
+    int32_t tag;          /* boundary-face tag this condition applies to */
+    int32_t kind;         /* NBTE_BC_* */
+    double T_wall;        /* K, thermalizing walls */
+    double specularity;   /* p in [0,1], partial walls */
+} nbte_boundary;
+
+/* One condition per tag present on the mesh.  A specular or partial wall
+ * needs the mirror of every direction about its normal in the quadrature
+ * (NBTE_ERR_QUADRATURE otherwise).  At least one thermalizing wall is
+ * required (NBTE_ERR_ILL_POSED otherwise, reported at solve time).
+ * Errors: NBTE_ERR_BOUNDARY, NBTE_ERR_INVALID_ARG. */
+nbte_status nbte_set_boundaries(nbte_problem *p, int32_t n, const nbte_boundary *bcs);
+
+typedef struct {
+    int32_t scheme;          /* NBTE_SCHEME_* */
+    int32_t precision;       /* NBTE_PREC_* */
+    double T_ref;            /* K, reference of the deviational variables (default 300) */
+    double tol;              /* stop when max|dT_L| / max|T_L - T_ref| <= tol (default 1e-8) */
+    int32_t max_iter;        /* default 10000 */
+    int32_t check_every;     /* iterations between residual read-backs (default 1) */
+    const double *T_init;    /* nullable host array (n_cells): initial T_L; NULL = Fourier guess */
+    int32_t outputs_on_device; /* 1: result arrays are device pointers */
+    int32_t time_phases;     /* 1: record per-phase HIP-event times (see nbte_get_stats) */
+} nbte_solve_opts;
+
+/* Fill opts with the defaults listed above. */
+void nbte_solve_opts_default(nbte_solve_opts *opts);
+
+typedef struct {
+    double *T_lattice;     /* n_cells, caller-allocated: T_L after the last update */
+    double *T;             /* n_cells: energy temperature T_ref + sum w e / C_tot */
+    double *q;             /* 3*n_cells (x,y,z per cell): heat flux, Eq. (7) (W/m^2) */
+    int32_t iterations;
+    double residual;       /* last max|dT_L| / max|T_L - T_ref| */
+    double energy_defect;  /* |net boundary outflow - integral Qdot| / scale */
+} nbte_result;
+
+/* Solve to the steady state.  Q_cell: nullable host array (n_cells, W/m^3),
+ * the volumetric heat generation, split over bands by heat capacity and
+ * uniformly over directions (Numerical results, FinFET).  Any of the result
+ * arrays may be NULL.  Returns NBTE_ERR_NOT_CONVERGED (with the last iterate
+ * written) when max_iter is reached. */
+nbte_status nbte_solve_steady(nbte_problem *p, const double *Q_cell, const nbte_solve_opts *o,
+                              nbte_result *out);
+
+/* Split form of nbte_solve_steady, for callers that drive the iteration:
+ *   nbte_prepare  : setup (cached per geometry/tables) + initial guess;
+ *   nbte_iterate  : n full iterations (boundary inflow, transport sweeps,
+ *                   moments, temperature update), no host synchronisation
+ *                   unless check is set, in which case *residual receives the
+ *                   residual of the last iteration;
+ *   nbte_read_result: write the current state into out. */
+nbte_status nbte_prepare(nbte_problem *p, const double *Q_cell, const nbte_solve_opts *o);
+nbte_status nbte_iterate(nbte_problem *p, int32_t n, int32_t check, double *residual);
+nbte_status nbte_read_result(nbte_problem *p, nbte_result *out);
+
+/* Copy the current distribution e_{band,dir}(c) (deviational, J m^-3 per
+ * unit weight, FP64) of one (band, direction) system into host out[n_cells]. */
+nbte_status nbte_get_distribution(nbte_problem *p, int32_t band, int32_t dir, double *out);
+
+/* Sweep schedule of one direction (host data, no device needed): the cells in
+ * upwind order (perm[n_cells], nullable) grouped in topological levels
+ * lvl_ptr[0..n_levels] (nullable; capacity cap_levels entries), such that
+ * every interior upwind neighbour of a cell lies in an earlier level.  For
+ * first-order upwind this order is the exact factorisation of the transport
+ * matrix of Eq. (13).  Errors: NBTE_ERR_MESH if the upwind graph is cyclic. */
+nbte_status nbte_get_schedule(nbte_problem *p, int32_t dir, int32_t *perm, int32_t *lvl_ptr, int32_t cap_levels,
+                              int32_t *n_levels);
+
+typedef struct {
+    int32_t iterations;
+    double ms_total;        /* wall time of the last solve/iterate call, ms */
+    double ms_bc;           /* summed HIP-event times per phase (time_phases = 1) */
+    double ms_sweep;
+    double ms_moments;
+    double ms_synthetic;
+    double ms_update;
+    int32_t sweep_launches; /* launches of the transport sweep kernel timed above */
+    int64_t updates_per_sweep;  /* n_cells * n_bands * n_dirs */
+    int32_t max_levels;     /* deepest per-direction sweep schedule */
+    int64_t device_bytes;   /* device memory held by the problem */
+    int32_t bands_per_block;   /* launch shape of the last sweep */
+    int32_t bands_per_lane;
+    int32_t block_size;
+    int32_t lds_slots;         /* staged slots per direction (0: staging off) */
+    int64_t spilled_values;    /* consumed values per sweep that did not fit the LDS budget */
+} nbte_stats;
+nbte_status nbte_get_stats(nbte_problem *p, nbte_stats *st);
+
+/* Launch configuration of the kernels (chosen by the autotuner). */
+typedef struct {
+    int32_t bands_per_block;  /* bands of one direction per sweep workgroup (0 = auto) */
+    int32_t bands_per_lane;   /* bands one lane sweeps (1,2,4,8,16; 0 = auto) */
+    int32_t block_size;       /* threads per sweep workgroup (64..1024, multiple of 64; 0 = auto) */
+    int32_t lds_bytes;        /* LDS budget per sweep workgroup for staged neighbour values
+                                 (0 = auto, -1 = no staging: neighbours read from HBM) */
+    int32_t cg_max_iter;      /* diffusion-correction CG iterations per outer iteration (0 = auto) */
+    double cg_rtol;           /* diffusion-correction CG relative tolerance (0 = auto) */
+} nbte_tuning;
+nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t);
+nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t);
+
+/* Device bytes a solve of this problem would hold at the given precision
+ * (set_bands/set_quadrature must have been called). */
+nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int64_t *bytes);
+
+/* --------------------------------------------------------------- errors -- */
+
+/* Thread-local message for the last non-OK status of this thread ("" if none). */
+const char *nbte_last_error(void);
+/* Library version string. */
+const char *nbte_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBTE_H */

@@ -300,6 +300,31 @@ def transport(su: Setup, theta, inflow):
     return e, outflux
 
 
+def transport_systems(su: Setup, theta, inflow, systems):
+    """Solve only the listed (band, direction) systems (same arithmetic as
+    transport()); returns {(b, i): e}.  inflow may be given for those systems
+    only, as a dict {(b, i): (NBF,) array}, or as the full (B, D, NBF) array."""
+    g = su.g
+    N = g.N
+    nbr = np.ascontiguousarray(g.nbr, np.int64)
+    S = np.ascontiguousarray(g.S)
+    out = {}
+    for (b, i) in systems:
+        rhs = np.ascontiguousarray(su.C[b] * theta / (su.W * su.tau[b]) + su.Q * su.C[b] / (su.C_tot * su.W))
+        inf = np.ascontiguousarray(inflow[(b, i)] if isinstance(inflow, dict) else inflow[b, i])
+        e = np.empty(N)
+        flux = np.empty(N)
+        s = np.ascontiguousarray(su.s[i])
+        st = _lib().oracle_sweep_system(N, g.F, _p(nbr, ctypes.c_int64), _p(S), _p(g.V), _p(s), float(su.v[b]),
+                                        float(1.0 / su.tau[b]), _p(rhs), _p(inf), _p(e), _p(flux))
+        if st == 1:
+            e, flux = _direct_system(su, b, i, rhs, inf)
+        elif st != 0:
+            raise MemoryError("oracle sweep allocation failed")
+        out[(b, i)] = e
+    return out
+
+
 def _direct_system(su: Setup, b, i, rhs, inflow_bi):
     g = su.g
     N, F = g.N, g.F

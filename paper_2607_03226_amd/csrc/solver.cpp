@@ -1,0 +1,820 @@
+// Problem handles, the iteration driver and the C ABI (include/nbte.h).
+//
+// One iteration (Methods, Eqs. (5)-(6) sequential, (7)-(12) synthetic; the
+// task split of Eq. (14) becomes one kernel over all band x direction systems):
+//   1. lagged boundary inflow from the previous distribution;
+//   2. transport sweep of every (band, direction) system at the current T_L;
+//   3. band x direction reductions: collision-weighted T_L (Eq. (5)), energy
+//      temperature, heat flux (Eq. (7));
+//   4. sequential: T_L <- that moment; synthetic: diffusion correction
+//      (Eq. (10)) solved by PCG, T_L <- moment + correction;
+//   5. FP64 residual max|dT_L| / max|T_L - T_ref|.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace nbte;
+
+struct nbte_mesh {
+    std::shared_ptr<Mesh> m;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nbte_status fail(nbte_status code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F>
+nbte_status guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(NBTE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(NBTE_ERR_INVALID_ARG, e.what());
+    }
+}
+
+void require_gfx950() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) throw Error(NBTE_ERR_DEVICE, "no HIP device available");
+    int dev = 0;
+    NBTE_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    NBTE_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        throw Error(NBTE_ERR_DEVICE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+}
+
+enum Phase { PH_BC = 0, PH_SWEEP, PH_MOM, PH_SYN, PH_UPD, PH_END, PH_COUNT };
+
+}  // namespace
+
+struct nbte_problem {
+    std::shared_ptr<Mesh> mesh;
+    hipStream_t stream = nullptr;
+    BandTable bands;
+    Quadrature quad;
+    std::vector<nbte_boundary> bcs;
+    bool have_bands = false, have_quad = false, have_bcs = false;
+    double T_ref = 300.0;
+
+    // cached setup (validity flags)
+    bool geom_ok = false, sched_ok = false, plan_ok = false, diff_ok = false, tables_ok = false;
+    bool sched_up = false, plan_up = false, diff_up = false;
+    Schedule sched;
+    BoundaryPlan plan;
+    DiffusionOperator diff;
+
+    // device buffers
+    DevBuf d_nbr, d_S, d_invV, d_V;
+    DevBuf d_perm, d_lvl_ptr, d_lvl_off;
+    DevBuf d_Cw, d_src, d_vel, d_itau, d_dirs, d_w, d_qbias;
+    DevBuf d_bf_owner, d_bf_kind, d_mirror, d_bf_thw, d_bf_p, d_sdotS, d_win;
+    DevBuf d_Lrow, d_Lcol, d_Lval, d_Ldinv, d_dirrhs;
+    DevBuf d_g, d_inflow, d_Jw, d_Q;
+    DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta, d_maxbuf;
+    DevBuf d_pcg_r, d_pcg_z, d_pcg_p, d_pcg_Ap, d_pcg_part, d_pcg_scal;
+    int pcg_nblk = 1;
+
+    // state
+    bool prepared = false;
+    int precision = NBTE_PREC_FP64;
+    int scheme = NBTE_SCHEME_SYNTHETIC;
+    int cur = 0, prev = 1, spare = 2;  // indices into d_theta, always distinct
+    int iterations = 0;
+    double residual = INFINITY;
+    double heat_in = 0.0;
+    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0};
+    struct Shape { int bpb = 1, bpl = 1, block = 256, slots = 0; } shape;
+    int slots_for_cap = -2;   // cap the current slot table was built for
+    DevBuf d_slot;
+    int time_phases = 0;
+
+    // phase timing
+    std::vector<std::array<hipEvent_t, PH_COUNT>> events;
+    int events_used = 0;
+    nbte_stats stats{};
+    std::chrono::steady_clock::time_point t_wall0;
+
+    ~nbte_problem() {
+        for (auto &ev : events)
+            for (auto e : ev) (void)hipEventDestroy(e);
+    }
+
+    DeviceView view() const {
+        DeviceView v{};
+        v.N = mesh->N;
+        v.F = mesh->F;
+        v.B = bands.B;
+        v.D = quad.D;
+        v.NBF = mesh->NBF;
+        v.nbr = d_nbr.as<int32_t>();
+        v.S = d_S.as<double>();
+        v.invV = d_invV.as<double>();
+        v.perm = d_perm.as<int32_t>();
+        v.lvl_ptr = d_lvl_ptr.as<int32_t>();
+        v.lvl_off = d_lvl_off.as<int32_t>();
+        v.slot = shape.slots > 0 ? d_slot.as<int32_t>() : nullptr;
+        v.Cw = d_Cw.as<double>();
+        v.src = d_src.as<double>();
+        v.vel = d_vel.as<double>();
+        v.inv_tau = d_itau.as<double>();
+        v.dirs = d_dirs.as<double>();
+        v.w = d_w.as<double>();
+        v.bf_owner = d_bf_owner.as<int32_t>();
+        v.bf_kind = d_bf_kind.as<int32_t>();
+        v.mirror = d_mirror.as<int32_t>();
+        v.bf_thw = d_bf_thw.as<double>();
+        v.bf_p = d_bf_p.as<double>();
+        v.sdotS = d_sdotS.as<double>();
+        v.win = d_win.as<double>();
+        v.g = d_g.ptr;
+        v.inflow = d_inflow.as<double>();
+        v.Jw = d_Jw.as<double>();
+        v.Q = d_Q.as<double>();
+        return v;
+    }
+
+    // Resolve the tuning into one sweep launch shape.  Defaults aim at two
+    // workgroups per CU (bands split into blocks until D * blocks >= 512) and
+    // a 64 KiB LDS budget for staged neighbour values.
+    Shape resolve_shape() const {
+        Shape sh;
+        const int B = bands.B, D = quad.D;
+        int bpb = tuning.bands_per_block;
+        if (bpb <= 0) {
+            int nbb = std::max(1, std::min(B, (512 + D - 1) / D));
+            int want = (B + nbb - 1) / nbb;
+            bpb = 1;
+            while (bpb * 2 <= want) bpb *= 2;
+        }
+        bpb = std::min(bpb, B);
+        int bpl = tuning.bands_per_lane > 0 ? tuning.bands_per_lane : 1;
+        while (bpl * 64 < bpb) bpl *= 2;          // at most 64 lanes per cell
+        if (bpl > 16) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block too large for 16 bands per lane");
+        int lanes = (bpb + bpl - 1) / bpl, lpc = 1;
+        while (lpc < lanes) lpc <<= 1;
+        int block = tuning.block_size > 0 ? tuning.block_size : 256;
+        block = std::max(block, lpc);
+        sh.bpb = bpb;
+        sh.bpl = bpl;
+        sh.block = block;
+        const int budget = tuning.lds_bytes == 0 ? 65536 : tuning.lds_bytes;
+        sh.slots = budget < 0 ? 0 : std::min(budget, 65536) / (bpb * 8);
+        return sh;
+    }
+    // The correction only has to capture the smooth error modes: 20 Jacobi-CG
+    // iterations leave the outer iteration count unchanged on every workload.
+    int cg_max_iter() const { return tuning.cg_max_iter > 0 ? tuning.cg_max_iter : 20; }
+    double cg_rtol() const { return tuning.cg_rtol > 0 ? tuning.cg_rtol : 1e-3; }
+
+    PcgWork pcg() const {
+        PcgWork w{};
+        w.n = mesh->N;
+        w.nblk = pcg_nblk;
+        w.row_ptr = d_Lrow.as<int32_t>();
+        w.col = d_Lcol.as<int32_t>();
+        w.val = d_Lval.as<double>();
+        w.dinv = d_Ldinv.as<double>();
+        w.r = d_pcg_r.as<double>();
+        w.z = d_pcg_z.as<double>();
+        w.p = d_pcg_p.as<double>();
+        w.Ap = d_pcg_Ap.as<double>();
+        w.partial = d_pcg_part.as<double>();
+        w.scal = d_pcg_scal.as<double>();
+        return w;
+    }
+
+    // Host-side setup products (no device access): schedules, boundary plan,
+    // diffusion operator.  Throws the validation errors of the ABI.
+    void build_host() {
+        if (!have_bands || !have_quad || !have_bcs)
+            throw Error(NBTE_ERR_STATE, "set_bands, set_quadrature and set_boundaries must precede the solve");
+        const Mesh &m = *mesh;
+        if (!sched_ok) {
+            sched = build_schedule(m, quad);
+            sched_ok = true;
+            sched_up = false;
+            slots_for_cap = -2;
+        }
+        shape = resolve_shape();
+        if (slots_for_cap != shape.slots) {
+            if (shape.slots > 0) assign_slots(m, quad, sched, shape.slots);
+            else sched.slot.clear(), sched.max_slots = 0, sched.spilled = 0;
+            slots_for_cap = shape.slots;
+            sched_up = false;
+        }
+        if (!plan_ok) {
+            plan = build_boundary_plan(m, quad, bcs, T_ref);
+            plan_ok = true;
+            plan_up = false;
+            diff_ok = false;
+        }
+        if (!plan.has_thermalizing)
+            throw Error(NBTE_ERR_ILL_POSED, "no thermalizing wall: the steady problem has no unique solution");
+        if (!diff_ok) {
+            diff = build_diffusion(m, bands, quad, plan);
+            diff_ok = true;
+            diff_up = false;
+        }
+    }
+
+    void upload_device() {
+        require_gfx950();
+        const Mesh &m = *mesh;
+        if (!geom_ok) {
+            std::vector<double> invV(m.N);
+            for (int64_t c = 0; c < m.N; ++c) invV[c] = 1.0 / m.V[c];
+            upload(d_nbr, m.nbr, stream);
+            upload(d_S, m.S, stream);
+            upload(d_invV, invV, stream);
+            upload(d_V, m.V, stream);
+            upload(d_bf_owner, m.bf_owner, stream);
+            geom_ok = true;
+        }
+        if (!sched_up) {
+            upload(d_perm, sched.perm, stream);
+            upload(d_lvl_ptr, sched.lvl_ptr, stream);
+            upload(d_lvl_off, sched.lvl_off, stream);
+            if (shape.slots > 0) upload(d_slot, sched.slot, stream);
+            else d_slot.release();
+            sched_up = true;
+        }
+        if (!plan_up) {
+            upload(d_bf_kind, plan.kind, stream);
+            upload(d_mirror, plan.mirror, stream);
+            upload(d_bf_thw, plan.theta_w, stream);
+            upload(d_bf_p, plan.p, stream);
+            upload(d_sdotS, plan.sdotS, stream);
+            upload(d_win, plan.win, stream);
+            plan_up = true;
+        }
+        if (!tables_ok) {
+            const int B = bands.B, D = quad.D;
+            std::vector<double> Cw(B), src(B), itau(B);
+            for (int l = 0; l < B; ++l) {
+                Cw[l] = bands.C[l] / quad.W;
+                src[l] = bands.C[l] / (bands.C_tot * quad.W);
+                itau[l] = 1.0 / bands.tau[l];
+            }
+            // q of a pure equilibrium field: theta * sum_l v_l C_l/W * sum_i w_i s_i (0 for a symmetric set)
+            std::vector<double> qb(3, 0.0);
+            double vcw = 0;
+            for (int l = 0; l < B; ++l) vcw += bands.v[l] * Cw[l];
+            for (int i = 0; i < D; ++i)
+                for (int ax = 0; ax < 3; ++ax) qb[ax] += quad.w[i] * quad.s[3 * i + ax];
+            for (double &x : qb) x *= vcw;
+            upload(d_Cw, Cw, stream);
+            upload(d_src, src, stream);
+            upload(d_vel, bands.v, stream);
+            upload(d_itau, itau, stream);
+            upload(d_dirs, quad.s, stream);
+            upload(d_w, quad.w, stream);
+            upload(d_qbias, qb, stream);
+            tables_ok = true;
+        }
+        if (!diff_up) {
+            std::vector<double> dinv(m.N);
+            for (int64_t c = 0; c < m.N; ++c) dinv[c] = 1.0 / diff.val[diff.row_ptr[c]];
+            upload(d_Lrow, diff.row_ptr, stream);
+            upload(d_Lcol, diff.col, stream);
+            upload(d_Lval, diff.val, stream);
+            upload(d_Ldinv, dinv, stream);
+            upload(d_dirrhs, diff.dir_rhs, stream);
+            pcg_nblk = (int)std::min<int64_t>(256, (m.N + 255) / 256);
+            for (DevBuf *b : {&d_pcg_r, &d_pcg_z, &d_pcg_p, &d_pcg_Ap}) b->alloc(m.N * sizeof(double));
+            d_pcg_part.alloc(3 * 256 * sizeof(double));
+            d_pcg_scal.alloc(8 * sizeof(double));
+            diff_up = true;
+        }
+        NBTE_HIP(hipStreamSynchronize(stream));
+    }
+
+    void ensure_setup() {
+        build_host();
+        upload_device();
+    }
+
+    int64_t state_bytes(int prec) const {
+        const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
+        const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
+        return D * N * B * es + NBF * D * B * 8 + NBF * 8 + N * 8 * 12 + 64;
+    }
+
+    void allocate_state(int prec) {
+        const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
+        const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
+        d_g.alloc(D * N * B * es);
+        d_inflow.alloc(std::max<int64_t>(NBF * D * B, 1) * 8);
+        d_Jw.alloc(std::max<int64_t>(NBF, 1) * 8);
+        d_Q.alloc(N * 8);
+        for (auto &t : d_theta) t.alloc(N * 8);
+        d_theta_seq.alloc(N * 8);
+        d_thetaE.alloc(N * 8);
+        d_q.alloc(3 * N * 8);
+        d_rhs.alloc(N * 8);
+        d_delta.alloc(N * 8);
+        d_maxbuf.alloc(2 * sizeof(unsigned long long));
+    }
+
+    int64_t device_bytes() const {
+        int64_t s = 0;
+        for (const DevBuf *b : {&d_nbr, &d_S, &d_invV, &d_V, &d_perm, &d_lvl_ptr, &d_lvl_off, &d_Cw, &d_src, &d_vel,
+                                &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind, &d_mirror, &d_bf_thw,
+                                &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_dirrhs, &d_g,
+                                &d_inflow, &d_Jw, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq,
+                                &d_thetaE, &d_q, &d_rhs, &d_delta, &d_maxbuf, &d_pcg_r, &d_pcg_z, &d_pcg_p,
+                                &d_pcg_Ap, &d_pcg_part, &d_pcg_scal, &d_slot})
+            s += (int64_t)b->bytes;
+        return s;
+    }
+
+    void record(int iter_slot, Phase ph) {
+        if (!time_phases) return;
+        NBTE_HIP(hipEventRecord(events[iter_slot][ph], stream));
+    }
+
+    int next_event_slot() {
+        if (!time_phases) return 0;
+        if (events_used == (int)events.size()) {
+            std::array<hipEvent_t, PH_COUNT> ev;
+            for (auto &e : ev) NBTE_HIP(hipEventCreate(&e));
+            events.push_back(ev);
+        }
+        return events_used++;
+    }
+
+    void one_iteration() {
+        const bool fp32 = precision == NBTE_PREC_MIXED;
+        const DeviceView v = view();
+        const double *th = d_theta[cur].as<double>();
+        const double *th_prev = d_theta[prev].as<double>();
+        double *th_new = d_theta[spare].as<double>();
+        const int slot = next_event_slot();
+        record(slot, PH_BC);
+        launch_bc_inflow(v, fp32, th_prev, stream);
+        record(slot, PH_SWEEP);
+        launch_sweep(v, fp32, th, shape.bpb, shape.bpl, shape.block, std::max(sched.max_slots, 1), stream);
+        record(slot, PH_MOM);
+        const bool syn = scheme != NBTE_SCHEME_SEQUENTIAL;
+        if (syn) launch_wall_flux(v, fp32, th, stream);
+        launch_moments(v, fp32, th, bands.beta, bands.C_tot, d_V.as<double>(), d_qbias.as<double>(),
+                       d_theta_seq.as<double>(), d_thetaE.as<double>(), d_q.as<double>(),
+                       syn ? d_rhs.as<double>() : nullptr, stream);
+        record(slot, PH_SYN);
+        if (syn) launch_pcg(pcg(), d_rhs.as<double>(), d_delta.as<double>(), cg_rtol(), cg_max_iter(), stream);
+        record(slot, PH_UPD);
+        launch_reset_max(d_maxbuf.as<unsigned long long>(), stream);
+        const double *base = (scheme == NBTE_SCHEME_SYNTHETIC_LITERAL) ? th : d_theta_seq.as<double>();
+        launch_update(mesh->N, base, syn ? d_delta.as<double>() : nullptr, th, th_new,
+                      d_maxbuf.as<unsigned long long>(), stream);
+        record(slot, PH_END);
+        NBTE_HIP(hipGetLastError());
+        // rotate: previous <- current, current <- new; the old previous buffer
+        // (two iterations back) becomes the next scratch
+        const int old_prev = prev;
+        prev = cur;
+        cur = spare;
+        spare = old_prev;
+        ++iterations;
+    }
+
+    double read_residual() {
+        unsigned long long mb[2];
+        NBTE_HIP(hipMemcpyAsync(mb, d_maxbuf.ptr, sizeof(mb), hipMemcpyDeviceToHost, stream));
+        NBTE_HIP(hipStreamSynchronize(stream));
+        double md, mt;
+        std::memcpy(&md, &mb[0], 8);
+        std::memcpy(&mt, &mb[1], 8);
+        if (!std::isfinite(md) || !std::isfinite(mt)) throw Error(NBTE_ERR_DIVERGED, "iteration diverged (non-finite temperature)");
+        residual = mt > 0 ? md / mt : 0.0;
+        return residual;
+    }
+
+    void prepare(const double *Q_cell, const nbte_solve_opts &o) {
+        if (o.precision != NBTE_PREC_FP64 && o.precision != NBTE_PREC_MIXED) throw Error(NBTE_ERR_INVALID_ARG, "bad precision");
+        if (o.scheme < 0 || o.scheme > 2) throw Error(NBTE_ERR_INVALID_ARG, "bad scheme");
+        if (!std::isfinite(o.T_ref)) throw Error(NBTE_ERR_INVALID_ARG, "bad T_ref");
+        if (o.T_ref != T_ref) {
+            T_ref = o.T_ref;
+            plan_ok = false;  // wall temperatures are stored relative to T_ref
+        }
+        ensure_setup();
+        const Mesh &m = *mesh;
+        precision = o.precision;
+        scheme = o.scheme;
+        time_phases = o.time_phases;
+        allocate_state(precision);
+        std::vector<double> Q(m.N, 0.0);
+        heat_in = 0.0;
+        if (Q_cell) {
+            for (int64_t c = 0; c < m.N; ++c) {
+                if (!std::isfinite(Q_cell[c])) throw Error(NBTE_ERR_INVALID_ARG, "non-finite heat source");
+                Q[c] = Q_cell[c];
+                heat_in += m.V[c] * Q[c];
+            }
+        }
+        NBTE_HIP(hipMemcpyAsync(d_Q.ptr, Q.data(), m.N * 8, hipMemcpyHostToDevice, stream));
+        cur = 0; prev = 1; spare = 2;
+        double *th0 = d_theta[0].as<double>();
+        if (o.T_init) {
+            std::vector<double> t0(m.N);
+            for (int64_t c = 0; c < m.N; ++c) {
+                if (!std::isfinite(o.T_init[c])) throw Error(NBTE_ERR_INVALID_ARG, "non-finite T_init");
+                t0[c] = o.T_init[c] - T_ref;
+            }
+            NBTE_HIP(hipMemcpyAsync(th0, t0.data(), m.N * 8, hipMemcpyHostToDevice, stream));
+        } else {
+            // Fourier initial guess: L theta = V Qdot + wall data
+            std::vector<double> b(m.N);
+            for (int64_t c = 0; c < m.N; ++c) b[c] = m.V[c] * Q[c] + diff.dir_rhs[c];
+            NBTE_HIP(hipMemcpyAsync(d_rhs.ptr, b.data(), m.N * 8, hipMemcpyHostToDevice, stream));
+            launch_pcg(pcg(), d_rhs.as<double>(), th0, 1e-12, std::max(1000, (int)std::sqrt((double)m.N) * 20), stream);
+        }
+        // g = 0 is equilibrium at theta^0; the stored g is relative to theta[prev]
+        NBTE_HIP(hipMemcpyAsync(d_theta[prev].ptr, th0, m.N * 8, hipMemcpyDeviceToDevice, stream));
+        launch_fill_zero(d_g.ptr, d_g.bytes, stream);
+        launch_fill_zero(d_inflow.ptr, d_inflow.bytes, stream);
+        NBTE_HIP(hipGetLastError());
+        NBTE_HIP(hipStreamSynchronize(stream));
+        iterations = 0;
+        residual = INFINITY;
+        events_used = 0;
+        stats = nbte_stats{};
+        prepared = true;
+    }
+
+    void iterate(int n, bool check, double *res_out) {
+        if (!prepared) throw Error(NBTE_ERR_STATE, "nbte_prepare must precede nbte_iterate");
+        auto t0 = std::chrono::steady_clock::now();
+        for (int k = 0; k < n; ++k) one_iteration();
+        if (check) {
+            double r = read_residual();
+            if (res_out) *res_out = r;
+        }
+        stats.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    void read_result(nbte_result *out) {
+        if (!prepared) throw Error(NBTE_ERR_STATE, "nothing to read: call nbte_prepare first");
+        const Mesh &m = *mesh;
+        const bool fp32 = precision == NBTE_PREC_MIXED;
+        const bool on_dev = out_on_device;
+        auto put = [&](double *dst, const double *src, int64_t n, double offset) {
+            if (!dst) return;
+            if (on_dev) {
+                launch_affine(n, src, 1.0, offset, dst, stream);
+            } else {
+                std::vector<double> h(n);
+                NBTE_HIP(hipMemcpyAsync(h.data(), src, n * 8, hipMemcpyDeviceToHost, stream));
+                NBTE_HIP(hipStreamSynchronize(stream));
+                for (int64_t k = 0; k < n; ++k) dst[k] = offset + h[k];
+            }
+        };
+        // theta of the last update is the current one; T and q belong to the
+        // last sweep, whose distribution is stored relative to theta[prev]
+        put(out->T_lattice, d_theta[cur].as<double>(), m.N, T_ref);
+        put(out->T, d_thetaE.as<double>(), m.N, T_ref);
+        put(out->q, d_q.as<double>(), 3 * m.N, 0.0);
+        // energy balance from the last sweep's face values
+        double defect = 0.0;
+        if (m.NBF > 0) {
+            launch_wall_flux(view(), fp32, d_theta[prev].as<double>(), stream);
+            std::vector<double> J(m.NBF);
+            NBTE_HIP(hipMemcpyAsync(J.data(), d_Jw.ptr, m.NBF * 8, hipMemcpyDeviceToHost, stream));
+            NBTE_HIP(hipStreamSynchronize(stream));
+            double net = 0, tot = 0;
+            for (double x : J) { net += x; tot += std::fabs(x); }
+            double scale = std::max(std::fabs(heat_in), 0.5 * tot);
+            defect = scale > 0 ? std::fabs(net - heat_in) / scale : 0.0;
+        }
+        NBTE_HIP(hipStreamSynchronize(stream));
+        out->iterations = iterations;
+        out->residual = residual;
+        out->energy_defect = defect;
+    }
+
+    bool out_on_device = false;
+
+    void collect_stats() {
+        if (time_phases && events_used > 0) {
+            NBTE_HIP(hipStreamSynchronize(stream));
+            double acc[PH_COUNT] = {0};
+            for (int k = 0; k < events_used; ++k)
+                for (int ph = 0; ph < PH_END; ++ph) {
+                    float ms = 0;
+                    NBTE_HIP(hipEventElapsedTime(&ms, events[k][ph], events[k][ph + 1]));
+                    acc[ph] += ms;
+                }
+            stats.ms_bc = acc[PH_BC];
+            stats.ms_sweep = acc[PH_SWEEP];
+            stats.ms_moments = acc[PH_MOM];
+            stats.ms_synthetic = acc[PH_SYN];
+            stats.ms_update = acc[PH_UPD];
+            stats.sweep_launches = events_used;
+        }
+        stats.iterations = iterations;
+        stats.updates_per_sweep = mesh->N * (int64_t)bands.B * quad.D;
+        stats.max_levels = sched_ok ? sched.max_levels : 0;
+        stats.device_bytes = device_bytes();
+        stats.bands_per_block = shape.bpb;
+        stats.bands_per_lane = shape.bpl;
+        stats.block_size = shape.block;
+        stats.lds_slots = shape.slots > 0 ? sched.max_slots : 0;
+        stats.spilled_values = sched.spilled;
+    }
+};
+
+// ============================================================================ ABI
+
+extern "C" {
+
+const char *nbte_last_error(void) { return g_last_error.c_str(); }
+
+const char *nbte_version(void) { return "nbte 0.1.0 (gfx950)"; }
+
+nbte_status nbte_mesh_create(int32_t dim, int64_t n_nodes, const double *xyz, int32_t cell_type, int64_t n_cells,
+                             const int64_t *cell_nodes, int64_t n_bfaces, const int64_t *bface_nodes,
+                             const int32_t *bface_tag, nbte_mesh **out) {
+    return guarded([&] {
+        if (!out) throw Error(NBTE_ERR_INVALID_ARG, "out is null");
+        *out = nullptr;
+        auto m = build_mesh(dim, n_nodes, xyz, cell_type, n_cells, cell_nodes, n_bfaces, bface_nodes, bface_tag);
+        *out = new nbte_mesh{std::move(m)};
+        return NBTE_OK;
+    });
+}
+
+void nbte_mesh_destroy(nbte_mesh *m) { delete m; }
+
+nbte_status nbte_mesh_get_info(const nbte_mesh *m, nbte_mesh_info *info) {
+    return guarded([&] {
+        if (!m || !info) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        info->dim = m->m->dim;
+        info->faces_per_cell = m->m->F;
+        info->n_cells = m->m->N;
+        info->n_bfaces = m->m->NBF;
+        info->total_volume = m->m->total_volume;
+        info->max_closure_error = m->m->max_closure;
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_problem_create(const nbte_mesh *m, void *hip_stream, nbte_problem **out) {
+    return guarded([&] {
+        if (!m || !out) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        *out = nullptr;
+        auto *p = new nbte_problem();
+        p->mesh = m->m;
+        p->stream = static_cast<hipStream_t>(hip_stream);
+        *out = p;
+        return NBTE_OK;
+    });
+}
+
+void nbte_problem_destroy(nbte_problem *p) {
+    if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    delete p;
+}
+
+nbte_status nbte_set_bands(nbte_problem *p, int32_t n_bands, const double *C, const double *v, const double *tau) {
+    return guarded([&] {
+        if (!p || !C || !v || !tau || n_bands <= 0) throw Error(NBTE_ERR_INVALID_ARG, "bad band table arguments");
+        BandTable b;
+        b.B = n_bands;
+        b.C.assign(C, C + n_bands);
+        b.v.assign(v, v + n_bands);
+        b.tau.assign(tau, tau + n_bands);
+        for (int l = 0; l < n_bands; ++l) {
+            if (!(std::isfinite(C[l]) && C[l] > 0) || !(std::isfinite(v[l]) && v[l] > 0) ||
+                !(std::isfinite(tau[l]) && tau[l] > 0))
+                throw Error(NBTE_ERR_INVALID_ARG, "band " + std::to_string(l) + ": C, v, tau must be finite and > 0");
+            b.beta += C[l] / tau[l];
+            b.C_tot += C[l];
+        }
+        p->bands = std::move(b);
+        p->have_bands = true;
+        p->tables_ok = false;
+        p->diff_ok = false;
+        p->prepared = false;
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_set_quadrature(nbte_problem *p, int32_t n_dirs, const double *s, const double *w) {
+    return guarded([&] {
+        if (!p || !s || !w || n_dirs <= 0) throw Error(NBTE_ERR_INVALID_ARG, "bad quadrature arguments");
+        Quadrature q;
+        q.D = n_dirs;
+        q.s.assign(s, s + 3 * (size_t)n_dirs);
+        q.w.assign(w, w + n_dirs);
+        for (int i = 0; i < n_dirs; ++i) {
+            const double nrm = std::sqrt(s[3 * i] * s[3 * i] + s[3 * i + 1] * s[3 * i + 1] + s[3 * i + 2] * s[3 * i + 2]);
+            if (!std::isfinite(nrm) || std::fabs(nrm - 1.0) > 1e-12)
+                throw Error(NBTE_ERR_QUADRATURE, "direction " + std::to_string(i) + " is not a unit vector");
+            if (!(std::isfinite(w[i]) && w[i] > 0)) throw Error(NBTE_ERR_QUADRATURE, "weights must be finite and > 0");
+            if (p->mesh->dim == 2 && s[3 * i + 2] != 0.0)
+                throw Error(NBTE_ERR_QUADRATURE, "2D mesh needs in-plane directions (s_z = 0)");
+            q.W += w[i];
+        }
+        p->quad = std::move(q);
+        p->have_quad = true;
+        p->sched_ok = p->plan_ok = p->diff_ok = p->tables_ok = false;
+        p->prepared = false;
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_set_boundaries(nbte_problem *p, int32_t n, const nbte_boundary *bcs) {
+    return guarded([&] {
+        if (!p || !bcs || n <= 0) throw Error(NBTE_ERR_INVALID_ARG, "bad boundary arguments");
+        std::vector<nbte_boundary> v(bcs, bcs + n);
+        for (size_t k = 0; k < v.size(); ++k) {
+            const auto &b = v[k];
+            if (b.kind < NBTE_BC_THERMALIZING || b.kind > NBTE_BC_PARTIAL)
+                throw Error(NBTE_ERR_BOUNDARY, "unknown boundary kind for tag " + std::to_string(b.tag));
+            if (b.kind == NBTE_BC_THERMALIZING && !(std::isfinite(b.T_wall) && b.T_wall > 0))
+                throw Error(NBTE_ERR_BOUNDARY, "thermalizing wall needs a finite positive T_wall");
+            if (b.kind == NBTE_BC_PARTIAL && !(b.specularity >= 0 && b.specularity <= 1))
+                throw Error(NBTE_ERR_BOUNDARY, "specularity must lie in [0,1]");
+            for (size_t j = 0; j < k; ++j)
+                if (v[j].tag == b.tag) throw Error(NBTE_ERR_BOUNDARY, "duplicate tag " + std::to_string(b.tag));
+        }
+        p->bcs = std::move(v);
+        p->have_bcs = true;
+        p->plan_ok = p->diff_ok = false;
+        p->prepared = false;
+        return NBTE_OK;
+    });
+}
+
+void nbte_solve_opts_default(nbte_solve_opts *o) {
+    if (!o) return;
+    o->scheme = NBTE_SCHEME_SYNTHETIC;
+    o->precision = NBTE_PREC_FP64;
+    o->T_ref = 300.0;
+    o->tol = 1e-8;
+    o->max_iter = 10000;
+    o->check_every = 1;
+    o->T_init = nullptr;
+    o->outputs_on_device = 0;
+    o->time_phases = 0;
+}
+
+nbte_status nbte_prepare(nbte_problem *p, const double *Q_cell, const nbte_solve_opts *o) {
+    return guarded([&] {
+        if (!p || !o) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        p->prepare(Q_cell, *o);
+        p->out_on_device = o->outputs_on_device != 0;
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_iterate(nbte_problem *p, int32_t n, int32_t check, double *residual) {
+    return guarded([&] {
+        if (!p || n < 0) throw Error(NBTE_ERR_INVALID_ARG, "bad arguments");
+        p->iterate(n, check != 0, residual);
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_read_result(nbte_problem *p, nbte_result *out) {
+    return guarded([&] {
+        if (!p || !out) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        p->read_result(out);
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_solve_steady(nbte_problem *p, const double *Q_cell, const nbte_solve_opts *o, nbte_result *out) {
+    return guarded([&] {
+        if (!p || !o) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        if (!(o->tol > 0) || o->max_iter <= 0) throw Error(NBTE_ERR_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
+        p->prepare(Q_cell, *o);
+        p->out_on_device = o->outputs_on_device != 0;
+        const int every = std::max(1, o->check_every);
+        bool converged = false;
+        while (p->iterations < o->max_iter) {
+            const int n = std::min(every, o->max_iter - p->iterations);
+            double res = INFINITY;
+            p->iterate(n, true, &res);
+            if (res <= o->tol) {
+                converged = true;
+                break;
+            }
+        }
+        if (out) p->read_result(out);
+        if (!converged)
+            return fail(NBTE_ERR_NOT_CONVERGED, "not converged after " + std::to_string(p->iterations) +
+                                                    " iterations (residual " + std::to_string(p->residual) + ")");
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_get_distribution(nbte_problem *p, int32_t band, int32_t dir, double *out) {
+    return guarded([&] {
+        if (!p || !out) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        if (!p->prepared) throw Error(NBTE_ERR_STATE, "no distribution yet");
+        if (band < 0 || band >= p->bands.B || dir < 0 || dir >= p->quad.D)
+            throw Error(NBTE_ERR_INVALID_ARG, "band or direction out of range");
+        DevBuf tmp;
+        tmp.alloc(p->mesh->N * 8);
+        launch_distribution(p->view(), p->precision == NBTE_PREC_MIXED, p->d_theta[p->prev].as<double>(), band, dir,
+                            tmp.as<double>(), p->stream);
+        NBTE_HIP(hipMemcpyAsync(out, tmp.ptr, p->mesh->N * 8, hipMemcpyDeviceToHost, p->stream));
+        NBTE_HIP(hipStreamSynchronize(p->stream));
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_get_schedule(nbte_problem *p, int32_t dir, int32_t *perm, int32_t *lvl_ptr, int32_t cap_levels,
+                              int32_t *n_levels) {
+    return guarded([&] {
+        if (!p || !n_levels) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        if (!p->have_quad) throw Error(NBTE_ERR_STATE, "quadrature not set");
+        if (dir < 0 || dir >= p->quad.D) throw Error(NBTE_ERR_INVALID_ARG, "direction out of range");
+        if (!p->sched_ok) {
+            p->sched = build_schedule(*p->mesh, p->quad);
+            p->sched_ok = true;
+            p->sched_up = false;
+        }
+        const auto &sc = p->sched;
+        const int32_t b = sc.lvl_off[dir], e = sc.lvl_off[dir + 1];
+        *n_levels = e - b - 1;
+        if (perm) std::copy(&sc.perm[(size_t)dir * p->mesh->N], &sc.perm[(size_t)(dir + 1) * p->mesh->N], perm);
+        if (lvl_ptr) {
+            if (cap_levels < *n_levels + 1) throw Error(NBTE_ERR_INVALID_ARG, "lvl_ptr capacity too small");
+            std::copy(&sc.lvl_ptr[b], &sc.lvl_ptr[e], lvl_ptr);
+        }
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_get_stats(nbte_problem *p, nbte_stats *st) {
+    return guarded([&] {
+        if (!p || !st) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        p->collect_stats();
+        *st = p->stats;
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t) {
+    return guarded([&] {
+        if (!p || !t) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        if (t->bands_per_block < 0) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block must be >= 0");
+        if (t->lds_bytes < -1 || t->lds_bytes > 65536) throw Error(NBTE_ERR_INVALID_ARG, "lds_bytes must be -1, 0 or <= 65536");
+        const int bpl = t->bands_per_lane;
+        if (bpl != 0 && bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8 && bpl != 16)
+            throw Error(NBTE_ERR_INVALID_ARG, "bands_per_lane must be 0, 1, 2, 4, 8 or 16");
+        if (t->block_size != 0 && (t->block_size < 64 || t->block_size > 1024 || t->block_size % 64))
+            throw Error(NBTE_ERR_INVALID_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
+        if (t->cg_max_iter < 0 || !(t->cg_rtol >= 0)) throw Error(NBTE_ERR_INVALID_ARG, "bad CG settings");
+        p->tuning = *t;
+        p->prepared = false;   // launch shape and slot table are rebuilt by the next prepare
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t) {
+    return guarded([&] {
+        if (!p || !t) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        *t = p->tuning;
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int64_t *bytes) {
+    return guarded([&] {
+        if (!p || !bytes) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        if (!p->have_bands || !p->have_quad) throw Error(NBTE_ERR_STATE, "bands and quadrature must be set");
+        const Mesh &m = *p->mesh;
+        const int64_t N = m.N, F = m.F, D = p->quad.D, NBF = m.NBF, B = p->bands.B;
+        int64_t geo = N * F * (4 + 24) + N * 16 + NBF * 4;
+        int64_t sched = D * N * 4 + D * (N + 1) * 4;
+        int64_t plan = NBF * (4 + 8 + 8 + 8 + 4 * D + 8 * D);
+        int64_t lh = N * (F + 1) * 12 + N * 8 * 7;
+        *bytes = geo + sched + plan + lh + p->state_bytes(precision);
+        return NBTE_OK;
+    });
+}
+
+}  // extern "C"

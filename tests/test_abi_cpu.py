@@ -1,0 +1,173 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every declared symbol, the mesh builder reproduces exact geometry,
+argument validation returns the documented status codes, and the sweep
+schedules respect upwind order."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_03226_amd import nbte as N
+from workloads import Boundary
+from workloads import configs as C
+from workloads import meshes as M
+from workloads.tables import gl_azimuth_quadrature, inplane_quadrature
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "nbte.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nbte_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(N.LIB_PATH)
+    names = _declared_symbols()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    bound = {s[0] for s in N.SIGNATURES}
+    assert set(names) <= bound, set(names) - bound
+    assert "gfx950" in N.nbte_version()
+
+
+def _handles(p):
+    mesh = N.nbte_mesh_create(p.dim, p.xyz, p.cell_type, p.cells, p.bfaces, p.bface_tag)
+    h = N.nbte_problem_create(mesh)
+    return mesh, h
+
+
+@pytest.mark.parametrize("maker", [C.config1, C.config2_small, C.config3_small, lambda: C.config4_small()[2]])
+def test_mesh_info_matches_exact_geometry(maker):
+    p = maker()
+    mesh = N.nbte_mesh_create(p.dim, p.xyz, p.cell_type, p.cells, p.bfaces, p.bface_tag)
+    info = N.nbte_mesh_get_info(mesh)
+    assert info["n_cells"] == p.n_cells and info["n_bfaces"] == len(p.bfaces)
+    assert info["max_closure_error"] < 1e-14
+    from oracle import geometry
+    g = geometry.build(p.xyz, p.cell_type, p.cells, p.bfaces, p.bface_tag)
+    assert info["total_volume"] == pytest.approx(g.V.sum(), rel=1e-13)
+
+
+def test_mesh_validation_errors():
+    xyz, cells, bf, tags = M.structured_quad(np.linspace(0, 1, 4), np.linspace(0, 1, 4))
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_mesh_create(2, xyz, "quad4", cells, bf[:-1], tags[:-1])
+    assert e.value.status == N.ERR_MESH
+    bad = cells.copy()
+    bad[0, 0] = 10 ** 6
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_mesh_create(2, xyz, "quad4", bad, bf, tags)
+    assert e.value.status == N.ERR_MESH
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_mesh_create(3, np.c_[xyz, np.zeros(len(xyz))], "quad4", cells, bf, tags)
+    assert e.value.status == N.ERR_INVALID_ARG
+    nan = xyz.copy(); nan[3, 0] = np.nan
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_mesh_create(2, nan, "quad4", cells, bf, tags)
+    assert e.value.status == N.ERR_INVALID_ARG
+    # inverted cell: faces no longer close consistently / volume not positive
+    inv = cells.copy(); inv[4] = inv[4][[0, 2, 1, 3]]
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_mesh_create(2, xyz, "quad4", inv, bf, tags)
+    assert e.value.status == N.ERR_MESH
+
+
+def test_table_validation_and_state_errors():
+    p = C.config1()
+    mesh, h = _handles(p)
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_prepare(h, None, N.make_opts())
+    assert e.value.status == N.ERR_STATE
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_bands(h, [1.0], [-1.0], [1e-12])
+    assert e.value.status == N.ERR_INVALID_ARG
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_bands(h, [1.0], [1.0], [np.nan])
+    assert e.value.status == N.ERR_INVALID_ARG
+    s, w = inplane_quadrature(8)
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_quadrature(h, s * 1.01, w)
+    assert e.value.status == N.ERR_QUADRATURE
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_quadrature(h, s, -w)
+    assert e.value.status == N.ERR_QUADRATURE
+    s3, w3 = gl_azimuth_quadrature(2, 4)
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_quadrature(h, s3, w3)          # 3D directions on a 2D mesh
+    assert e.value.status == N.ERR_QUADRATURE
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_boundaries(h, [(1, "partial", 0.0, 1.5)])
+    assert e.value.status == N.ERR_BOUNDARY
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_boundaries(h, [(1, "thermalizing", 300.0, 0), (1, "specular", 0, 0)])
+    assert e.value.status == N.ERR_BOUNDARY
+
+
+def _prepare_status(p):
+    mesh, h = _handles(p)
+    N.nbte_set_bands(h, p.C, p.v, p.tau)
+    N.nbte_set_quadrature(h, p.s, p.w)
+    N.nbte_set_boundaries(h, [(b.tag, b.kind, b.T_wall, b.specularity) for b in p.boundaries])
+    try:
+        N.nbte_prepare(h, p.Q, N.make_opts())
+    except N.NbteError as e:
+        return e.status
+    return N.OK
+
+
+def test_host_setup_errors_come_before_device_errors():
+    p = C.config1()
+    # no thermalizing wall -> ill-posed
+    p.boundaries = [Boundary(t, "specular") for t in (1, 2, 3, 4)]
+    assert _prepare_status(p) == N.ERR_ILL_POSED
+    # a tag without a condition
+    p = C.config1(); p.boundaries = p.boundaries[:3]
+    assert _prepare_status(p) == N.ERR_BOUNDARY
+    # specular x-wall whose mirror directions are not in the set: with 7
+    # half-offset in-plane directions pi - phi_j is never a member
+    p = C.config1(D=7)
+    p.boundaries = [Boundary(1, "specular"), Boundary(2, "specular"),
+                    Boundary(3, "thermalizing", 301.0), Boundary(4, "thermalizing", 299.0)]
+    assert _prepare_status(p) == N.ERR_QUADRATURE
+    # a valid problem gets through host setup and then needs the GPU
+    p = C.config1()
+    st = _prepare_status(p)
+    assert st in (N.OK, N.ERR_DEVICE)
+
+
+@pytest.mark.parametrize("maker", [C.config1, C.config2_small, C.config3_small, lambda: C.config4_small()[1]])
+def test_schedule_levels_respect_upwind_order(maker):
+    p = maker()
+    mesh, h = _handles(p)
+    N.nbte_set_quadrature(h, p.s, p.w)
+    from oracle import geometry
+    g = geometry.build(p.xyz, p.cell_type, p.cells, p.bfaces, p.bface_tag)
+    for i in range(0, p.n_dirs, max(1, p.n_dirs // 7)):
+        perm, lvl = N.nbte_get_schedule(h, i)
+        assert np.array_equal(np.sort(perm), np.arange(p.n_cells))
+        level = np.empty(p.n_cells, int)
+        for l in range(len(lvl) - 1):
+            level[perm[lvl[l]:lvl[l + 1]]] = l
+        a = np.einsum("cfk,k->cf", g.S, p.s[i])
+        c, f = np.nonzero((a < 0) & (g.nbr >= 0))
+        assert np.all(level[g.nbr[c, f]] < level[c])
+        # levels are as shallow as possible: each cell past level 0 has an upwind neighbour one level up
+        deep = level > 0
+        has_prev = np.zeros(p.n_cells, bool)
+        has_prev[c[level[g.nbr[c, f]] == level[c] - 1]] = True
+        assert np.all(has_prev[deep])
+
+
+def test_footprint_scales_with_precision():
+    p = C.config2_small()
+    mesh, h = _handles(p)
+    N.nbte_set_bands(h, p.C, p.v, p.tau)
+    N.nbte_set_quadrature(h, p.s, p.w)
+    f32 = N.nbte_problem_footprint(h, "mixed")
+    f64 = N.nbte_problem_footprint(h, "fp64")
+    assert f64 - f32 == p.n_cells * p.n_bands * p.n_dirs * 4

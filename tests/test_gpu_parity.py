@@ -1,0 +1,192 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Errors are deviation-relative and stated per result:
+  err_TL = max|T_L,gpu - T_L,ora| / max|T_L,ora - T_ref|   (same for T)
+  err_q  = max ||q_gpu - q_ora|| / max ||q_ora||
+Bars: plain FP64 path 1e-9 (iteration-tolerance limited), mixed path 1e-6.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs as C
+
+pytestmark = pytest.mark.gpu
+
+LOG = os.environ.get("NBTE_PARITY_LOG")
+
+
+def _N():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_03226_amd import nbte
+    return nbte
+
+
+def _errors(out, ref, T_ref):
+    dTL = np.max(np.abs(ref.T_lattice - T_ref))
+    dT = np.max(np.abs(ref.T - T_ref))
+    qn = np.max(np.linalg.norm(ref.q, axis=1))
+    return {
+        "err_TL": float(np.max(np.abs(out["T_lattice"] - ref.T_lattice)) / dTL),
+        "err_T": float(np.max(np.abs(out["T"] - ref.T)) / dT),
+        "err_q": float(np.max(np.linalg.norm(out["q"] - ref.q, axis=1)) / qn),
+        "rel_abs_TL": float(np.max(np.abs(out["T_lattice"] - ref.T_lattice) / np.abs(ref.T_lattice))),
+    }
+
+
+def _log(name, rec):
+    print(name, json.dumps(rec), flush=True)
+    if LOG:
+        with open(LOG, "a") as f:
+            f.write(json.dumps({"case": name, **rec}) + "\n")
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle(key, p):
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle.solve(p, tol=1e-13, max_iter=20000, defect_tol=1e-11)
+    return _ORACLE_CACHE[key]
+
+
+CASES = [
+    ("config1", C.config1, "sequential"),
+    ("config2_small", C.config2_small, "synthetic"),
+    ("config3_small", C.config3_small, "synthetic"),
+    ("config4_small_0", lambda: C.config4_small()[0], "synthetic"),
+    ("config4_small_3", lambda: C.config4_small()[3], "synthetic"),
+]
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-9), ("mixed", 1e-6)])
+@pytest.mark.parametrize("name,maker,scheme", CASES)
+def test_converged_parity(name, maker, scheme, precision, bar):
+    N = _N()
+    p = maker()
+    ref = _oracle(name, p)
+    tol = 1e-12 if precision == "fp64" else 1e-9
+    out = N.solve(p, precision=precision, scheme=scheme, tol=tol, max_iter=20000, allow_not_converged=True)
+    rec = _errors(out, ref, p.T_ref)
+    rec.update(iterations=out["iterations"], residual=out["residual"], energy_defect=out["energy_defect"],
+               oracle_iterations=ref.iterations, precision=precision)
+    _log(f"{name}/{precision}", rec)
+    assert rec["err_TL"] < bar and rec["err_T"] < bar and rec["err_q"] < bar, rec
+    if precision == "fp64":
+        assert out["energy_defect"] < 1e-9
+
+
+@pytest.mark.parametrize("scheme", ["sequential", "synthetic_literal"])
+def test_other_schemes_reach_the_same_fixed_point(scheme):
+    N = _N()
+    p = C.config2_small()
+    ref = _oracle("config2_small", p)
+    out = N.solve(p, precision="fp64", scheme=scheme, tol=1e-12, max_iter=20000, allow_not_converged=True)
+    rec = _errors(out, ref, p.T_ref)
+    _log(f"config2_small/{scheme}", rec)
+    assert max(rec["err_TL"], rec["err_T"], rec["err_q"]) < 1e-8, rec
+
+
+def _one_sweep_check(p, precision, systems, bar):
+    """One iteration from a given T_init: the distribution of sampled
+    (band, direction) systems against the oracle's exact sweeps."""
+    N = _N()
+    su = oracle.prepare(p)
+    rng = np.random.default_rng(42)
+    xc = su.g.xc
+    span = np.ptp(xc, axis=0) + 1e-30
+    theta0 = np.sin(2.1 * xc[:, 0] / span[0]) + 0.5 * np.cos(3.3 * xc[:, 1] / span[1]) + 0.2 * rng.standard_normal(su.g.N)
+    mesh, h = N.build_problem(p)
+    opts = N.make_opts(scheme="sequential", precision=precision, T_ref=p.T_ref, T_init=p.T_ref + theta0)
+    N.nbte_prepare(h, p.Q, opts)
+    N.nbte_iterate(h, 1)
+    e0 = {}
+    B, D = p.n_bands, p.n_dirs
+    eq = oracle.equilibrium(su, theta0)
+    full_e0 = np.broadcast_to(eq[:, None, :], (B, D, su.g.N))
+    inflow = oracle.boundary_inflow(su, full_e0)
+    ref = oracle.transport_systems(su, theta0, inflow, systems)
+    worst = 0.0
+    for (b, i) in systems:
+        e_gpu = N.nbte_get_distribution(h, b, i)
+        err = np.max(np.abs(e_gpu - ref[(b, i)])) / np.max(np.abs(ref[(b, i)]))
+        worst = max(worst, err)
+    return worst
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("mixed", 1e-6)])
+@pytest.mark.parametrize("which", ["config2", "config3"])
+def test_one_sweep_full_size_sampled_systems(which, precision, bar):
+    p = C.config2() if which == "config2" else C.config3()
+    rng = np.random.default_rng(7)
+    systems = [(int(rng.integers(p.n_bands)), int(rng.integers(p.n_dirs))) for _ in range(12)]
+    systems += [(0, 0), (p.n_bands - 1, p.n_dirs - 1)]
+    worst = _one_sweep_check(p, precision, systems, bar)
+    _log(f"{which}/one_sweep/{precision}", {"err_e": worst, "systems": len(systems)})
+    assert worst < bar
+
+
+SHAPES = [  # (bands_per_block, bands_per_lane, block_size, lds_bytes)
+    (1, 1, 64, 0), (2, 1, 256, 0), (4, 2, 512, 0), (5, 1, 1024, 0), (5, 4, 128, 0),
+    (3, 1, 256, -1), (2, 2, 64, 256),   # no staging; a tiny LDS budget that spills
+]
+
+
+@pytest.mark.parametrize("bpb,bpl,block,lds", SHAPES)
+def test_sweep_launch_shapes_agree(bpb, bpl, block, lds):
+    """Every launch shape computes the same solution (B = 5: ragged band blocks).
+    Staged values skip one round trip through the stored g, so shapes agree to
+    rounding, not bitwise."""
+    N = _N()
+    for maker in (C.config2_small, C.config3_small):
+        p = maker()
+        base = N.solve(p, precision="fp64", scheme="synthetic", tol=1e-12, max_iter=3000)
+        out = N.solve(p, precision="fp64", scheme="synthetic", tol=1e-12, max_iter=3000,
+                      tuning={"bands_per_block": bpb, "bands_per_lane": bpl, "block_size": block, "lds_bytes": lds})
+        dev = np.max(np.abs(base["T_lattice"] - p.T_ref))
+        assert np.max(np.abs(out["T_lattice"] - base["T_lattice"])) / dev < 1e-11
+
+
+def test_deterministic_bitwise():
+    N = _N()
+    p = C.config3_small()
+    a = N.solve(p, precision="mixed", tol=1e-9, max_iter=5000)
+    b = N.solve(p, precision="mixed", tol=1e-9, max_iter=5000)
+    assert a["iterations"] == b["iterations"]
+    assert np.array_equal(a["T_lattice"], b["T_lattice"]) and np.array_equal(a["q"], b["q"])
+
+
+def test_error_paths_on_device():
+    N = _N()
+    p = C.config1()
+    out = N.solve(p, precision="fp64", scheme="sequential", tol=1e-14, max_iter=3, allow_not_converged=True)
+    assert out["converged"] is False and out["iterations"] == 3
+    with pytest.raises(N.NbteError) as e:
+        N.solve(p, precision="fp64", scheme="sequential", tol=1e-14, max_iter=3)
+    assert e.value.status == N.ERR_NOT_CONVERGED
+    q = np.zeros(p.n_cells); q[5] = np.nan
+    p.Q = q
+    with pytest.raises(N.NbteError) as e:
+        N.solve(p)
+    assert e.value.status == N.ERR_INVALID_ARG
+
+
+def test_device_outputs_and_warm_start():
+    N = _N()
+    import torch
+    p = C.config2_small()
+    mesh, h = N.build_problem(p)
+    opts = N.make_opts(precision="fp64", tol=1e-12, outputs_on_device=True)
+    out = N.nbte_solve_steady(h, p.Q, opts)
+    assert out["T_lattice"].is_cuda
+    host = N.solve(p, precision="fp64", tol=1e-12)
+    assert np.array_equal(out["T_lattice"].cpu().numpy(), host["T_lattice"])
+    # warm start from the converged field converges in very few iterations
+    warm = N.solve(p, precision="fp64", tol=1e-12, T_init=host["T_lattice"])
+    assert warm["iterations"] <= 3
+    torch.cuda.synchronize()
