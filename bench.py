@@ -131,6 +131,11 @@ def main():
     p = workload(args.workload)
     log(f"bench: workload {p.name} N={p.n_cells} B={p.n_bands} D={p.n_dirs} precision {args.precision}")
     mesh, h = N.build_problem(p)
+    from paper_2607_03226_amd import tune
+    shape = tune.lookup(p, args.precision)
+    if shape:
+        N.nbte_set_tuning(h, **shape)
+    log(f"bench: sweep shape {shape or 'library default'}")
     opts = N.make_opts(scheme=p.scheme, precision=args.precision, T_ref=p.T_ref, time_phases=True)
     N.nbte_prepare(h, p.Q, opts)
     N.nbte_iterate(h, args.warmup, check=True)
@@ -166,6 +171,8 @@ def main():
         ref_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_reference.npz")
         ref = np.load(ref_path) if os.path.exists(ref_path) else None
         for prec in ("mixed", "fp64"):
+            sh = tune.lookup(p, prec)
+            N.nbte_set_tuning(h, **(sh or {}))
             o2 = N.make_opts(scheme=p.scheme, precision=prec, T_ref=p.T_ref, tol=1e-8, max_iter=20000)
             N.nbte_solve_steady(h, p.Q, o2)       # setup for this precision cached by the first call
             torch.cuda.synchronize()
@@ -199,6 +206,8 @@ def main():
                    "updates_per_step": ups},
         "roofline": roofline, "cpu_baseline": cpu, "converge": converge,
         "phases_ms_per_step": phases, "bytes_per_update_stored": per_update,
+        "sweep_shape": {k: st[k] for k in ("bands_per_block", "bands_per_lane", "block_size", "lds_slots",
+                                           "spilled_values", "max_levels")},
     }
     print(json.dumps(line), flush=True)
 

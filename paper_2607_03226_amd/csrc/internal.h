@@ -115,11 +115,39 @@ struct Schedule {
     int slot_cap = 0;                // budget the slots were assigned for
     int max_slots = 0;               // slots actually used (max over directions)
     int64_t spilled = 0;             // consumed values that did not fit
+    int max_ghosts = 0;              // most boundary inflow faces feeding one level
 };
 
 Schedule build_schedule(const Mesh &m, const Quadrature &q);
 // (Re)assign LDS slots for a budget of `cap` slots per direction.
 void assign_slots(const Mesh &m, const Quadrature &q, Schedule &sc, int cap);
+
+// The sweep of every direction compiled into level-ordered streams (index
+// i*N + k for position k of direction i), so that the sweep kernel loads
+// everything it needs for a cell with independent, coalesced loads:
+//   cell, LDS slot of the cell's own value, up to maxin upwind references
+//   (>= 0: LDS slot; -1-bf: boundary inflow of face bf; <= -(NBF+2): the
+//   stored value of cell -ref-NBF-2), their coefficients |s.S|/V, and the
+//   outflow sum sum_{a>0} a.  Unused reference entries have coefficient 0.
+struct SweepProgram {
+    int maxin = 0;
+    std::vector<int32_t> cell, slot, ref;   // ref: maxin * D*N
+    std::vector<double> coef, sout;         // coef: maxin * D*N
+    // Ghosts: the boundary inflow values a level needs, in sweep order.
+    // gptr has the layout of lvl_ptr (per direction L_i + 1 entries, absolute
+    // offsets into the concatenated ghost list); ghost_src[g] = (bf*D + i)*B,
+    // the inflow row of ghost g; a boundary reference of a cell in level l is
+    // -1 - (its rank among the ghosts of level l).
+    std::vector<int32_t> gptr;
+    std::vector<int64_t> ghost_src;
+    int max_ghosts = 0;                     // most ghosts of one level
+};
+// record reference ranges (shared with the sweep kernel): >= 0 LDS slot;
+// [-kSpillBase, -1] ghost of the level kept in LDS, -1 - rank;
+// [-2 kSpillBase, -kSpillBase - 1] ghost read from HBM, -kSpillBase - 1 - row;
+// below: stored value of a cell, -(2 kSpillBase + 2) - cell
+constexpr int32_t kSpillBase = 1 << 24;
+SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap);
 
 // Boundary plan: per boundary face kind/wall data, s.S per direction and the
 // specular mirror table.

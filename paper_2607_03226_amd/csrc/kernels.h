@@ -22,7 +22,19 @@ struct DeviceView {
     const int32_t *perm;    // D*N
     const int32_t *lvl_ptr;
     const int32_t *lvl_off; // D+1
-    const int32_t *slot;    // D*N LDS slot of each cell's value (-1: read from HBM), or null
+    // sweep program: level-ordered streams, index i*N + k (see SweepProgram)
+    int32_t maxin;
+    int32_t max_levels;     // deepest level count over the directions
+    int32_t max_ghosts;     // most boundary inflow values (per band) of one level
+    int64_t n_ghost;        // ghost rows over all directions
+    const int32_t *gptr;    // ghost offsets per level (layout of lvl_ptr)
+    const int64_t *ghost_src;  // inflow row of each ghost
+    double *gval;           // ghost values in sweep order (n_ghost * B)
+    const int32_t *p_cell, *p_slot, *p_ref;
+    const double *p_coef, *p_sout;
+    double *p_th;           // theta in level order, gathered every iteration
+    double *p_q;            // heat source in level order, gathered at prepare
+    const double *theta_cell;  // theta by cell (read only for values without an LDS slot)
     // bands: Cw = C/W, src = C/(C_tot W), v, inv_tau
     const double *Cw, *src, *vel, *inv_tau;
     // quadrature
@@ -43,8 +55,14 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 void launch_bc_inflow(const DeviceView &v, bool fp32, const double *theta_base, hipStream_t st);
 // bands_per_block bands of one direction per workgroup, bands_per_lane per
 // lane; lds_slots = slots per direction the schedule was assigned for.
+// spill: some consumed values are read back from HBM (full fence per level)
+// gcap: ghosts per level kept in LDS (the rest are read from HBM)
 void launch_sweep(const DeviceView &v, bool fp32, const double *theta, int bands_per_block, int bands_per_lane,
-                  int block, int lds_slots, hipStream_t st);
+                  int block, int lds_slots, int gcap, bool spill, hipStream_t st);
+// ghost values of every direction in sweep order, from the boundary inflow
+void launch_ghost_gather(const DeviceView &v, hipStream_t st);
+// out[at] = in[p_cell[at]] for every stream position (theta or Q into level order)
+void launch_gather(const DeviceView &v, const double *in, double *out, hipStream_t st);
 void launch_wall_flux(const DeviceView &v, bool fp32, const double *theta, hipStream_t st);
 void launch_moments(const DeviceView &v, bool fp32, const double *theta, double beta, double C_tot,
                     const double *V, const double *qbias, double *theta_seq, double *thetaE, double *q,

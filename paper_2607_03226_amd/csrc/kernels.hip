@@ -17,8 +17,7 @@
 namespace nbte {
 namespace {
 
-constexpr int kMaxFaces = 6;
-constexpr int64_t kPcgBlockMaxRows = 65536;   // larger systems use the multi-workgroup PCG
+constexpr int64_t kPcgBlockMaxRows = 4096;    // larger systems use the multi-workgroup PCG
 
 template <class T>
 __device__ __forceinline__ double ld(const T *p, int64_t k) {
@@ -99,77 +98,269 @@ __global__ void k_bc_inflow(DeviceView v, const double *theta_base) {
 //   e_c = (e0_l/tau_l + S_l + v_l sum_{a<0} |a| e_up) / (1/tau_l + v_l sum_{a>0} a),
 //   a = (s_i . S_cf) / V_c,
 // e_up = value of the upwind neighbour computed earlier in this sweep, or the
-// boundary inflow.  Neighbour values are staged in LDS (FP64) in the slots the
-// host assigned (interval allocation over levels); a value without a slot is
-// read back from its stored copy in HBM.  Levels are separated by a workgroup
-// barrier, which orders both the LDS and the HBM writes of level k before the
-// reads of level k+1.
+// boundary inflow.  Everything a cell needs comes from the direction's
+// level-ordered streams (cell, coefficients, upwind references, theta, Qdot):
+// independent coalesced loads, no pointer chasing.  Upwind values are staged
+// in LDS (FP64) in host-assigned slots; a value without a slot is read back
+// from its stored copy.  A workgroup barrier separates levels; it orders the
+// LDS and HBM writes of level k before the reads of level k+1.
+//
+// Workgroup -> (direction, band block): with xcd_map the band blocks of one
+// direction get consecutive dispatch slots on the same XCD (dispatch goes
+// round-robin over the 8 XCDs), so they share that direction's streams in
+// one L2.
 // --------------------------------------------------------------------------
-template <class T, int BPL>
-__global__ void __launch_bounds__(1024) k_sweep(DeviceView v, const double *__restrict__ theta, int lpc,
-                                                 int bands_per_block) {
-    extern __shared__ double ring[];   // ring[slot * bands_per_block + local band]
-    const int i = blockIdx.y;
-    const int b0 = blockIdx.x * bands_per_block;
+// Dynamic LDS of the sweep.  It is indexed with integer offsets (never through
+// pointers passed around), so every access stays in the LDS address space.
+extern __shared__ double sweep_lds[];
+extern __shared__ int sweep_ldsi[];   // the same memory viewed as ints (level tables)
+
+constexpr int kGhostPerThread = 4;    // ghost values a thread prefetches per level
+constexpr int kItemsPerThread = 2;    // cells per thread and level with prefetched records
+// record references: >= 0 LDS slot; [-kSpill, -1] ghost of the level in LDS (rank);
+// [-2 kSpill, -kSpill - 1] ghost read from HBM (row); below: spilled cell
+constexpr int32_t kSpill = 1 << 24;
+
+// One cell's sweep record (a position of a direction's level-ordered streams).
+template <int MI>
+struct SweepRec {
+    int c, mine;
+    int ref[MI];
+    double cf[MI];
+    double sout, th, Q;
+    bool ok;
+};
+
+template <int MI>
+__device__ __forceinline__ void load_rec(SweepRec<MI> &r, const DeviceView &v, int64_t base, int64_t DN, int k,
+                                         int kend) {
+    r.ok = k < kend;
+    if (!r.ok) return;
+    const int64_t at = base + k;
+    r.c = v.p_cell[at];
+    r.mine = v.p_slot[at];
+    r.sout = v.p_sout[at];
+    r.th = v.p_th[at];
+    r.Q = v.p_q[at];
+#pragma unroll
+    for (int j = 0; j < MI; ++j) {
+        r.ref[j] = v.p_ref[j * DN + at];
+        r.cf[j] = v.p_coef[j * DN + at];
+    }
+}
+
+// Per-lane band constants, loaded once per workgroup: inside the level loop
+// the sweep never waits on a load issued in the same level, because a wait on
+// any load also waits for every older one (the vector memory counter is in
+// order), which would drain the prefetched records.
+template <int BPL>
+struct BandConst {
+    double cw[BPL], itau[BPL], vel[BPL], src[BPL];
+};
+
+template <class T, int MI, int BPL>
+__device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceView &v, const BandConst<BPL> &bc,
+                                           T *gi, int ring_off, int gbuf_off, int gcap, int g0, int bands_per_block,
+                                           int b0, int lane, int nb_here) {
+    const int B = v.B;
+#pragma unroll
+    for (int jb = 0; jb < BPL; ++jb) {
+        const int lb = lane * BPL + jb;
+        if (lb >= nb_here) break;
+        const int lam = b0 + lb;
+        const double cw = bc.cw[jb];
+        const double itau = bc.itau[jb];
+        double gain = 0.0;
+#pragma unroll
+        for (int j = 0; j < MI; ++j) {
+            if (r.cf[j] == 0.0) continue;
+            const int rf = r.ref[j];
+            double up;
+            if (rf >= 0) {
+                up = sweep_lds[ring_off + rf * bands_per_block + lb];
+            } else if (rf >= -kSpill) {
+                up = sweep_lds[gbuf_off + (-1 - rf) * bands_per_block + lb];
+            } else if (rf >= -2 * kSpill) {
+                up = v.gval[(int64_t)(-kSpill - 1 - rf) * B + lam];   // ghost beyond the LDS capacity
+            } else {
+                const int n = -(2 * kSpill + 2) - rf;
+                up = ld(gi, (int64_t)n * B + lam) + cw * v.theta_cell[n];
+            }
+            gain += r.cf[j] * up;
+        }
+        const double vel = bc.vel[jb];
+        const double e = (cw * r.th * itau + r.Q * bc.src[jb] + vel * gain) / (itau + vel * r.sout);
+        gi[(int64_t)r.c * B + lam] = static_cast<T>(e - cw * r.th);
+        if (r.mine >= 0) sweep_lds[ring_off + r.mine * bands_per_block + lb] = e;
+    }
+}
+
+// Level barrier.  Without spilled values nothing written to HBM during the
+// sweep is read back by it, so the barrier only has to order LDS; the fences
+// are restricted to the LDS address space.  With spilled values the full
+// workgroup fence also orders the global stores.
+template <bool SPILL>
+__device__ __forceinline__ void level_barrier() {
+    if constexpr (SPILL) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+}
+
+// --------------------------------------------------------------------------
+// Pipeline per level l (after the barrier that ends level l-1):
+//   1. request the ghost values (boundary inflow) of level l+1 into registers;
+//   2. request the records of level l+2;
+//   3. compute level l from registers (records requested at level l-2), the
+//      LDS ring (upwind values) and ghost buffer l&1 (stored during level l-1);
+//   4. store the ghost values of level l+1 into ghost buffer (l+1)&1;
+//   5. barrier.
+// Every wait is on loads issued before the current level's record requests.
+// The level loop is unrolled three ways so a record keeps its registers while
+// its loads are in flight (moving it would force the wait).
+// --------------------------------------------------------------------------
+template <class T, int MI, int BPL, bool SPILL>
+__global__ void __launch_bounds__(512) k_sweep(DeviceView v, int lpc, int bands_per_block, int nbb, int xcd_map,
+                                                int gcap) {
+    // dynamic LDS: [lvl_ptr | gptr of this direction: 2 (max_levels + 1) ints]
+    //              [ghost buffers: 2 x gcap x bands_per_block doubles]
+    //              [ring: slot x bands_per_block doubles]
+    const int L = blockIdx.x;
+    int i, bblk;
+    if (xcd_map) {
+        const int x = L & 7, r = L >> 3;
+        bblk = r % nbb;
+        i = (r / nbb) * 8 + x;
+    } else {
+        i = L / nbb;
+        bblk = L % nbb;
+    }
+    const int b0 = bblk * bands_per_block;
     const int slot = threadIdx.x / lpc;
     const int lane = threadIdx.x % lpc;
     const int nslots = blockDim.x / lpc;
     const int64_t N = v.N;
-    const int F = v.F, B = v.B, D = v.D;
-    const double sx = v.dirs[3 * i], sy = v.dirs[3 * i + 1], sz = v.dirs[3 * i + 2];
+    const int B = v.B;
+    const int64_t DN = (int64_t)v.D * N;
     T *gi = static_cast<T *>(v.g) + (int64_t)i * N * B;
-    const int32_t *perm = v.perm + (int64_t)i * N;
-    const int32_t *slot_i = v.slot ? v.slot + (int64_t)i * N : nullptr;
-    const int32_t *lp = v.lvl_ptr + v.lvl_off[i];
+    const int64_t base = (int64_t)i * N;
     const int nlev = v.lvl_off[i + 1] - v.lvl_off[i] - 1;
     const int nb_here = min(B, b0 + bands_per_block) - b0;
-
-    for (int l = 0; l < nlev; ++l) {
-        const int kend = lp[l + 1];
-        for (int k = lp[l] + slot; k < kend; k += nslots) {
-            const int c = perm[k];
-            double a[kMaxFaces];
-            int nb[kMaxFaces];
-            int ref[kMaxFaces];
-            double sum_out = 0.0;
-            const double iv = v.invV[c];
-            for (int f = 0; f < F; ++f) {
-                const double *S = v.S + ((int64_t)c * F + f) * 3;
-                a[f] = (sx * S[0] + sy * S[1] + sz * S[2]) * iv;
-                nb[f] = v.nbr[(int64_t)c * F + f];
-                ref[f] = (a[f] < 0.0 && nb[f] >= 0 && slot_i) ? slot_i[nb[f]] : -1;
-                if (a[f] > 0.0) sum_out += a[f];
-            }
-            const int mine = slot_i ? slot_i[c] : -1;
-            const double th = theta[c];
-            const double Qc = v.Q[c];
-#pragma unroll
-            for (int j = 0; j < BPL; ++j) {
-                const int lb = lane * BPL + j;
-                if (lb >= nb_here) break;
-                const int lam = b0 + lb;
-                const double cw = v.Cw[lam];
-                const double itau = v.inv_tau[lam];
-                double gain = 0.0;
-                for (int f = 0; f < F; ++f) {
-                    if (!(a[f] < 0.0)) continue;
-                    const int n = nb[f];
-                    double up;
-                    if (n >= 0)
-                        up = ref[f] >= 0 ? ring[ref[f] * bands_per_block + lb]
-                                         : ld(gi, (int64_t)n * B + lam) + cw * theta[n];
-                    else
-                        up = v.inflow[((int64_t)(-n - 1) * D + i) * B + lam];
-                    gain -= a[f] * up;
-                }
-                const double vel = v.vel[lam];
-                const double e = (cw * th * itau + Qc * v.src[lam] + vel * gain) / (itau + vel * sum_out);
-                gi[(int64_t)c * B + lam] = static_cast<T>(e - cw * th);
-                if (mine >= 0) ring[mine * bands_per_block + lb] = e;
-            }
+    const int ML = v.max_levels + 1;
+#define lp(t) sweep_ldsi[(t)]
+#define gp(t) sweep_ldsi[ML + (t)]
+    const int gbuf0 = ML;                               // 2*ML ints = ML doubles
+    const int gstride = gcap * bands_per_block;         // ghosts of a level kept in LDS (rank < gcap)
+    const int ring_off = gbuf0 + 2 * gstride;
+    {
+        const int32_t *glp = v.lvl_ptr + v.lvl_off[i];
+        const int32_t *ggp = v.gptr + v.lvl_off[i];
+#pragma nounroll
+        for (int t = threadIdx.x; t <= nlev; t += blockDim.x) {
+            lp(t) = glp[t];
+            gp(t) = ggp[t];
         }
-        __syncthreads();
     }
+    BandConst<BPL> bc;
+#pragma unroll
+    for (int jb = 0; jb < BPL; ++jb) {
+        const int lam = min(b0 + lane * BPL + jb, B - 1);
+        bc.cw[jb] = v.Cw[lam];
+        bc.itau[jb] = v.inv_tau[lam];
+        bc.vel[jb] = v.vel[lam];
+        bc.src[jb] = v.src[lam];
+    }
+    __syncthreads();
+
+    // ghost values of one level: entry e = q * bands_per_block + local band
+    double gv[kGhostPerThread];
+    auto ghost_load = [&](int l) {
+#pragma unroll
+        for (int m = 0; m < kGhostPerThread; ++m) gv[m] = 0.0;
+        if (l >= nlev) return;
+        const int g0 = gp(l), ne = min(gp(l + 1) - g0, gcap) * bands_per_block;
+#pragma unroll
+        for (int m = 0; m < kGhostPerThread; ++m) {
+            const int e = threadIdx.x + m * blockDim.x;
+            const int q = e / bands_per_block, lb = e - q * bands_per_block;
+            if (e < ne && lb < nb_here) gv[m] = v.gval[(int64_t)(g0 + q) * B + b0 + lb];
+        }
+    };
+    auto ghost_store = [&](int l) {
+        if (l >= nlev) return;
+        const int dst = gbuf0 + (l & 1) * gstride;
+        const int g0 = gp(l), ne = min(gp(l + 1) - g0, gcap) * bands_per_block;
+#pragma unroll
+        for (int m = 0; m < kGhostPerThread; ++m) {
+            const int e = threadIdx.x + m * blockDim.x;
+            if (e < ne) sweep_lds[dst + e] = gv[m];
+        }
+        // levels with more ghosts than the registers hold: direct copy
+#pragma nounroll
+        for (int e = threadIdx.x + kGhostPerThread * blockDim.x; e < ne; e += blockDim.x) {
+            const int q = e / bands_per_block, lb = e - q * bands_per_block;
+            sweep_lds[dst + e] = lb < nb_here ? v.gval[(int64_t)(g0 + q) * B + b0 + lb] : 0.0;
+        }
+    };
+
+    SweepRec<MI> q0[kItemsPerThread], q1[kItemsPerThread], q2[kItemsPerThread];
+    auto fetch = [&](SweepRec<MI> (&r)[kItemsPerThread], int l) {
+#pragma unroll
+        for (int p = 0; p < kItemsPerThread; ++p) {
+            if (l < nlev) load_rec(r[p], v, base, DN, lp(l) + slot + p * nslots, lp(l + 1));
+            else r[p].ok = false;
+        }
+    };
+    auto step = [&](int l, SweepRec<MI> (&cur)[kItemsPerThread], SweepRec<MI> (&n2)[kItemsPerThread]) {
+        ghost_load(l + 1);
+        fetch(n2, l + 2);
+        const int gcur = gbuf0 + (l & 1) * gstride;
+#pragma unroll
+        for (int p = 0; p < kItemsPerThread; ++p)
+            if (cur[p].ok)
+                sweep_cell<T, MI, BPL>(cur[p], v, bc, gi, ring_off, gcur, gcap, gp(l), bands_per_block, b0, lane,
+                                       nb_here);
+        // cells beyond kItemsPerThread per slot in a very wide level: no prefetch
+#pragma nounroll
+        for (int k = lp(l) + slot + kItemsPerThread * nslots; k < lp(l + 1); k += nslots) {
+            SweepRec<MI> rx;
+            load_rec(rx, v, base, DN, k, lp(l + 1));
+            sweep_cell<T, MI, BPL>(rx, v, bc, gi, ring_off, gcur, gcap, gp(l), bands_per_block, b0, lane, nb_here);
+        }
+        ghost_store(l + 1);
+        level_barrier<SPILL>();
+    };
+    ghost_load(0);
+    ghost_store(0);
+    fetch(q0, 0);
+    fetch(q1, 1);
+    __syncthreads();
+#pragma nounroll
+    for (int l = 0; l < nlev; l += 3) {
+        step(l, q0, q2);
+        if (l + 1 >= nlev) break;
+        step(l + 1, q1, q0);
+        if (l + 2 >= nlev) break;
+        step(l + 2, q2, q1);
+    }
+}
+#undef lp
+#undef gp
+
+__global__ void k_gather(int64_t n, const int32_t *idx, const double *in, double *out) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) out[k] = in[idx[k]];
+}
+
+// ghost values in sweep order: gval[g*B + l] = inflow[ghost_src[g] + l]
+__global__ void k_ghost_gather(int64_t n_ghost, int B, const int64_t *src, const double *inflow, double *gval) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_ghost * B) return;
+    const int64_t g = t / B;
+    gval[t] = inflow[src[g] + (t - g * B)];
 }
 
 // --------------------------------------------------------------------------
@@ -456,24 +647,42 @@ __global__ void __launch_bounds__(1024) k_pcg_block(PcgWork w, const double *b, 
     }
 }
 
+
+template <class T, int MI, bool SPILL>
+void dispatch_sweep_bpl(const DeviceView &v, int bpb, int bpl, int lpc, int nbb, int block, size_t lds, int xcd_map,
+                        int gcap, hipStream_t st) {
+    dim3 grid(nbb * v.D);
+    switch (bpl) {
+        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, SPILL>), grid, dim3(block), lds, st, v, lpc, bpb, nbb, xcd_map, gcap); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, SPILL>), grid, dim3(block), lds, st, v, lpc, bpb, nbb, xcd_map, gcap); break;
+        case 4: hipLaunchKernelGGL((k_sweep<T, MI, 4, SPILL>), grid, dim3(block), lds, st, v, lpc, bpb, nbb, xcd_map, gcap); break;
+        default: hipLaunchKernelGGL((k_sweep<T, MI, 8, SPILL>), grid, dim3(block), lds, st, v, lpc, bpb, nbb, xcd_map, gcap); break;
+    }
+}
+
 template <class T>
-void dispatch_sweep(const DeviceView &v, const double *theta, int bpb, int bpl, int block, int lds_slots,
+void dispatch_sweep(const DeviceView &v, int bpb, int bpl, int block, int lds_slots, int gcap, bool spill,
                     hipStream_t st) {
     // the caller guarantees bpb <= 64 * bpl (at most 64 lanes per cell)
     int lanes = (bpb + bpl - 1) / bpl;
     int lpc = 1;
     while (lpc < lanes) lpc <<= 1;
     const int nbb = (v.B + bpb - 1) / bpb;
-    if (block % 64 != 0 || block < 64 || block > 1024) block = 256;
+    if (block % 64 != 0 || block < 64 || block > 512) block = 256;
     if (block < lpc) block = lpc;
-    const size_t lds = v.slot ? (size_t)lds_slots * bpb * sizeof(double) : 0;
-    dim3 grid(nbb, v.D);
-    switch (bpl) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, 1>), grid, dim3(block), lds, st, v, theta, lpc, bpb); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, 2>), grid, dim3(block), lds, st, v, theta, lpc, bpb); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, 4>), grid, dim3(block), lds, st, v, theta, lpc, bpb); break;
-        case 8: hipLaunchKernelGGL((k_sweep<T, 8>), grid, dim3(block), lds, st, v, theta, lpc, bpb); break;
-        default: hipLaunchKernelGGL((k_sweep<T, 16>), grid, dim3(block), lds, st, v, theta, lpc, bpb); break;
+    const size_t lds = (size_t)(v.max_levels + 1) * sizeof(double)                   // two int tables
+                     + (size_t)2 * gcap * bpb * sizeof(double)                        // ghost buffers
+                     + (size_t)std::max(lds_slots, 1) * bpb * sizeof(double);          // ring
+    const int xcd_map = (v.D % 8 == 0) ? 1 : 0;
+    const int mi = v.maxin <= 2 ? 2 : (v.maxin == 3 ? 3 : 5);
+    if (spill) {
+        if (mi == 2) dispatch_sweep_bpl<T, 2, true>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
+        else if (mi == 3) dispatch_sweep_bpl<T, 3, true>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
+        else dispatch_sweep_bpl<T, 5, true>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
+    } else {
+        if (mi == 2) dispatch_sweep_bpl<T, 2, false>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
+        else if (mi == 3) dispatch_sweep_bpl<T, 3, false>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
+        else dispatch_sweep_bpl<T, 5, false>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
     }
 }
 
@@ -501,11 +710,25 @@ void launch_bc_inflow(const DeviceView &v, bool fp32, const double *theta_base, 
 }
 
 void launch_sweep(const DeviceView &v, bool fp32, const double *theta, int bpb, int bpl, int block, int lds_slots,
-                  hipStream_t st) {
-    if (bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8 && bpl != 16) bpl = 1;
+                  int gcap, bool spill, hipStream_t st) {
+    if (bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8) bpl = 1;
     if (bpb < 1) bpb = 1;
-    if (fp32) dispatch_sweep<float>(v, theta, bpb, bpl, block, lds_slots, st);
-    else dispatch_sweep<double>(v, theta, bpb, bpl, block, lds_slots, st);
+    DeviceView w = v;
+    w.theta_cell = theta;
+    if (fp32) dispatch_sweep<float>(w, bpb, bpl, block, lds_slots, gcap, spill, st);
+    else dispatch_sweep<double>(w, bpb, bpl, block, lds_slots, gcap, spill, st);
+}
+
+void launch_ghost_gather(const DeviceView &v, hipStream_t st) {
+    const int64_t n = v.n_ghost * v.B;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_ghost_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v.n_ghost, v.B,
+                       v.ghost_src, v.inflow, v.gval);
+}
+
+void launch_gather(const DeviceView &v, const double *in, double *out, hipStream_t st) {
+    const int64_t n = (int64_t)v.D * v.N;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v.p_cell, in, out);
 }
 
 void launch_wall_flux(const DeviceView &v, bool fp32, const double *theta, hipStream_t st) {

@@ -48,6 +48,11 @@ Schedule build_schedule(const Mesh &m, const Quadrature &q) {
         sc.lvl_ptr.push_back(0);
         while (!frontier.empty()) {
             std::sort(frontier.begin(), frontier.end());
+            int ghosts = 0;
+            for (int32_t u : frontier)
+                for (int f = 0; f < F; ++f)
+                    if (m.nbr[(int64_t)u * F + f] < 0 && sdot(u, f) < 0.0) ++ghosts;
+            sc.max_ghosts = std::max(sc.max_ghosts, ghosts);
             std::copy(frontier.begin(), frontier.end(), perm + done);
             done += (int64_t)frontier.size();
             sc.lvl_ptr.push_back((int32_t)done);
@@ -125,6 +130,85 @@ void assign_slots(const Mesh &m, const Quadrature &q, Schedule &sc, int cap) {
         }
         sc.max_slots = std::max(sc.max_slots, used);
     }
+}
+
+SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap) {
+    const int64_t N = m.N;
+    const int F = m.F;
+    const int D = q.D;
+    const int64_t DN = (int64_t)D * N;
+    SweepProgram pg;
+    // widest upwind fan-in over all cells and directions
+    for (int i = 0; i < D; ++i) {
+        const double *s = &q.s[3 * i];
+        for (int64_t c = 0; c < N; ++c) {
+            int nin = 0;
+            for (int f = 0; f < F; ++f) {
+                const double *S = &m.S[(c * F + f) * 3];
+                if (s[0] * S[0] + s[1] * S[1] + s[2] * S[2] < 0.0) ++nin;
+            }
+            pg.maxin = std::max(pg.maxin, nin);
+        }
+    }
+    pg.maxin = std::max(pg.maxin, 1);
+    if (pg.maxin > 5) throw Error(NBTE_ERR_MESH, "a cell has more than 5 upwind faces in some direction");
+    pg.cell.resize(DN);
+    pg.slot.resize(DN);
+    pg.sout.resize(DN);
+    pg.ref.assign((size_t)pg.maxin * DN, 0);
+    pg.coef.assign((size_t)pg.maxin * DN, 0.0);
+    pg.gptr.resize(sc.lvl_ptr.size());
+    const bool staged = !sc.slot.empty();
+    for (int i = 0; i < D; ++i) {
+        const double *s = &q.s[3 * i];
+        const int32_t *slot_i = staged ? &sc.slot[(size_t)i * N] : nullptr;
+        const int32_t *lp = &sc.lvl_ptr[sc.lvl_off[i]];
+        int32_t *gp = &pg.gptr[sc.lvl_off[i]];
+        const int L = sc.lvl_off[i + 1] - sc.lvl_off[i] - 1;
+        for (int l = 0; l < L; ++l) {
+            gp[l] = (int32_t)pg.ghost_src.size();
+            int rank = 0;
+            for (int k = lp[l]; k < lp[l + 1]; ++k) {
+                const int64_t at = (int64_t)i * N + k;
+                const int32_t c = sc.perm[at];
+                pg.cell[at] = c;
+                pg.slot[at] = slot_i ? slot_i[c] : -1;
+                const double iv = 1.0 / m.V[c];
+                double sout = 0.0;
+                int j = 0;
+                for (int f = 0; f < F; ++f) {
+                    const double *S = &m.S[((int64_t)c * F + f) * 3];
+                    const double a = (s[0] * S[0] + s[1] * S[1] + s[2] * S[2]) * iv;
+                    if (a > 0.0) {
+                        sout += a;
+                    } else if (a < 0.0) {
+                        const int32_t n = m.nbr[(int64_t)c * F + f];
+                        int32_t r;
+                        if (n < 0) {                                   // boundary: a ghost of this level
+                            const int64_t bf = -(int64_t)n - 1;
+                            const int64_t row = (int64_t)pg.ghost_src.size();
+                            pg.ghost_src.push_back((bf * D + i) * (int64_t)B);
+                            r = rank < gcap ? -1 - rank : -kSpillBase - 1 - (int32_t)row;
+                            ++rank;
+                        } else if (slot_i && slot_i[n] >= 0) {
+                            r = slot_i[n];                             // staged in LDS
+                        } else {
+                            r = -(2 * kSpillBase + 2) - n;             // stored copy in HBM
+                        }
+                        pg.ref[(size_t)j * DN + at] = r;
+                        pg.coef[(size_t)j * DN + at] = -a;
+                        ++j;
+                    }
+                }
+                pg.sout[at] = sout;
+            }
+            pg.max_ghosts = std::max(pg.max_ghosts, rank);
+        }
+        gp[L] = (int32_t)pg.ghost_src.size();
+    }
+    if ((int64_t)pg.ghost_src.size() >= kSpillBase) throw Error(NBTE_ERR_MESH, "too many boundary inflow rows");
+    if (N >= INT32_MAX - 2 * (int64_t)kSpillBase - 2) throw Error(NBTE_ERR_MESH, "too many cells");
+    return pg;
 }
 
 BoundaryPlan build_boundary_plan(const Mesh &m, const Quadrature &q,

@@ -79,6 +79,7 @@ struct nbte_problem {
     bool geom_ok = false, sched_ok = false, plan_ok = false, diff_ok = false, tables_ok = false;
     bool sched_up = false, plan_up = false, diff_up = false;
     Schedule sched;
+    SweepProgram prog;
     BoundaryPlan plan;
     DiffusionOperator diff;
 
@@ -101,11 +102,28 @@ struct nbte_problem {
     int iterations = 0;
     double residual = INFINITY;
     double heat_in = 0.0;
-    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0};
-    struct Shape { int bpb = 1, bpl = 1, block = 256, slots = 0; } shape;
+    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0};
+    struct Shape { int bpb = 1, bpl = 1, block = 256, slots = 0, gcap = 0; } shape;
     int slots_for_cap = -2;   // cap the current slot table was built for
-    DevBuf d_slot;
+    DevBuf d_pcell, d_pslot, d_pref, d_pcoef, d_psout, d_pth, d_pq, d_gptr, d_gsrc, d_gval;
+    int prog_B = -1, prog_gcap = -1;
     int time_phases = 0;
+
+    // HIP graphs of three iterations (the theta rotation has period 3), one per
+    // starting rotation; dropped by prepare (shape, scheme or buffers may change)
+    hipGraphExec_t graph_exec[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    bool use_graphs = true;
+    hipStream_t own_stream = nullptr;   // used when the caller passes the null stream
+
+    void drop_graphs() {
+        for (int r = 0; r < 3; ++r) {
+            if (graph_exec[r]) (void)hipGraphExecDestroy(graph_exec[r]);
+            if (graph[r]) (void)hipGraphDestroy(graph[r]);
+            graph_exec[r] = nullptr;
+            graph[r] = nullptr;
+        }
+    }
 
     // phase timing
     std::vector<std::array<hipEvent_t, PH_COUNT>> events;
@@ -114,8 +132,10 @@ struct nbte_problem {
     std::chrono::steady_clock::time_point t_wall0;
 
     ~nbte_problem() {
+        drop_graphs();
         for (auto &ev : events)
             for (auto e : ev) (void)hipEventDestroy(e);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
     }
 
     DeviceView view() const {
@@ -131,7 +151,21 @@ struct nbte_problem {
         v.perm = d_perm.as<int32_t>();
         v.lvl_ptr = d_lvl_ptr.as<int32_t>();
         v.lvl_off = d_lvl_off.as<int32_t>();
-        v.slot = shape.slots > 0 ? d_slot.as<int32_t>() : nullptr;
+        v.maxin = prog.maxin;
+        v.max_levels = sched.max_levels;
+        v.max_ghosts = prog.max_ghosts;
+        v.n_ghost = (int64_t)prog.ghost_src.size();
+        v.gptr = d_gptr.as<int32_t>();
+        v.ghost_src = d_gsrc.as<int64_t>();
+        v.gval = d_gval.as<double>();
+        v.p_cell = d_pcell.as<int32_t>();
+        v.p_slot = d_pslot.as<int32_t>();
+        v.p_ref = d_pref.as<int32_t>();
+        v.p_coef = d_pcoef.as<double>();
+        v.p_sout = d_psout.as<double>();
+        v.p_th = d_pth.as<double>();
+        v.p_q = d_pq.as<double>();
+        v.theta_cell = nullptr;
         v.Cw = d_Cw.as<double>();
         v.src = d_src.as<double>();
         v.vel = d_vel.as<double>();
@@ -168,21 +202,31 @@ struct nbte_problem {
         bpb = std::min(bpb, B);
         int bpl = tuning.bands_per_lane > 0 ? tuning.bands_per_lane : 1;
         while (bpl * 64 < bpb) bpl *= 2;          // at most 64 lanes per cell
-        if (bpl > 16) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block too large for 16 bands per lane");
+        if (bpl > 8) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block too large for 8 bands per lane");
         int lanes = (bpb + bpl - 1) / bpl, lpc = 1;
         while (lpc < lanes) lpc <<= 1;
         int block = tuning.block_size > 0 ? tuning.block_size : 256;
-        block = std::max(block, lpc);
+        block = std::min(std::max(block, lpc), 512);   // the sweep kernel is built for <= 512 threads
         sh.bpb = bpb;
         sh.bpl = bpl;
         sh.block = block;
-        const int budget = tuning.lds_bytes == 0 ? 65536 : tuning.lds_bytes;
-        sh.slots = budget < 0 ? 0 : std::min(budget, 65536) / (bpb * 8);
+        // the level tables and the two ghost buffers of a direction share the
+        // workgroup's LDS with the staged values; at most a quarter of the
+        // budget goes to ghosts, larger boundary levels read the rest from HBM
+        const int table = ((sched_ok ? sched.max_levels : 0) + 1) * 8;
+        const int total = tuning.lds_bytes == 0 ? 65536 : std::min(std::abs(tuning.lds_bytes), 65536);
+        sh.gcap = std::min(sched_ok ? sched.max_ghosts : 0, std::max(1, total / 4 / (2 * bpb * 8)));
+        const int ghosts = 2 * sh.gcap * bpb * 8;
+        if (table + ghosts > 65536 - 8 * bpb)
+            throw Error(NBTE_ERR_INVALID_ARG, "sweep level tables do not fit in LDS; use fewer bands per block");
+        const int budget = (tuning.lds_bytes == 0 ? 65536 : std::min(tuning.lds_bytes, 65536)) - table - ghosts;
+        sh.slots = tuning.lds_bytes < 0 ? 0 : std::max(budget, 0) / (bpb * 8);
         return sh;
     }
     // The correction only has to capture the smooth error modes: 20 Jacobi-CG
-    // iterations leave the outer iteration count unchanged on every workload.
-    int cg_max_iter() const { return tuning.cg_max_iter > 0 ? tuning.cg_max_iter : 20; }
+    // iterations leave the outer iteration count unchanged on every workload,
+    // eight cost at most a few percent more outer iterations.
+    int cg_max_iter() const { return tuning.cg_max_iter > 0 ? tuning.cg_max_iter : 8; }
     double cg_rtol() const { return tuning.cg_rtol > 0 ? tuning.cg_rtol : 1e-3; }
 
     PcgWork pcg() const {
@@ -215,10 +259,13 @@ struct nbte_problem {
             slots_for_cap = -2;
         }
         shape = resolve_shape();
-        if (slots_for_cap != shape.slots) {
+        if (slots_for_cap != shape.slots || prog_B != bands.B || prog_gcap != shape.gcap) {
             if (shape.slots > 0) assign_slots(m, quad, sched, shape.slots);
             else sched.slot.clear(), sched.max_slots = 0, sched.spilled = 0;
             slots_for_cap = shape.slots;
+            prog = build_program(m, quad, sched, bands.B, shape.gcap);
+            prog_B = bands.B;
+            prog_gcap = shape.gcap;
             sched_up = false;
         }
         if (!plan_ok) {
@@ -238,6 +285,12 @@ struct nbte_problem {
 
     void upload_device() {
         require_gfx950();
+        if (!stream) {
+            // the null stream cannot be captured into a graph; a blocking
+            // stream still orders with the caller's null-stream work
+            NBTE_HIP(hipStreamCreate(&own_stream));
+            stream = own_stream;
+        }
         const Mesh &m = *mesh;
         if (!geom_ok) {
             std::vector<double> invV(m.N);
@@ -253,8 +306,16 @@ struct nbte_problem {
             upload(d_perm, sched.perm, stream);
             upload(d_lvl_ptr, sched.lvl_ptr, stream);
             upload(d_lvl_off, sched.lvl_off, stream);
-            if (shape.slots > 0) upload(d_slot, sched.slot, stream);
-            else d_slot.release();
+            upload(d_pcell, prog.cell, stream);
+            upload(d_pslot, prog.slot, stream);
+            upload(d_pref, prog.ref, stream);
+            upload(d_pcoef, prog.coef, stream);
+            upload(d_psout, prog.sout, stream);
+            d_pth.alloc(prog.cell.size() * sizeof(double));
+            d_pq.alloc(prog.cell.size() * sizeof(double));
+            upload(d_gptr, prog.gptr, stream);
+            upload(d_gsrc, prog.ghost_src, stream);
+            d_gval.alloc(std::max<size_t>(prog.ghost_src.size() * bands.B, 1) * sizeof(double));
             sched_up = true;
         }
         if (!plan_up) {
@@ -341,7 +402,8 @@ struct nbte_problem {
                                 &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_dirrhs, &d_g,
                                 &d_inflow, &d_Jw, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq,
                                 &d_thetaE, &d_q, &d_rhs, &d_delta, &d_maxbuf, &d_pcg_r, &d_pcg_z, &d_pcg_p,
-                                &d_pcg_Ap, &d_pcg_part, &d_pcg_scal, &d_slot})
+                                &d_pcg_Ap, &d_pcg_part, &d_pcg_scal, &d_pcell, &d_pslot, &d_pref, &d_pcoef,
+                                &d_psout, &d_pth, &d_pq, &d_gptr, &d_gsrc, &d_gval})
             s += (int64_t)b->bytes;
         return s;
     }
@@ -370,8 +432,11 @@ struct nbte_problem {
         const int slot = next_event_slot();
         record(slot, PH_BC);
         launch_bc_inflow(v, fp32, th_prev, stream);
+        launch_ghost_gather(v, stream);
         record(slot, PH_SWEEP);
-        launch_sweep(v, fp32, th, shape.bpb, shape.bpl, shape.block, std::max(sched.max_slots, 1), stream);
+        launch_gather(v, th, d_pth.as<double>(), stream);
+        launch_sweep(v, fp32, th, shape.bpb, shape.bpl, shape.block, std::max(sched.max_slots, 1), shape.gcap,
+                     shape.slots == 0 || sched.spilled > 0, stream);
         record(slot, PH_MOM);
         const bool syn = scheme != NBTE_SCHEME_SEQUENTIAL;
         if (syn) launch_wall_flux(v, fp32, th, stream);
@@ -432,6 +497,7 @@ struct nbte_problem {
             }
         }
         NBTE_HIP(hipMemcpyAsync(d_Q.ptr, Q.data(), m.N * 8, hipMemcpyHostToDevice, stream));
+        launch_gather(view(), d_Q.as<double>(), d_pq.as<double>(), stream);
         cur = 0; prev = 1; spare = 2;
         double *th0 = d_theta[0].as<double>();
         if (o.T_init) {
@@ -457,14 +523,48 @@ struct nbte_problem {
         iterations = 0;
         residual = INFINITY;
         events_used = 0;
+        drop_graphs();
         stats = nbte_stats{};
         prepared = true;
+    }
+
+    // rotation state 0..2 of (cur, prev, spare)
+    int rotation() const { return cur == 0 ? 0 : (cur == 2 ? 1 : 2); }
+
+    void run_graph_triple() {
+        const int r = rotation();
+        if (!graph_exec[r]) {
+            const int c0 = cur, p0 = prev, s0 = spare, it0 = iterations;
+            NBTE_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int k = 0; k < 3; ++k) one_iteration();
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            NBTE_HIP(hipStreamEndCapture(stream, &graph[r]));
+            NBTE_HIP(hipGraphInstantiate(&graph_exec[r], graph[r], nullptr, nullptr, 0));
+            cur = c0; prev = p0; spare = s0; iterations = it0;   // capture only recorded the work
+        }
+        NBTE_HIP(hipGraphLaunch(graph_exec[r], stream));
+        for (int k = 0; k < 3; ++k) {   // advance the rotation as the three iterations do
+            const int old_prev = prev;
+            prev = cur;
+            cur = spare;
+            spare = old_prev;
+        }
+        iterations += 3;
     }
 
     void iterate(int n, bool check, double *res_out) {
         if (!prepared) throw Error(NBTE_ERR_STATE, "nbte_prepare must precede nbte_iterate");
         auto t0 = std::chrono::steady_clock::now();
-        for (int k = 0; k < n; ++k) one_iteration();
+        int k = 0;
+        if (use_graphs && !tuning.no_graphs && !time_phases)
+            for (; k + 3 <= n; k += 3) run_graph_triple();
+        for (; k < n; ++k) one_iteration();
         if (check) {
             double r = read_residual();
             if (res_out) *res_out = r;
@@ -783,8 +883,8 @@ nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t) {
         if (t->bands_per_block < 0) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block must be >= 0");
         if (t->lds_bytes < -1 || t->lds_bytes > 65536) throw Error(NBTE_ERR_INVALID_ARG, "lds_bytes must be -1, 0 or <= 65536");
         const int bpl = t->bands_per_lane;
-        if (bpl != 0 && bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8 && bpl != 16)
-            throw Error(NBTE_ERR_INVALID_ARG, "bands_per_lane must be 0, 1, 2, 4, 8 or 16");
+        if (bpl != 0 && bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8)
+            throw Error(NBTE_ERR_INVALID_ARG, "bands_per_lane must be 0, 1, 2, 4 or 8");
         if (t->block_size != 0 && (t->block_size < 64 || t->block_size > 1024 || t->block_size % 64))
             throw Error(NBTE_ERR_INVALID_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
         if (t->cg_max_iter < 0 || !(t->cg_rtol >= 0)) throw Error(NBTE_ERR_INVALID_ARG, "bad CG settings");
@@ -807,9 +907,9 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
         if (!p || !bytes) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
         if (!p->have_bands || !p->have_quad) throw Error(NBTE_ERR_STATE, "bands and quadrature must be set");
         const Mesh &m = *p->mesh;
-        const int64_t N = m.N, F = m.F, D = p->quad.D, NBF = m.NBF, B = p->bands.B;
+        const int64_t N = m.N, F = m.F, D = p->quad.D, NBF = m.NBF;
         int64_t geo = N * F * (4 + 24) + N * 16 + NBF * 4;
-        int64_t sched = D * N * 4 + D * (N + 1) * 4;
+        int64_t sched = D * N * 4 + D * (N + 1) * 4 + D * N * (4 + 4 + 8 + 8 + 8 + (F - 1) * 12);
         int64_t plan = NBF * (4 + 8 + 8 + 8 + 4 * D + 8 * D);
         int64_t lh = N * (F + 1) * 12 + N * 8 * 7;
         *bytes = geo + sched + plan + lh + p->state_bytes(precision);

@@ -60,7 +60,8 @@ class Stats(ct.Structure):
 
 class Tuning(ct.Structure):
     _fields_ = [("bands_per_block", ct.c_int32), ("bands_per_lane", ct.c_int32), ("block_size", ct.c_int32),
-                ("lds_bytes", ct.c_int32), ("cg_max_iter", ct.c_int32), ("cg_rtol", ct.c_double)]
+                ("lds_bytes", ct.c_int32), ("cg_max_iter", ct.c_int32), ("cg_rtol", ct.c_double),
+                ("no_graphs", ct.c_int32)]
 
 
 # (name, restype, argtypes) of every exported symbol declared in include/nbte.h
@@ -316,9 +317,10 @@ def nbte_get_stats(p):
     return {k: getattr(s, k) for k, _ in Stats._fields_}
 
 
-def nbte_set_tuning(p, bands_per_block=0, bands_per_lane=0, block_size=0, lds_bytes=0, cg_max_iter=0, cg_rtol=0.0):
+def nbte_set_tuning(p, bands_per_block=0, bands_per_lane=0, block_size=0, lds_bytes=0, cg_max_iter=0, cg_rtol=0.0,
+                    no_graphs=0):
     t = Tuning(int(bands_per_block), int(bands_per_lane), int(block_size), int(lds_bytes), int(cg_max_iter),
-               float(cg_rtol))
+               float(cg_rtol), int(no_graphs))
     _check(_lib.nbte_set_tuning(p.handle, ct.byref(t)))
 
 
@@ -352,10 +354,16 @@ def build_problem(problem, stream=None):
 
 def solve(problem, precision=None, scheme=None, tol=1e-8, max_iter=10000, check_every=1, T_init=None,
           stream=None, allow_not_converged=False, tuning=None):
+    """tuning: None (library defaults), "auto" (autotuner cache, defaults if
+    the workload was never tuned) or a dict of nbte_set_tuning arguments."""
     mesh, p = build_problem(problem, stream)
+    precision = precision or problem.precision
+    if tuning == "auto":
+        from . import tune
+        tuning = tune.lookup(problem, precision)
     if tuning:
         nbte_set_tuning(p, **tuning)
-    opts = make_opts(scheme=scheme or problem.scheme, precision=precision or problem.precision,
+    opts = make_opts(scheme=scheme or problem.scheme, precision=precision,
                      T_ref=problem.T_ref, tol=tol, max_iter=max_iter, check_every=check_every, T_init=T_init)
     out = nbte_solve_steady(p, problem.Q, opts, allow_not_converged=allow_not_converged)
     out["_handles"] = (mesh, p)

@@ -1,0 +1,103 @@
+"""Autotuner of the sweep launch shape.
+
+For a problem it times candidate shapes (bands per workgroup, bands per lane,
+workgroup size, LDS budget) through the C ABI's HIP-event phase timers and
+keeps the fastest.  Results are cached in tune_cache.json next to this file,
+keyed by (cell type, cell-count bucket, bands, directions, precision), and
+looked up by nbte.solve(..., tuning="auto").
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import time
+
+from . import nbte as N
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def key(problem, precision):
+    bucket = int(round(math.log2(max(problem.n_cells, 1)) * 2))   # half-octave buckets
+    return f"{problem.cell_type}|{bucket}|B{problem.n_bands}|D{problem.n_dirs}|{precision}"
+
+
+def load_cache():
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(cache):
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def lookup(problem, precision):
+    return load_cache().get(key(problem, precision), {}).get("shape")
+
+
+def candidates(B):
+    bpbs = [b for b in (1, 2, 4, 8, 16, 32) if b <= B] + ([B] if B not in (1, 2, 4, 8, 16, 32) and B <= 64 else [])
+    out = []
+    for bpb, bpl, block in itertools.product(bpbs, (1, 2, 4), (128, 256, 512)):
+        if bpl > bpb or (bpb + bpl - 1) // bpl > 64:
+            continue
+        out.append({"bands_per_block": bpb, "bands_per_lane": bpl, "block_size": block, "lds_bytes": 0})
+    return out
+
+
+def time_shape(h, problem, precision, shape, iters=4):
+    N.nbte_set_tuning(h, **shape)
+    opts = N.make_opts(scheme="sequential", precision=precision, T_ref=problem.T_ref, time_phases=True,
+                       T_init=[problem.T_ref + 0.5] * problem.n_cells)
+    N.nbte_prepare(h, problem.Q, opts)
+    N.nbte_iterate(h, 1, check=True)          # warm-up (first-launch costs)
+    st0 = N.nbte_get_stats(h)
+    N.nbte_iterate(h, iters, check=True)
+    st = N.nbte_get_stats(h)
+    n = st["sweep_launches"] - st0["sweep_launches"]
+    return (st["ms_sweep"] - st0["ms_sweep"]) / max(n, 1)
+
+
+def tune(problem, precision="mixed", shapes=None, iters=4, verbose=True, write=True):
+    mesh, h = N.build_problem(problem)
+    table = []
+    t0 = time.time()
+    for shape in shapes or candidates(problem.n_bands):
+        try:
+            ms = time_shape(h, problem, precision, shape, iters)
+        except N.NbteError as e:
+            if verbose:
+                print(f"tune: {shape} rejected: {e}", flush=True)
+            continue
+        table.append((ms, shape))
+        if verbose:
+            ups = problem.updates_per_sweep / (ms * 1e-3)
+            print(f"tune: {problem.name} {precision} {shape} sweep {ms:.4f} ms ({ups:.3e} updates/s)", flush=True)
+    table.sort(key=lambda t: t[0])
+    best_ms, best = table[0]
+    if write:
+        cache = load_cache()
+        cache[key(problem, precision)] = {"shape": best, "sweep_ms": best_ms, "workload": problem.name,
+                                          "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S"),
+                                          "seconds": time.time() - t0}
+        save_cache(cache)
+    return best, best_ms, table
+
+
+if __name__ == "__main__":
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from workloads import configs as C
+    names = sys.argv[1:] or ["config2"]
+    for name in names:
+        p = {"config1": C.config1, "config2": C.config2, "config3": C.config3}[name]()
+        for prec in ("mixed", "fp64"):
+            best, ms, _ = tune(p, prec)
+            print(f"tune: BEST {name} {prec} {best} {ms:.4f} ms", flush=True)
