@@ -142,7 +142,9 @@ typedef struct {
     double T_ref;            /* K, reference of the deviational variables (default 300) */
     double tol;              /* stop when max|dT_L| / max|T_L - T_ref| <= tol (default 1e-8) */
     int32_t max_iter;        /* default 10000 */
-    int32_t check_every;     /* iterations between residual read-backs (default 1) */
+    int32_t check_every;     /* iterations between host polls of the device state (default 8);
+                                the stop test runs on the device after every iteration, so
+                                the result does not depend on it */
     const double *T_init;    /* nullable host array (n_cells): initial T_L; NULL = Fourier guess */
     int32_t outputs_on_device; /* 1: result arrays are device pointers */
     int32_t time_phases;     /* 1: record per-phase HIP-event times (see nbte_get_stats) */
@@ -170,11 +172,13 @@ nbte_status nbte_solve_steady(nbte_problem *p, const double *Q_cell, const nbte_
 
 /* Split form of nbte_solve_steady, for callers that drive the iteration:
  *   nbte_prepare  : setup (cached per geometry/tables) + initial guess;
- *   nbte_iterate  : n full iterations (boundary inflow, transport sweeps,
- *                   moments, temperature update), no host synchronisation
- *                   unless check is set, in which case *residual receives the
- *                   residual of the last iteration;
- *   nbte_read_result: write the current state into out. */
+ *   nbte_iterate  : exactly n full iterations (boundary inflow, transport
+ *                   sweeps, moments, temperature update; no stop test), no
+ *                   host synchronisation unless check is set, in which case
+ *                   *residual receives the residual of the last iteration
+ *                   (NBTE_ERR_DIVERGED if it is not finite);
+ *   nbte_read_result: write the current state into out (waits for the
+ *                   problem's work). */
 nbte_status nbte_prepare(nbte_problem *p, const double *Q_cell, const nbte_solve_opts *o);
 nbte_status nbte_iterate(nbte_problem *p, int32_t n, int32_t check, double *residual);
 nbte_status nbte_read_result(nbte_problem *p, nbte_result *out);
@@ -222,7 +226,8 @@ typedef struct {
     int32_t cg_max_iter;      /* diffusion-correction CG iterations per outer iteration (0 = auto) */
     double cg_rtol;           /* diffusion-correction CG relative tolerance (0 = auto) */
     int32_t no_graphs;        /* 1: launch every kernel eagerly instead of replaying HIP graphs
-                                 of three iterations (phase timing always runs eagerly) */
+                                 of one and of eight iterations (phase timing always runs
+                                 eagerly) */
 } nbte_tuning;
 nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t);
 nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t);
@@ -230,6 +235,55 @@ nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t);
 /* Device bytes a solve of this problem would hold at the given precision
  * (set_bands/set_quadrature must have been called). */
 nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int64_t *bytes);
+
+/* -------------------------------------------------------------- batches -- */
+
+/* A batch iterates many independent solves together: every kernel of an
+ * iteration is one launch over all running members (Methods, Eq. (14): the
+ * band x direction systems of all solves are independent tasks), replayed
+ * from HIP graphs.  Members are admitted and removed at any time (continuous
+ * batching); each member stops on the device when it reaches its own tol or
+ * max_iter, and its result is the one a stand-alone nbte_solve_steady with the
+ * same options and tuning computes (same kernels, same per-solve reduction
+ * order: bitwise equal).
+ *   hip_stream   stream of the batch's iterations (NULL: a stream of its own)
+ *   budget_bytes device memory the members may hold together, by
+ *                nbte_problem_footprint (0 = no limit) */
+nbte_status nbte_batch_create(void *hip_stream, int64_t budget_bytes, nbte_batch **out);
+/* Waits for the batch's work; members are released (not destroyed). */
+void nbte_batch_destroy(nbte_batch *b);
+
+/* Prepare p (as nbte_prepare, on p's own stream, so it overlaps the batch's
+ * work in flight) and add it to the batch; it starts iterating with the next
+ * nbte_batch_step and stops at o->tol or o->max_iter.  While it is a member,
+ * the stand-alone calls nbte_prepare / nbte_iterate / nbte_solve_steady /
+ * nbte_set_* on it fail with NBTE_ERR_STATE; nbte_read_result,
+ * nbte_get_distribution and nbte_get_stats work (they wait for the batch).
+ * Errors: NBTE_ERR_OUT_OF_MEMORY when the footprint exceeds what is left of
+ * the budget (nothing is allocated then), the errors of nbte_prepare. */
+nbte_status nbte_batch_admit(nbte_batch *b, nbte_problem *p, const double *Q_cell, const nbte_solve_opts *o);
+
+/* Enqueue n iterations of every running member (asynchronous). */
+nbte_status nbte_batch_step(nbte_batch *b, int32_t n);
+
+/* Wait for the batch's stream; report up to cap members that have stopped
+ * (converged, max_iter or diverged: see nbte_read_result) in done[0..*n_done)
+ * and the number still running in *n_running (both nullable). */
+nbte_status nbte_batch_poll(nbte_batch *b, nbte_problem **done, int32_t cap, int32_t *n_done,
+                            int32_t *n_running);
+
+/* Remove a member (stopped or not; waits for the batch's stream).  Its
+ * state and results stay on the device until it is prepared again or
+ * destroyed.  Destroying a member removes it first. */
+nbte_status nbte_batch_remove(nbte_batch *b, nbte_problem *p);
+
+typedef struct {
+    int32_t members;              /* problems in the batch */
+    int64_t budget_bytes;         /* as created */
+    int64_t bytes_in_use;         /* footprint of the members */
+    int64_t iterations_launched;  /* sum of the n of every nbte_batch_step */
+} nbte_batch_info;
+nbte_status nbte_batch_get_info(const nbte_batch *b, nbte_batch_info *info);
 
 /* --------------------------------------------------------------- errors -- */
 

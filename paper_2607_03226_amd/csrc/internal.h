@@ -126,9 +126,8 @@ void assign_slots(const Mesh &m, const Quadrature &q, Schedule &sc, int cap);
 // i*N + k for position k of direction i), so that the sweep kernel loads
 // everything it needs for a cell with independent, coalesced loads:
 //   cell, LDS slot of the cell's own value, up to maxin upwind references
-//   (>= 0: LDS slot; -1-bf: boundary inflow of face bf; <= -(NBF+2): the
-//   stored value of cell -ref-NBF-2), their coefficients |s.S|/V, and the
-//   outflow sum sum_{a>0} a.  Unused reference entries have coefficient 0.
+//   (ranges below), their coefficients |s.S|/V, and the outflow sum
+//   sum_{a>0} a.  Unused reference entries have coefficient 0.
 struct SweepProgram {
     int maxin = 0;
     std::vector<int32_t> cell, slot, ref;   // ref: maxin * D*N
@@ -140,12 +139,15 @@ struct SweepProgram {
     // -1 - (its rank among the ghosts of level l).
     std::vector<int32_t> gptr;
     std::vector<int64_t> ghost_src;
+    std::vector<int32_t> in_row;            // NBF*D: ghost row of incoming (bf, i), -1 otherwise
     int max_ghosts = 0;                     // most ghosts of one level
 };
 // record reference ranges (shared with the sweep kernel): >= 0 LDS slot;
 // [-kSpillBase, -1] ghost of the level kept in LDS, -1 - rank;
 // [-2 kSpillBase, -kSpillBase - 1] ghost read from HBM, -kSpillBase - 1 - row;
-// below: stored value of a cell, -(2 kSpillBase + 2) - cell
+// below: stored value of the upwind cell at stream position k of the same
+// direction, -(2 kSpillBase + 2) - k (its cell index and theta are read from
+// the streams, so a program does not depend on where theta lives)
 constexpr int32_t kSpillBase = 1 << 24;
 SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap);
 

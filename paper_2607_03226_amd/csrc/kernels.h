@@ -1,4 +1,11 @@
 // Device kernels of the transport path and their host-side launchers.
+//
+// Every per-iteration kernel serves a list of solves in one launch: it reads
+// the solve's descriptor (DeviceView, device memory) through a work table of
+// WorkItems, one per workgroup.  A single solve is a list of one.  The
+// iteration state of each solve (theta rotation, iteration count, residual,
+// stop flag) lives in device memory and is advanced by the kernels
+// themselves, so one captured launch sequence serves every iteration.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,87 +14,140 @@
 
 namespace nbte {
 
-// Everything the per-iteration kernels read, as raw device pointers.
+// Iteration state of one solve (device memory).
+struct SolveState {
+    int32_t rot;          // theta rotation 0..2 (cur = (3 - rot) % 3, prev = cur + 1, spare = cur + 2, mod 3)
+    int32_t iterations;   // iterations done
+    int32_t done;         // 0 running; NBTE_DONE_* once stopped (kernels then skip the solve)
+    int32_t stop;         // host: 1 = stop at tol / max_iter, 0 = run every launched iteration
+    int32_t max_iter;
+    int32_t pad;
+    double tol;           // residual tolerance
+    double residual;      // max|theta_new - theta| / max|theta_new| of the last iteration
+    unsigned long long maxbuf[2];   // running maxima of the update (ordered bit patterns)
+};
+enum { NBTE_DONE_CONVERGED = 1, NBTE_DONE_MAX_ITER = 2, NBTE_DONE_DIVERGED = 3 };
+
+// Jacobi-preconditioned conjugate gradients on a symmetric positive definite
+// CSR matrix (the synthetic correction); per-solve work arrays.
+struct PcgWork {
+    int64_t n;
+    int32_t nblk;         // workgroups of the multi-workgroup form
+    int32_t max_iter;
+    double rtol2;         // stop when r.z <= rtol2 * r0.z0
+    const int32_t *row_ptr, *col;
+    const double *val, *dinv;
+    double *r, *z, *p, *Ap;
+    double *partial;      // 3 * nblk: two r.z buffers, p.Ap
+    double *scal;         // [-, rz0, -, -, converged flag, iterations]
+};
+
+// Everything the kernels read and write of one solve, as raw device pointers.
 struct DeviceView {
     int64_t N;       // cells
     int32_t F;       // faces per cell
     int32_t B;       // bands
     int32_t D;       // directions
+    int32_t fp32;    // g stored in FP32 (else FP64)
     int64_t NBF;     // boundary faces
+    int32_t scheme;  // NBTE_SCHEME_*
+    int32_t mom_lpc; // lanes per cell of the reductions
     // mesh
     const int32_t *nbr;     // N*F
-    const double *S;        // N*F*3
-    const double *invV;     // N
-    // schedule
-    const int32_t *perm;    // D*N
-    const int32_t *lvl_ptr;
-    const int32_t *lvl_off; // D+1
+    const double *V;        // N
     // sweep program: level-ordered streams, index i*N + k (see SweepProgram)
     int32_t maxin;
     int32_t max_levels;     // deepest level count over the directions
-    int32_t max_ghosts;     // most boundary inflow values (per band) of one level
-    int64_t n_ghost;        // ghost rows over all directions
+    int32_t lpc;            // sweep lanes per cell
+    int32_t bpb;            // sweep bands per workgroup
+    int32_t gcap;           // ghosts per level kept in LDS
+    int32_t pad0;
+    const int32_t *lvl_ptr; // per direction L_i + 1 level offsets, concatenated
+    const int32_t *lvl_off; // D+1: start of direction i's entries in lvl_ptr
     const int32_t *gptr;    // ghost offsets per level (layout of lvl_ptr)
-    const int64_t *ghost_src;  // inflow row of each ghost
-    double *gval;           // ghost values in sweep order (n_ghost * B)
     const int32_t *p_cell, *p_slot, *p_ref;
     const double *p_coef, *p_sout;
     double *p_th;           // theta in level order, gathered every iteration
-    double *p_q;            // heat source in level order, gathered at prepare
-    const double *theta_cell;  // theta by cell (read only for values without an LDS slot)
+    const double *p_q;      // heat source in level order, gathered at prepare
     // bands: Cw = C/W, src = C/(C_tot W), v, inv_tau
     const double *Cw, *src, *vel, *inv_tau;
+    double beta, C_tot;     // sum C/tau, sum C
     // quadrature
     const double *dirs;     // D*3
     const double *w;        // D
+    const double *qbias;    // 3: q of a uniform unit equilibrium
     // boundary plan
     const int32_t *bf_owner, *bf_kind, *mirror;
+    const int32_t *in_row;  // NBF*D: ghost row of an incoming (face, direction), -1 otherwise
     const double *bf_thw, *bf_p, *sdotS, *win;
     // state
     void *g;                // D*N*B, FP32 or FP64: non-equilibrium part e - C theta/W
-    double *inflow;         // NBF*D*B
+    double *gval;           // n_ghost*B boundary inflow in sweep (ghost) order
     double *Jw;             // NBF: net flux through each boundary face
-    const double *Q;        // N
+    double *theta[3];       // deviational lattice temperature, rotated by state->rot
+    double *theta_seq, *thetaE, *q, *rhs, *delta;
+    SolveState *state;
+    PcgWork pcg;
 };
 
-// Launchers (all asynchronous on `st`).  `fp32` selects the storage type of g.
+// One workgroup's share of a launch: the solve (index into the descriptor
+// array) and two kernel-specific coordinates (sweep: direction and band
+// block; elementwise kernels: kind and local workgroup index).  solve < 0
+// marks padding.
+struct WorkItem {
+    int32_t solve, a, b, c;
+};
+
+// Launchers (all asynchronous on `st`; `vs` and `wk` are device arrays).
 void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
-void launch_bc_inflow(const DeviceView &v, bool fp32, const double *theta_base, hipStream_t st);
-// bands_per_block bands of one direction per workgroup, bands_per_lane per
-// lane; lds_slots = slots per direction the schedule was assigned for.
-// spill: some consumed values are read back from HBM (full fence per level)
-// gcap: ghosts per level kept in LDS (the rest are read from HBM)
-void launch_sweep(const DeviceView &v, bool fp32, const double *theta, int bands_per_block, int bands_per_lane,
-                  int block, int lds_slots, int gcap, bool spill, hipStream_t st);
-// ghost values of every direction in sweep order, from the boundary inflow
-void launch_ghost_gather(const DeviceView &v, hipStream_t st);
-// out[at] = in[p_cell[at]] for every stream position (theta or Q into level order)
-void launch_gather(const DeviceView &v, const double *in, double *out, hipStream_t st);
-void launch_wall_flux(const DeviceView &v, bool fp32, const double *theta, hipStream_t st);
-void launch_moments(const DeviceView &v, bool fp32, const double *theta, double beta, double C_tot,
-                    const double *V, const double *qbias, double *theta_seq, double *thetaE, double *q,
-                    double *rhs_dsa, hipStream_t st);
+
+// Work tables of the elementwise kernels: items (solve, kind, local block,
+// blocks of this (solve, kind)), 256 threads each.
+//   stage:   kind 0 = boundary inflow, one thread per (boundary face, band);
+//            kind 1 = theta gathered into sweep order, one per stream entry
+//   flux:    net flow through each boundary face, four faces per workgroup
+//   moments: band x direction reductions, mom_lpc lanes per cell
+//   update:  theta update and residual maxima (grid-stride over the cells)
+//   finish:  one thread per solve (a = solve); residual, stop test, rotation
+void launch_stage(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
+// after = 0: inside the iteration (theta[cur] is the sweep's temperature);
+// after = 1: once the iteration has rotated theta (theta[prev] is)
+void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int after, hipStream_t st);
+void launch_moments(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
+void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
+void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
+
+// One sweep launch over a work list (solve, direction, band block).  All
+// items share the kernel variant (storage type, fan-in bound maxin, bands per
+// lane, spill mode) and the workgroup size; lds_bytes is the largest LDS need
+// among their solves.
+void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool spill,
+                  int block, size_t lds_bytes, hipStream_t st);
+size_t sweep_lds_bytes(int max_levels, int gcap, int bpb, int slots);
+
+// PCG of the synthetic correction for a list of solves.
+//   mode 0: solve L delta = rhs (every iteration);
+//   mode 1: solve L theta[cur] = rhs (Fourier initial guess at prepare).
+// Block form: one 1024-thread workgroup runs the whole PCG of a solve (items
+// (solve, -, -, -)).  Multi-workgroup form: items (solve, -, local block,
+// nblk); max_iter is the largest PCG iteration count of the listed solves,
+// each solve stops at its own.
+void launch_pcg_block(const DeviceView *vs, const WorkItem *wk, int n, int mode, hipStream_t st);
+void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, const WorkItem *wk_one, int n_one, int mode,
+                      int max_iter, hipStream_t st);
+constexpr int64_t kPcgBlockMaxRows = 8192;   // larger systems use the multi-workgroup form
+
+// Iteration state: clear the stop flag and set the stop rule of a solve;
+// copy the states of a list of solves into out[0..n).
+void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, hipStream_t st);
+void launch_collect_states(const DeviceView *vs, int n, SolveState *out, hipStream_t st);
+
+// Single-solve helpers (outside the iteration).
 // out[k] = offset + scale * in[k]
 void launch_affine(int64_t n, const double *in, double scale, double offset, double *out, hipStream_t st);
-// theta_new = base + delta (delta may be null), residual maxima into maxbuf[0..1]
-// (as ordered uint64 bit patterns of non-negative doubles).
-void launch_update(int64_t N, const double *base, const double *delta, const double *theta_old,
-                   double *theta_new, unsigned long long *maxbuf, hipStream_t st);
-void launch_reset_max(unsigned long long *maxbuf, hipStream_t st);
-void launch_distribution(const DeviceView &v, bool fp32, const double *theta_base, int band, int dir,
-                         double *out, hipStream_t st);
-
-// Jacobi-preconditioned conjugate gradients on a symmetric positive definite
-// CSR matrix, fixed launch sequence (capturable), deterministic reductions.
-struct PcgWork {
-    int64_t n;
-    int nblk;
-    const int32_t *row_ptr, *col;
-    const double *val, *dinv;
-    double *r, *z, *p, *Ap;
-    double *partial;   // 2*nblk
-    double *scal;      // [rz, rz0, alpha, beta, converged, iters]
-};
-void launch_pcg(const PcgWork &w, const double *b, double *x, double rtol, int max_iter, hipStream_t st);
+// out[at] = in[p_cell[at]] over the D*N stream entries
+void launch_gather(int64_t n, const int32_t *idx, const double *in, double *out, hipStream_t st);
+// e(band, dir, c) of the last sweep of a solve
+void launch_distribution(const DeviceView *v, bool fp32, int band, int dir, double *out, int64_t N, hipStream_t st);
 
 }  // namespace nbte

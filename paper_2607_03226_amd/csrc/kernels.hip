@@ -7,6 +7,11 @@
 // one (direction, cell) are contiguous, so the lanes that share a cell read
 // and write one contiguous run.  Arithmetic is FP64 everywhere; g is stored in
 // FP64 or FP32.
+//
+// Every per-iteration kernel takes the descriptor array of the solves it
+// serves and a work table (one WorkItem per workgroup).  A solve whose state
+// says it has stopped is skipped by every kernel, so a captured launch
+// sequence can run past the convergence of some of its solves.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,12 +22,16 @@
 namespace nbte {
 namespace {
 
-constexpr int64_t kPcgBlockMaxRows = 4096;    // larger systems use the multi-workgroup PCG
-
 template <class T>
 __device__ __forceinline__ double ld(const T *p, int64_t k) {
     return static_cast<double>(p[k]);
 }
+
+// theta buffers of a solve under its rotation
+__device__ __forceinline__ int th_cur(const SolveState *s) { return (3 - s->rot) % 3; }
+__device__ __forceinline__ const double *theta_cur(const DeviceView &v) { return v.theta[th_cur(v.state)]; }
+__device__ __forceinline__ const double *theta_prev(const DeviceView &v) { return v.theta[(th_cur(v.state) + 1) % 3]; }
+__device__ __forceinline__ double *theta_spare(const DeviceView &v) { return v.theta[(th_cur(v.state) + 2) % 3]; }
 
 __device__ __forceinline__ double wave_sum(double x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
@@ -53,28 +62,34 @@ __global__ void k_fill_zero(uint32_t *p, size_t n) {
 }
 
 // --------------------------------------------------------------------------
-// boundary inflow (lagged): one thread per (boundary face, band)
+// stage: lagged boundary inflow (kind 0) and theta in sweep order (kind 1)
+//
+// Boundary inflow of an incoming (face f, direction i), from the previous
+// distribution of the owner cell (Methods, boundary conditions):
+//   thermalizing  C theta_w / W
+//   specular      e of the mirror direction
+//   diffuse       sum_out w (s.S) e / sum_in w |s.S|
+//   partial       p specular + (1 - p) diffuse
+// written straight into the ghost row the sweep reads it from.
 // --------------------------------------------------------------------------
 template <class T>
-__global__ void k_bc_inflow(DeviceView v, const double *theta_base) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= v.NBF * v.B) return;
+__device__ void bc_inflow(const DeviceView &v, int64_t t) {
     const int64_t bf = t / v.B;
-    const int lam = (int)(t % v.B);
+    const int lam = (int)(t - bf * v.B);
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
     const T *g = static_cast<const T *>(v.g);
     const double *sd = v.sdotS + bf * D;
-    double *out = v.inflow + bf * D * B;
+    const int32_t *row = v.in_row + bf * D;
     const double cw = v.Cw[lam];
     if (v.bf_kind[bf] == NBTE_BC_THERMALIZING) {
         const double val = cw * v.bf_thw[bf];
         for (int i = 0; i < D; ++i)
-            if (sd[i] < 0.0) out[i * B + lam] = val;
+            if (row[i] >= 0) v.gval[(int64_t)row[i] * B + lam] = val;
         return;
     }
-    const double eq = cw * theta_base[c];
+    const double eq = cw * theta_prev(v)[c];
     const double p = v.bf_p[bf];
     double diff = 0.0;
     if (p < 1.0) {
@@ -84,10 +99,27 @@ __global__ void k_bc_inflow(DeviceView v, const double *theta_base) {
     }
     const int32_t *mir = v.mirror + bf * D;
     for (int i = 0; i < D; ++i) {
-        if (!(sd[i] < 0.0)) continue;
+        if (row[i] < 0) continue;
         double val = (1.0 - p) * diff;
         if (p > 0.0) val += p * (ld(g, ((int64_t)mir[i] * N + c) * B + lam) + eq);
-        out[i * B + lam] = val;
+        v.gval[(int64_t)row[i] * B + lam] = val;
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    const int64_t stride = (int64_t)it.c * blockDim.x;
+    const int64_t t0 = (int64_t)it.b * blockDim.x + threadIdx.x;
+    if (it.a == 0) {
+        const int64_t n = v.NBF * v.B;
+        for (int64_t t = t0; t < n; t += stride) bc_inflow<T>(v, t);
+    } else {
+        const int64_t n = (int64_t)v.D * v.N;
+        const double *th = theta_cur(v);
+        for (int64_t t = t0; t < n; t += stride) v.p_th[t] = th[v.p_cell[t]];
     }
 }
 
@@ -105,10 +137,10 @@ __global__ void k_bc_inflow(DeviceView v, const double *theta_base) {
 // from its stored copy.  A workgroup barrier separates levels; it orders the
 // LDS and HBM writes of level k before the reads of level k+1.
 //
-// Workgroup -> (direction, band block): with xcd_map the band blocks of one
-// direction get consecutive dispatch slots on the same XCD (dispatch goes
-// round-robin over the 8 XCDs), so they share that direction's streams in
-// one L2.
+// Workgroup -> (solve, direction, band block) through the work table; the
+// host orders it so that the band blocks of one direction land on the same
+// XCD (dispatch goes round-robin over the 8 XCDs) and share that direction's
+// streams in one L2.
 // --------------------------------------------------------------------------
 // Dynamic LDS of the sweep.  It is indexed with integer offsets (never through
 // pointers passed around), so every access stays in the LDS address space.
@@ -160,7 +192,7 @@ struct BandConst {
 
 template <class T, int MI, int BPL>
 __device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceView &v, const BandConst<BPL> &bc,
-                                           T *gi, int ring_off, int gbuf_off, int gcap, int g0, int bands_per_block,
+                                           T *gi, int64_t base, int ring_off, int gbuf_off, int bands_per_block,
                                            int b0, int lane, int nb_here) {
     const int B = v.B;
 #pragma unroll
@@ -183,8 +215,11 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceVi
             } else if (rf >= -2 * kSpill) {
                 up = v.gval[(int64_t)(-kSpill - 1 - rf) * B + lam];   // ghost beyond the LDS capacity
             } else {
-                const int n = -(2 * kSpill + 2) - rf;
-                up = ld(gi, (int64_t)n * B + lam) + cw * v.theta_cell[n];
+                // value without an LDS slot: its stored copy, located through
+                // the neighbour's position in this direction's streams
+                const int64_t at = base + (-(2 * kSpill + 2) - rf);
+                const int n = v.p_cell[at];
+                up = ld(gi, (int64_t)n * B + lam) + cw * v.p_th[at];
             }
             gain += r.cf[j] * up;
         }
@@ -223,22 +258,20 @@ __device__ __forceinline__ void level_barrier() {
 // its loads are in flight (moving it would force the wait).
 // --------------------------------------------------------------------------
 template <class T, int MI, int BPL, bool SPILL>
-__global__ void __launch_bounds__(512) k_sweep(DeviceView v, int lpc, int bands_per_block, int nbb, int xcd_map,
-                                                int gcap) {
+__global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs,
+                                                const WorkItem *__restrict__ wk) {
     // dynamic LDS: [lvl_ptr | gptr of this direction: 2 (max_levels + 1) ints]
     //              [ghost buffers: 2 x gcap x bands_per_block doubles]
     //              [ring: slot x bands_per_block doubles]
-    const int L = blockIdx.x;
-    int i, bblk;
-    if (xcd_map) {
-        const int x = L & 7, r = L >> 3;
-        bblk = r % nbb;
-        i = (r / nbb) * 8 + x;
-    } else {
-        i = L / nbb;
-        bblk = L % nbb;
-    }
-    const int b0 = bblk * bands_per_block;
+    const WorkItem tk = wk[blockIdx.x];
+    if (tk.solve < 0) return;   // padding of the XCD-ordered work list
+    const DeviceView &v = vs[tk.solve];
+    if (v.state->done) return;
+    const int lpc = v.lpc;
+    const int bands_per_block = v.bpb;
+    const int gcap = v.gcap;
+    const int i = tk.a;
+    const int b0 = tk.b * bands_per_block;
     const int slot = threadIdx.x / lpc;
     const int lane = threadIdx.x % lpc;
     const int nslots = blockDim.x / lpc;
@@ -321,14 +354,13 @@ __global__ void __launch_bounds__(512) k_sweep(DeviceView v, int lpc, int bands_
 #pragma unroll
         for (int p = 0; p < kItemsPerThread; ++p)
             if (cur[p].ok)
-                sweep_cell<T, MI, BPL>(cur[p], v, bc, gi, ring_off, gcur, gcap, gp(l), bands_per_block, b0, lane,
-                                       nb_here);
+                sweep_cell<T, MI, BPL>(cur[p], v, bc, gi, base, ring_off, gcur, bands_per_block, b0, lane, nb_here);
         // cells beyond kItemsPerThread per slot in a very wide level: no prefetch
 #pragma nounroll
         for (int k = lp(l) + slot + kItemsPerThread * nslots; k < lp(l + 1); k += nslots) {
             SweepRec<MI> rx;
             load_rec(rx, v, base, DN, k, lp(l + 1));
-            sweep_cell<T, MI, BPL>(rx, v, bc, gi, ring_off, gcur, gcap, gp(l), bands_per_block, b0, lane, nb_here);
+            sweep_cell<T, MI, BPL>(rx, v, bc, gi, base, ring_off, gcur, bands_per_block, b0, lane, nb_here);
         }
         ghost_store(l + 1);
         level_barrier<SPILL>();
@@ -350,60 +382,55 @@ __global__ void __launch_bounds__(512) k_sweep(DeviceView v, int lpc, int bands_
 #undef lp
 #undef gp
 
-__global__ void k_gather(int64_t n, const int32_t *idx, const double *in, double *out) {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k < n) out[k] = in[idx[k]];
-}
-
-// ghost values in sweep order: gval[g*B + l] = inflow[ghost_src[g] + l]
-__global__ void k_ghost_gather(int64_t n_ghost, int B, const int64_t *src, const double *inflow, double *gval) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n_ghost * B) return;
-    const int64_t g = t / B;
-    gval[t] = inflow[src[g] + (t - g * B)];
-}
-
 // --------------------------------------------------------------------------
-// net heat flow through each boundary face: one 64-lane block per face
-//   J_f = sum_l v_l sum_i w_i (s_i . S_f) e_up
+// net heat flow through each boundary face: one wave per face
+//   J_f = sum_l v_l sum_i w_i (s_i . S_f) e
+// with e the owner's value for outgoing and the inflow for incoming directions
 // --------------------------------------------------------------------------
 template <class T>
-__global__ void k_wall_flux(DeviceView v, const double *theta) {
-    const int64_t bf = blockIdx.x;
+__global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                              int after) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (!after && v.state->done) return;
+    const int64_t bf = (int64_t)it.b * 4 + (threadIdx.x >> 6);
     if (bf >= v.NBF) return;
+    const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
+    const double th = (after ? theta_prev(v) : theta_cur(v))[c];
     const T *g = static_cast<const T *>(v.g);
     double acc = 0.0;
-    for (int t = threadIdx.x; t < D * B; t += 64) {
-        const int i = t / B, lam = t % B;
+    for (int t = lane; t < D * B; t += 64) {
+        const int i = t / B, lam = t - i * B;
         const double sd = v.sdotS[bf * D + i];
-        if (sd == 0.0) continue;
+        const int32_t row = v.in_row[bf * D + i];
         double e;
-        if (sd > 0.0)
-            e = ld(g, ((int64_t)i * N + c) * B + lam) + v.Cw[lam] * theta[c];
-        else
-            e = v.inflow[(bf * D + i) * B + lam];
+        if (row >= 0) e = v.gval[(int64_t)row * B + lam];
+        else if (sd > 0.0) e = ld(g, ((int64_t)i * N + c) * B + lam) + v.Cw[lam] * th;
+        else continue;
         acc += v.vel[lam] * v.w[i] * sd * e;
     }
     acc = wave_sum(acc);
-    if (threadIdx.x == 0) v.Jw[bf] = acc;
+    if (lane == 0) v.Jw[bf] = acc;
 }
 
 // --------------------------------------------------------------------------
 // band x direction reductions (Methods, Eqs. (5), (7); T = energy temperature)
-// lpc lanes per cell, FP64 accumulation, shuffle reduction over the lanes.
-// Optionally the V-weighted right-hand side of the synthetic correction:
+// mom_lpc lanes per cell, FP64 accumulation, shuffle reduction over the lanes.
+// Synthetic schemes also get the V-weighted right-hand side of the correction:
 //   V (Qdot - D_h' q) = V beta (theta_seq - theta) + sum_{reflective f} J_f
 // (collision-divergence identity; reflective walls carry zero net flux at the
 // fixed point, so their transient flux is returned to the cell).
 // --------------------------------------------------------------------------
 template <class T>
-__global__ void k_moments(DeviceView v, const double *theta, double beta, double C_tot, const double *V,
-                          const double *qbias, double *theta_seq, double *thetaE, double *q, double *rhs_dsa,
-                          int lpc) {
-    const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / lpc;
+__global__ void __launch_bounds__(256) k_moments(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    const int lpc = v.mom_lpc;
+    const int64_t c = ((int64_t)it.b * blockDim.x + threadIdx.x) / lpc;
     const int lane = threadIdx.x % lpc;
     const int64_t N = v.N;
     const int B = v.B, D = v.D;
@@ -435,19 +462,19 @@ __global__ void k_moments(DeviceView v, const double *theta, double beta, double
         qz += __shfl_xor(qz, off);
     }
     if (c < N && lane == 0) {
-        const double th = theta[c];
-        theta_seq[c] = th + a_tau / beta;
-        thetaE[c] = th + a_w / C_tot;
-        q[3 * c] = qx + th * qbias[0];
-        q[3 * c + 1] = qy + th * qbias[1];
-        q[3 * c + 2] = qz + th * qbias[2];
-        if (rhs_dsa) {
-            double r = V[c] * a_tau;
+        const double th = theta_cur(v)[c];
+        v.theta_seq[c] = th + a_tau / v.beta;
+        v.thetaE[c] = th + a_w / v.C_tot;
+        v.q[3 * c] = qx + th * v.qbias[0];
+        v.q[3 * c + 1] = qy + th * v.qbias[1];
+        v.q[3 * c + 2] = qz + th * v.qbias[2];
+        if (v.scheme != NBTE_SCHEME_SEQUENTIAL) {
+            double r = v.V[c] * a_tau;
             for (int f = 0; f < v.F; ++f) {
                 const int n = v.nbr[c * v.F + f];
                 if (n < 0 && v.bf_kind[-n - 1] != NBTE_BC_THERMALIZING) r += v.Jw[-n - 1];
             }
-            rhs_dsa[c] = r;
+            v.rhs[c] = r;
         }
     }
 }
@@ -456,13 +483,22 @@ __device__ __forceinline__ unsigned long long dbits(double x) {
     return static_cast<unsigned long long>(__double_as_longlong(x));
 }
 
-__global__ void k_update(int64_t N, const double *base, const double *delta, const double *theta_old,
-                         double *theta_new, unsigned long long *maxbuf) {
+// theta_new = base + delta: sequential base = theta_seq (Eq. (5)); synthetic
+// base = theta_seq + correction (Eq. (12)); the literal variant adds the
+// correction to the previous theta.  Residual maxima into the solve's state.
+__global__ void __launch_bounds__(256) k_update(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    const double *th = theta_cur(v);
+    double *tn_out = theta_spare(v);
+    const double *base = v.scheme == NBTE_SCHEME_SYNTHETIC_LITERAL ? th : v.theta_seq;
+    const double *delta = v.scheme == NBTE_SCHEME_SEQUENTIAL ? nullptr : v.delta;
     double md = 0.0, mt = 0.0;
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t c = (int64_t)it.b * blockDim.x + threadIdx.x; c < v.N; c += (int64_t)it.c * blockDim.x) {
         const double tn = base[c] + (delta ? delta[c] : 0.0);
-        theta_new[c] = tn;
-        const double d = fabs(tn - theta_old[c]);
+        tn_out[c] = tn;
+        const double d = fabs(tn - th[c]);
         if (!(d <= 1e300)) md = INFINITY;   // NaN or overflow: report as divergence
         else md = fmax(md, d);
         mt = fmax(mt, fabs(tn));
@@ -472,13 +508,42 @@ __global__ void k_update(int64_t N, const double *base, const double *delta, con
         mt = fmax(mt, __shfl_xor(mt, off));
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&maxbuf[0], dbits(md));
-        atomicMax(&maxbuf[1], dbits(mt));
+        atomicMax(&v.state->maxbuf[0], dbits(md));
+        atomicMax(&v.state->maxbuf[1], dbits(mt));
     }
 }
 
-__global__ void k_reset_max(unsigned long long *maxbuf) {
-    if (threadIdx.x < 2) maxbuf[threadIdx.x] = 0ull;
+// End of an iteration: residual, stop test, theta rotation (one thread per solve).
+__global__ void k_finish(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    SolveState *s = vs[wk[k].solve].state;
+    if (s->done) return;
+    const double md = __longlong_as_double((long long)s->maxbuf[0]);
+    const double mt = __longlong_as_double((long long)s->maxbuf[1]);
+    const double res = mt > 0.0 ? md / mt : 0.0;
+    s->residual = res;
+    s->maxbuf[0] = 0ull;
+    s->maxbuf[1] = 0ull;
+    s->iterations += 1;
+    s->rot = (s->rot + 1) % 3;
+    if (!(res <= 1e300)) s->done = NBTE_DONE_DIVERGED;
+    else if (s->stop && res <= s->tol) s->done = NBTE_DONE_CONVERGED;
+    else if (s->stop && s->iterations >= s->max_iter) s->done = NBTE_DONE_MAX_ITER;
+}
+
+__global__ void k_set_controls(SolveState *s, int stop, double tol, int max_iter) {
+    if (threadIdx.x == 0) {
+        s->done = 0;
+        s->stop = stop;
+        s->tol = tol;
+        s->max_iter = max_iter;
+    }
+}
+
+__global__ void k_collect_states(const DeviceView *__restrict__ vs, int n, SolveState *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = *vs[k].state;
 }
 
 __global__ void k_affine(int64_t n, const double *in, double scale, double offset, double *out) {
@@ -486,119 +551,46 @@ __global__ void k_affine(int64_t n, const double *in, double scale, double offse
     if (k < n) out[k] = offset + scale * in[k];
 }
 
+__global__ void k_gather(int64_t n, const int32_t *idx, const double *in, double *out) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) out[k] = in[idx[k]];
+}
+
+// e of the last sweep: stored g relative to the theta that sweep used (prev)
 template <class T>
-__global__ void k_distribution(DeviceView v, const double *theta_base, int band, int dir, double *out) {
+__global__ void k_distribution(const DeviceView *__restrict__ vp, int band, int dir, double *out) {
+    const DeviceView &v = *vp;
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= v.N) return;
     const T *g = static_cast<const T *>(v.g);
-    out[c] = ld(g, ((int64_t)dir * v.N + c) * v.B + band) + v.Cw[band] * theta_base[c];
+    out[c] = ld(g, ((int64_t)dir * v.N + c) * v.B + band) + v.Cw[band] * theta_prev(v)[c];
 }
 
 // --------------------------------------------------------------------------
-// Jacobi PCG: two launches per iteration, every block re-sums the per-block
-// partials in the same order, so all blocks see identical scalars and the
-// result is bitwise reproducible.
+// Jacobi PCG of the synthetic correction (symmetric positive definite L).
+// mode 0: L delta = rhs inside the iteration; mode 1: L theta[cur] = rhs
+// (initial guess).  rtol2_o / max_o >= 0 override the solve's settings.
 // --------------------------------------------------------------------------
-// The converged flag is read once per block and broadcast through LDS, so
-// every thread of a block takes the same early exit (a block-uniform return
-// before any barrier).
-__device__ bool block_flag_set(const double *flag, double *lds) {
-    __syncthreads();
-    if (threadIdx.x == 0) lds[15] = *flag;
-    __syncthreads();
-    const bool set = lds[15] != 0.0;
-    __syncthreads();
-    return set;
-}
-
-__device__ double sum_partials(const double *p, int n, double *lds) {
-    double x = (threadIdx.x < (unsigned)n) ? p[threadIdx.x] : 0.0;
-    return block_sum(x, lds);
-}
-
-__global__ void k_pcg_init(PcgWork w, const double *b, double *x, double *prz) {
-    __shared__ double lds[16];
-    double acc = 0.0;
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < w.n; r += (int64_t)gridDim.x * blockDim.x) {
-        const double bi = b[r];
-        x[r] = 0.0;
-        w.r[r] = bi;
-        const double zi = w.dinv[r] * bi;
-        w.z[r] = zi;
-        acc += bi * zi;
-    }
-    acc = block_sum(acc, lds);
-    if (threadIdx.x == 0) prz[blockIdx.x] = acc;
-}
-
-__global__ void k_pcg_rz0(PcgWork w, const double *prz) {
-    __shared__ double lds[16];
-    const double rz0 = sum_partials(prz, w.nblk, lds);
-    if (threadIdx.x == 0) {
-        w.scal[1] = rz0;
-        w.scal[4] = 0.0;   // converged flag, sticky once set
-        w.scal[5] = 0.0;
-    }
-}
-
-// iteration k, part 1: beta, p = z + beta p, Ap = A z + beta Ap, partial p.Ap
-__global__ void k_pcg_dir(PcgWork w, const double *prz_new, const double *prz_old, double *ppap, int k,
-                          double rtol2) {
-    __shared__ double lds[16];
-    if (block_flag_set(&w.scal[4], lds)) return;
-    const double rz = sum_partials(prz_new, w.nblk, lds);
-    const double rz0 = w.scal[1];
-    if (!(rz > rtol2 * rz0)) {   // converged (or zero right-hand side)
-        if (blockIdx.x == 0 && threadIdx.x == 0) w.scal[4] = 1.0;
-        return;
-    }
-    const double beta = (k == 0) ? 0.0 : rz / sum_partials(prz_old, w.nblk, lds);
-    double acc = 0.0;
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < w.n; r += (int64_t)gridDim.x * blockDim.x) {
-        double az = 0.0;
-        for (int32_t kk = w.row_ptr[r]; kk < w.row_ptr[r + 1]; ++kk) az += w.val[kk] * w.z[w.col[kk]];
-        const double pn = (k == 0) ? w.z[r] : w.z[r] + beta * w.p[r];
-        const double apn = (k == 0) ? az : az + beta * w.Ap[r];
-        w.p[r] = pn;
-        w.Ap[r] = apn;
-        acc += pn * apn;
-    }
-    acc = block_sum(acc, lds);
-    if (threadIdx.x == 0) ppap[blockIdx.x] = acc;
-}
-
-// iteration k, part 2: alpha, x += alpha p, r -= alpha Ap, z = M^-1 r, partial r.z
-__global__ void k_pcg_step(PcgWork w, const double *prz_new, const double *ppap, double *prz_next, double *x,
-                           int k, double rtol2) {
-    __shared__ double lds[16];
-    if (block_flag_set(&w.scal[4], lds)) return;
-    const double rz = sum_partials(prz_new, w.nblk, lds);
-    const double rz0 = w.scal[1];
-    if (!(rz > rtol2 * rz0)) return;
-    const double alpha = rz / sum_partials(ppap, w.nblk, lds);
-    double acc = 0.0;
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < w.n; r += (int64_t)gridDim.x * blockDim.x) {
-        x[r] += alpha * w.p[r];
-        const double rn = w.r[r] - alpha * w.Ap[r];
-        w.r[r] = rn;
-        const double zn = w.dinv[r] * rn;
-        w.z[r] = zn;
-        acc += rn * zn;
-    }
-    acc = block_sum(acc, lds);
-    if (threadIdx.x == 0) {
-        prz_next[blockIdx.x] = acc;
-        if (blockIdx.x == 0) w.scal[5] = k + 1;
-    }
+__device__ __forceinline__ bool pcg_skip(const DeviceView &v, int mode) { return mode == 0 && v.state->done; }
+__device__ __forceinline__ double *pcg_x(const DeviceView &v, int mode) {
+    return mode == 0 ? v.delta : v.theta[th_cur(v.state)];
 }
 
 // Whole PCG in one workgroup (small systems): no launch per iteration, the
 // reductions are workgroup reductions in a fixed order (deterministic).
 // Every thread owns rows tid, tid + blockDim, ...; only the SpMV reads other
 // threads' entries of p, and p is complete at the barrier before it.
-__global__ void __launch_bounds__(1024) k_pcg_block(PcgWork w, const double *b, double *x, double rtol2,
-                                                    int max_iter) {
+__global__ void __launch_bounds__(1024) k_pcg_block(const DeviceView *__restrict__ vs,
+                                                    const WorkItem *__restrict__ wk, int mode, double rtol2_o,
+                                                    int max_o) {
     __shared__ double lds[16];
+    const DeviceView &v = vs[wk[blockIdx.x].solve];
+    if (pcg_skip(v, mode)) return;
+    const PcgWork &w = v.pcg;
+    const double *b = v.rhs;
+    double *x = pcg_x(v, mode);
+    const double rtol2 = rtol2_o >= 0 ? rtol2_o : w.rtol2;
+    const int max_iter = max_o >= 0 ? max_o : w.max_iter;
     const int64_t n = w.n;
     const int nt = blockDim.x;
     double acc = 0.0;
@@ -647,49 +639,159 @@ __global__ void __launch_bounds__(1024) k_pcg_block(PcgWork w, const double *b, 
     }
 }
 
+// Multi-workgroup form: two launches per PCG iteration; every workgroup of a
+// solve re-sums that solve's per-workgroup partials in the same order, so all
+// see identical scalars and the result is bitwise reproducible.
+// The converged flag is read once per workgroup and broadcast through LDS, so
+// every thread takes the same early exit (a uniform return before any barrier).
+__device__ bool block_flag_set(const double *flag, double *lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) lds[15] = *flag;
+    __syncthreads();
+    const bool set = lds[15] != 0.0;
+    __syncthreads();
+    return set;
+}
+
+__device__ double sum_partials(const double *p, int n, double *lds) {
+    double x = (threadIdx.x < (unsigned)n) ? p[threadIdx.x] : 0.0;
+    return block_sum(x, lds);
+}
+
+__global__ void __launch_bounds__(256) k_pcg_init(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                                  int mode) {
+    __shared__ double lds[16];
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (pcg_skip(v, mode)) return;
+    const PcgWork &w = v.pcg;
+    const double *b = v.rhs;
+    double *x = pcg_x(v, mode);
+    double acc = 0.0;
+    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < w.n; r += (int64_t)w.nblk * blockDim.x) {
+        const double bi = b[r];
+        x[r] = 0.0;
+        w.r[r] = bi;
+        const double zi = w.dinv[r] * bi;
+        w.z[r] = zi;
+        acc += bi * zi;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) w.partial[it.b] = acc;
+}
+
+// one workgroup per solve
+__global__ void __launch_bounds__(256) k_pcg_rz0(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                                 int mode) {
+    __shared__ double lds[16];
+    const DeviceView &v = vs[wk[blockIdx.x].solve];
+    if (pcg_skip(v, mode)) return;
+    const PcgWork &w = v.pcg;
+    const double rz0 = sum_partials(w.partial, w.nblk, lds);
+    if (threadIdx.x == 0) {
+        w.scal[1] = rz0;
+        w.scal[4] = 0.0;   // converged flag, sticky once set
+        w.scal[5] = 0.0;
+    }
+}
+
+// iteration k, part 1: beta, p = z + beta p, Ap = A z + beta Ap, partial p.Ap
+__global__ void __launch_bounds__(256) k_pcg_dir(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                                 int mode, int k, double rtol2_o, int max_o) {
+    __shared__ double lds[16];
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (pcg_skip(v, mode)) return;
+    const PcgWork &w = v.pcg;
+    const int max_iter = max_o >= 0 ? max_o : w.max_iter;
+    if (k >= max_iter) return;
+    if (block_flag_set(&w.scal[4], lds)) return;
+    const double rtol2 = rtol2_o >= 0 ? rtol2_o : w.rtol2;
+    const double *prz_new = w.partial + (k & 1) * w.nblk;
+    const double *prz_old = w.partial + ((k + 1) & 1) * w.nblk;
+    double *ppap = w.partial + 2 * w.nblk;
+    const double rz = sum_partials(prz_new, w.nblk, lds);
+    const double rz0 = w.scal[1];
+    if (!(rz > rtol2 * rz0)) {   // converged (or zero right-hand side)
+        if (it.b == 0 && threadIdx.x == 0) w.scal[4] = 1.0;
+        return;
+    }
+    const double beta = (k == 0) ? 0.0 : rz / sum_partials(prz_old, w.nblk, lds);
+    double acc = 0.0;
+    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < w.n; r += (int64_t)w.nblk * blockDim.x) {
+        double az = 0.0;
+        for (int32_t kk = w.row_ptr[r]; kk < w.row_ptr[r + 1]; ++kk) az += w.val[kk] * w.z[w.col[kk]];
+        const double pn = (k == 0) ? w.z[r] : w.z[r] + beta * w.p[r];
+        const double apn = (k == 0) ? az : az + beta * w.Ap[r];
+        w.p[r] = pn;
+        w.Ap[r] = apn;
+        acc += pn * apn;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) ppap[it.b] = acc;
+}
+
+// iteration k, part 2: alpha, x += alpha p, r -= alpha Ap, z = M^-1 r, partial r.z
+__global__ void __launch_bounds__(256) k_pcg_step(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                                  int mode, int k, double rtol2_o, int max_o) {
+    __shared__ double lds[16];
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (pcg_skip(v, mode)) return;
+    const PcgWork &w = v.pcg;
+    const int max_iter = max_o >= 0 ? max_o : w.max_iter;
+    if (k >= max_iter) return;
+    if (block_flag_set(&w.scal[4], lds)) return;
+    const double rtol2 = rtol2_o >= 0 ? rtol2_o : w.rtol2;
+    const double *prz_new = w.partial + (k & 1) * w.nblk;
+    double *prz_next = w.partial + ((k + 1) & 1) * w.nblk;
+    const double *ppap = w.partial + 2 * w.nblk;
+    const double rz = sum_partials(prz_new, w.nblk, lds);
+    const double rz0 = w.scal[1];
+    if (!(rz > rtol2 * rz0)) return;
+    const double alpha = rz / sum_partials(ppap, w.nblk, lds);
+    double *x = pcg_x(v, mode);
+    double acc = 0.0;
+    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < w.n; r += (int64_t)w.nblk * blockDim.x) {
+        x[r] += alpha * w.p[r];
+        const double rn = w.r[r] - alpha * w.Ap[r];
+        w.r[r] = rn;
+        const double zn = w.dinv[r] * rn;
+        w.z[r] = zn;
+        acc += rn * zn;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        prz_next[it.b] = acc;
+        if (it.b == 0) w.scal[5] = k + 1;
+    }
+}
 
 template <class T, int MI, bool SPILL>
-void dispatch_sweep_bpl(const DeviceView &v, int bpb, int bpl, int lpc, int nbb, int block, size_t lds, int xcd_map,
-                        int gcap, hipStream_t st) {
-    dim3 grid(nbb * v.D);
+void dispatch_sweep_bpl(const DeviceView *vs, const WorkItem *wk, int n, int bpl, int block, size_t lds,
+                        hipStream_t st) {
+    dim3 grid(n);
     switch (bpl) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, SPILL>), grid, dim3(block), lds, st, v, lpc, bpb, nbb, xcd_map, gcap); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, SPILL>), grid, dim3(block), lds, st, v, lpc, bpb, nbb, xcd_map, gcap); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, MI, 4, SPILL>), grid, dim3(block), lds, st, v, lpc, bpb, nbb, xcd_map, gcap); break;
-        default: hipLaunchKernelGGL((k_sweep<T, MI, 8, SPILL>), grid, dim3(block), lds, st, v, lpc, bpb, nbb, xcd_map, gcap); break;
+        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, SPILL>), grid, dim3(block), lds, st, vs, wk); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, SPILL>), grid, dim3(block), lds, st, vs, wk); break;
+        case 4: hipLaunchKernelGGL((k_sweep<T, MI, 4, SPILL>), grid, dim3(block), lds, st, vs, wk); break;
+        default: hipLaunchKernelGGL((k_sweep<T, MI, 8, SPILL>), grid, dim3(block), lds, st, vs, wk); break;
     }
 }
 
 template <class T>
-void dispatch_sweep(const DeviceView &v, int bpb, int bpl, int block, int lds_slots, int gcap, bool spill,
-                    hipStream_t st) {
-    // the caller guarantees bpb <= 64 * bpl (at most 64 lanes per cell)
-    int lanes = (bpb + bpl - 1) / bpl;
-    int lpc = 1;
-    while (lpc < lanes) lpc <<= 1;
-    const int nbb = (v.B + bpb - 1) / bpb;
-    if (block % 64 != 0 || block < 64 || block > 512) block = 256;
-    if (block < lpc) block = lpc;
-    const size_t lds = (size_t)(v.max_levels + 1) * sizeof(double)                   // two int tables
-                     + (size_t)2 * gcap * bpb * sizeof(double)                        // ghost buffers
-                     + (size_t)std::max(lds_slots, 1) * bpb * sizeof(double);          // ring
-    const int xcd_map = (v.D % 8 == 0) ? 1 : 0;
-    const int mi = v.maxin <= 2 ? 2 : (v.maxin == 3 ? 3 : 5);
+void dispatch_sweep(const DeviceView *vs, const WorkItem *wk, int n, int maxin, int bpl, bool spill, int block,
+                    size_t lds, hipStream_t st) {
+    const int mi = maxin <= 2 ? 2 : (maxin == 3 ? 3 : 5);
     if (spill) {
-        if (mi == 2) dispatch_sweep_bpl<T, 2, true>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
-        else if (mi == 3) dispatch_sweep_bpl<T, 3, true>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
-        else dispatch_sweep_bpl<T, 5, true>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
+        if (mi == 2) dispatch_sweep_bpl<T, 2, true>(vs, wk, n, bpl, block, lds, st);
+        else if (mi == 3) dispatch_sweep_bpl<T, 3, true>(vs, wk, n, bpl, block, lds, st);
+        else dispatch_sweep_bpl<T, 5, true>(vs, wk, n, bpl, block, lds, st);
     } else {
-        if (mi == 2) dispatch_sweep_bpl<T, 2, false>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
-        else if (mi == 3) dispatch_sweep_bpl<T, 3, false>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
-        else dispatch_sweep_bpl<T, 5, false>(v, bpb, bpl, lpc, nbb, block, lds, xcd_map, gcap, st);
+        if (mi == 2) dispatch_sweep_bpl<T, 2, false>(vs, wk, n, bpl, block, lds, st);
+        else if (mi == 3) dispatch_sweep_bpl<T, 3, false>(vs, wk, n, bpl, block, lds, st);
+        else dispatch_sweep_bpl<T, 5, false>(vs, wk, n, bpl, block, lds, st);
     }
-}
-
-int lanes_for(int B) {
-    int lpc = 1;
-    while (lpc < B && lpc < 64) lpc <<= 1;
-    return lpc;
 }
 
 }  // namespace
@@ -701,65 +803,75 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_zero, dim3(grid), dim3(256), 0, st, static_cast<uint32_t *>(p), n);
 }
 
-void launch_bc_inflow(const DeviceView &v, bool fp32, const double *theta_base, hipStream_t st) {
-    const int64_t n = v.NBF * v.B;
-    if (n == 0) return;
-    dim3 grid((unsigned)((n + 255) / 256));
-    if (fp32) hipLaunchKernelGGL(k_bc_inflow<float>, grid, dim3(256), 0, st, v, theta_base);
-    else hipLaunchKernelGGL(k_bc_inflow<double>, grid, dim3(256), 0, st, v, theta_base);
+void launch_stage(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_stage<float>, dim3(n), dim3(256), 0, st, vs, wk);
+    else hipLaunchKernelGGL(k_stage<double>, dim3(n), dim3(256), 0, st, vs, wk);
 }
 
-void launch_sweep(const DeviceView &v, bool fp32, const double *theta, int bpb, int bpl, int block, int lds_slots,
-                  int gcap, bool spill, hipStream_t st) {
+void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int after, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_flux<float>, dim3(n), dim3(256), 0, st, vs, wk, after);
+    else hipLaunchKernelGGL(k_flux<double>, dim3(n), dim3(256), 0, st, vs, wk, after);
+}
+
+void launch_moments(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_moments<float>, dim3(n), dim3(256), 0, st, vs, wk);
+    else hipLaunchKernelGGL(k_moments<double>, dim3(n), dim3(256), 0, st, vs, wk);
+}
+
+void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_update, dim3(n), dim3(256), 0, st, vs, wk);
+}
+
+void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_finish, dim3((n + 63) / 64), dim3(64), 0, st, vs, wk, n);
+}
+
+size_t sweep_lds_bytes(int max_levels, int gcap, int bpb, int slots) {
+    return (size_t)(max_levels + 1) * sizeof(double)             // two int level tables
+           + (size_t)2 * gcap * bpb * sizeof(double)              // ghost buffers
+           + (size_t)std::max(slots, 1) * bpb * sizeof(double);   // staged values
+}
+
+void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool spill,
+                  int block, size_t lds_bytes, hipStream_t st) {
+    if (n <= 0) return;
     if (bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8) bpl = 1;
-    if (bpb < 1) bpb = 1;
-    DeviceView w = v;
-    w.theta_cell = theta;
-    if (fp32) dispatch_sweep<float>(w, bpb, bpl, block, lds_slots, gcap, spill, st);
-    else dispatch_sweep<double>(w, bpb, bpl, block, lds_slots, gcap, spill, st);
+    if (fp32) dispatch_sweep<float>(vs, wk, n, maxin, bpl, spill, block, lds_bytes, st);
+    else dispatch_sweep<double>(vs, wk, n, maxin, bpl, spill, block, lds_bytes, st);
 }
 
-void launch_ghost_gather(const DeviceView &v, hipStream_t st) {
-    const int64_t n = v.n_ghost * v.B;
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_ghost_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v.n_ghost, v.B,
-                       v.ghost_src, v.inflow, v.gval);
+void launch_pcg_block(const DeviceView *vs, const WorkItem *wk, int n, int mode, hipStream_t st) {
+    if (n <= 0) return;
+    const double rtol2_o = mode == 1 ? 1e-24 : -1.0;
+    const int max_o = mode == 1 ? 4000 : -1;
+    hipLaunchKernelGGL(k_pcg_block, dim3(n), dim3(1024), 0, st, vs, wk, mode, rtol2_o, max_o);
 }
 
-void launch_gather(const DeviceView &v, const double *in, double *out, hipStream_t st) {
-    const int64_t n = (int64_t)v.D * v.N;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v.p_cell, in, out);
+void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, const WorkItem *wk_one, int n_one, int mode,
+                      int max_iter, hipStream_t st) {
+    if (n <= 0) return;
+    const double rtol2_o = mode == 1 ? 1e-24 : -1.0;
+    const int max_o = mode == 1 ? max_iter : -1;
+    hipLaunchKernelGGL(k_pcg_init, dim3(n), dim3(256), 0, st, vs, wk, mode);
+    hipLaunchKernelGGL(k_pcg_rz0, dim3(n_one), dim3(256), 0, st, vs, wk_one, mode);
+    for (int k = 0; k < max_iter; ++k) {
+        hipLaunchKernelGGL(k_pcg_dir, dim3(n), dim3(256), 0, st, vs, wk, mode, k, rtol2_o, max_o);
+        hipLaunchKernelGGL(k_pcg_step, dim3(n), dim3(256), 0, st, vs, wk, mode, k, rtol2_o, max_o);
+    }
 }
 
-void launch_wall_flux(const DeviceView &v, bool fp32, const double *theta, hipStream_t st) {
-    if (v.NBF == 0) return;
-    if (fp32) hipLaunchKernelGGL(k_wall_flux<float>, dim3((unsigned)v.NBF), dim3(64), 0, st, v, theta);
-    else hipLaunchKernelGGL(k_wall_flux<double>, dim3((unsigned)v.NBF), dim3(64), 0, st, v, theta);
+void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_controls, dim3(1), dim3(64), 0, st, s, stop, tol, max_iter);
 }
 
-void launch_moments(const DeviceView &v, bool fp32, const double *theta, double beta, double C_tot,
-                    const double *V, const double *qbias, double *theta_seq, double *thetaE, double *q,
-                    double *rhs_dsa, hipStream_t st) {
-    const int lpc = lanes_for(v.B);
-    const int block = 256;
-    const int64_t threads = v.N * lpc;
-    dim3 grid((unsigned)((threads + block - 1) / block));
-    if (fp32)
-        hipLaunchKernelGGL(k_moments<float>, grid, dim3(block), 0, st, v, theta, beta, C_tot, V, qbias, theta_seq,
-                           thetaE, q, rhs_dsa, lpc);
-    else
-        hipLaunchKernelGGL(k_moments<double>, grid, dim3(block), 0, st, v, theta, beta, C_tot, V, qbias, theta_seq,
-                           thetaE, q, rhs_dsa, lpc);
-}
-
-void launch_update(int64_t N, const double *base, const double *delta, const double *theta_old, double *theta_new,
-                   unsigned long long *maxbuf, hipStream_t st) {
-    const int grid = (int)std::min<int64_t>((N + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_update, dim3(grid), dim3(256), 0, st, N, base, delta, theta_old, theta_new, maxbuf);
-}
-
-void launch_reset_max(unsigned long long *maxbuf, hipStream_t st) {
-    hipLaunchKernelGGL(k_reset_max, dim3(1), dim3(64), 0, st, maxbuf);
+void launch_collect_states(const DeviceView *vs, int n, SolveState *out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_collect_states, dim3((n + 63) / 64), dim3(64), 0, st, vs, n, out);
 }
 
 void launch_affine(int64_t n, const double *in, double scale, double offset, double *out, hipStream_t st) {
@@ -767,29 +879,15 @@ void launch_affine(int64_t n, const double *in, double scale, double offset, dou
     hipLaunchKernelGGL(k_affine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, in, scale, offset, out);
 }
 
-void launch_distribution(const DeviceView &v, bool fp32, const double *theta_base, int band, int dir, double *out,
-                         hipStream_t st) {
-    dim3 grid((unsigned)((v.N + 255) / 256));
-    if (fp32) hipLaunchKernelGGL(k_distribution<float>, grid, dim3(256), 0, st, v, theta_base, band, dir, out);
-    else hipLaunchKernelGGL(k_distribution<double>, grid, dim3(256), 0, st, v, theta_base, band, dir, out);
+void launch_gather(int64_t n, const int32_t *idx, const double *in, double *out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, idx, in, out);
 }
 
-void launch_pcg(const PcgWork &w, const double *b, double *x, double rtol, int max_iter, hipStream_t st) {
-    if (w.n <= kPcgBlockMaxRows) {
-        hipLaunchKernelGGL(k_pcg_block, dim3(1), dim3(1024), 0, st, w, b, x, rtol * rtol, max_iter);
-        return;
-    }
-    double *prz[2] = {w.partial, w.partial + w.nblk};
-    double *ppap = w.partial + 2 * w.nblk;
-    const double rtol2 = rtol * rtol;
-    hipLaunchKernelGGL(k_pcg_init, dim3(w.nblk), dim3(256), 0, st, w, b, x, prz[0]);
-    hipLaunchKernelGGL(k_pcg_rz0, dim3(1), dim3(256), 0, st, w, prz[0]);
-    for (int k = 0; k < max_iter; ++k) {
-        hipLaunchKernelGGL(k_pcg_dir, dim3(w.nblk), dim3(256), 0, st, w, prz[k & 1], prz[(k + 1) & 1], ppap, k,
-                           rtol2);
-        hipLaunchKernelGGL(k_pcg_step, dim3(w.nblk), dim3(256), 0, st, w, prz[k & 1], ppap, prz[(k + 1) & 1], x, k,
-                           rtol2);
-    }
+void launch_distribution(const DeviceView *v, bool fp32, int band, int dir, double *out, int64_t N, hipStream_t st) {
+    dim3 grid((unsigned)((N + 255) / 256));
+    if (fp32) hipLaunchKernelGGL(k_distribution<float>, grid, dim3(256), 0, st, v, band, dir, out);
+    else hipLaunchKernelGGL(k_distribution<double>, grid, dim3(256), 0, st, v, band, dir, out);
 }
 
 }  // namespace nbte

@@ -1,0 +1,192 @@
+// The problem handle (one steady solve: mesh, tables, device-resident
+// iterates) and the runner that iterates a list of prepared problems.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <chrono>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace nbte {
+
+enum Phase { PH_BC = 0, PH_SWEEP, PH_MOM, PH_SYN, PH_UPD, PH_END, PH_COUNT };
+
+void require_gfx950();
+
+// ABI error plumbing: the status plus the thread-local message
+nbte_status fail(nbte_status code, const std::string &msg);
+template <class F>
+nbte_status guarded(F &&f) {
+    try {
+        set_last_error("");
+        return f();
+    } catch (const Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(NBTE_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(NBTE_ERR_INVALID_ARG, e.what());
+    }
+}
+
+// Iterates a list of prepared problems together: every kernel of an
+// iteration is one launch over all of them (work tables built here), and the
+// launch sequence is replayed from HIP graphs of one and of kGraphIters
+// iterations.  The problems' device state decides which of them still run.
+class Runner {
+  public:
+    static constexpr int kGraphIters = 8;
+    explicit Runner(hipStream_t st) : stream_(st) {}
+    ~Runner();
+    Runner(const Runner &) = delete;
+    Runner &operator=(const Runner &) = delete;
+
+    // replace the member list; the plan is rebuilt by the next run
+    void set_members(const std::vector<nbte_problem *> &m);
+    const std::vector<nbte_problem *> &members() const { return members_; }
+    // enqueue n iterations of every member (asynchronous)
+    void run(int n);
+    // wait for the stream and copy every member's state into its host mirror
+    void collect();
+    // per-phase HIP-event timing (eager launches while on)
+    void set_timing(bool on) { timing_ = on; }
+    void set_graphs(bool on) {
+        if (graphs_ != on) drop_graphs();
+        graphs_ = on;
+    }
+    // add the event times of the iterations timed since the last call
+    void harvest_timing();
+    double phase_ms[PH_COUNT] = {0};
+    int timed_iterations = 0;
+    void reset_timing();
+
+  private:
+    struct Launch {
+        int kind;              // see the enum in runner.cpp
+        bool fp32 = false;
+        int off = 0, n = 0;    // work items [off, off + n)
+        int off1 = 0, n1 = 0;  // second table (PCG: one item per solve)
+        int maxin = 0, bpl = 1, block = 256, iters = 0;
+        bool spill = false;
+        size_t lds = 0;
+    };
+    void build();
+    void enqueue_iteration(int event_slot);
+    void drop_graphs();
+    void release_retired();
+
+    hipStream_t stream_;
+    std::vector<nbte_problem *> members_;
+    bool dirty_ = true;
+    bool timing_ = false;
+    bool graphs_ = true;
+    std::vector<Launch> seq_;
+    DevBuf d_views_, d_work_, d_states_;
+    std::vector<std::unique_ptr<DevBuf>> retired_;
+    std::vector<std::shared_ptr<void>> staging_;   // pinned upload sources of the plans
+    hipGraph_t graph_[2] = {nullptr, nullptr};
+    hipGraphExec_t exec_[2] = {nullptr, nullptr};
+    std::vector<std::array<hipEvent_t, PH_COUNT>> events_;
+    int events_used_ = 0;
+};
+
+}  // namespace nbte
+
+namespace nbte {
+// batch side of a member (batch.cpp)
+void batch_sync(nbte_batch *b);
+void batch_forget(nbte_batch *b, nbte_problem *p);
+}  // namespace nbte
+
+struct nbte_problem {
+    std::shared_ptr<nbte::Mesh> mesh;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;   // created when the caller passes the null stream
+    nbte::BandTable bands;
+    nbte::Quadrature quad;
+    std::vector<nbte_boundary> bcs;
+    bool have_bands = false, have_quad = false, have_bcs = false;
+    double T_ref = 300.0;
+
+    // cached setup (validity flags)
+    bool geom_ok = false, sched_ok = false, plan_ok = false, diff_ok = false, tables_ok = false;
+    bool sched_up = false, plan_up = false, diff_up = false;
+    nbte::Schedule sched;
+    nbte::SweepProgram prog;
+    nbte::BoundaryPlan plan;
+    nbte::DiffusionOperator diff;
+
+    // device buffers
+    nbte::DevBuf d_nbr, d_V;
+    nbte::DevBuf d_lvl_ptr, d_lvl_off, d_gptr, d_pcell, d_pslot, d_pref, d_pcoef, d_psout, d_pth, d_pq, d_inrow;
+    nbte::DevBuf d_Cw, d_src, d_vel, d_itau, d_dirs, d_w, d_qbias;
+    nbte::DevBuf d_bf_owner, d_bf_kind, d_mirror, d_bf_thw, d_bf_p, d_sdotS, d_win;
+    nbte::DevBuf d_Lrow, d_Lcol, d_Lval, d_Ldinv;
+    nbte::DevBuf d_g, d_gval, d_Jw, d_Q;
+    nbte::DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta;
+    nbte::DevBuf d_pcg_r, d_pcg_z, d_pcg_p, d_pcg_Ap, d_pcg_part, d_pcg_scal;
+    nbte::DevBuf d_view, d_state, d_self_work;
+    int pcg_nblk = 1;
+
+    // launch shape of the sweep
+    struct Shape {
+        int bpb = 1, bpl = 1, block = 256, slots = 0, gcap = 0;
+    } shape;
+    int slots_for_cap = -2;   // slot budget the current slot table was built for
+    int prog_B = -1, prog_gcap = -1;
+    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0};
+
+    // iteration state
+    bool prepared = false;
+    int precision = NBTE_PREC_FP64;
+    int scheme = NBTE_SCHEME_SYNTHETIC;
+    double heat_in = 0.0;
+    bool out_on_device = false;
+    int time_phases = 0;
+    nbte::DeviceView hv{};      // host copy of the descriptor in d_view
+    nbte::SolveState hs{};      // host mirror of the device state (after a collect)
+    int self_one = 0, self_pcg = 1, self_flux = 0, n_self_pcg = 0, n_self_flux = 0;   // offsets in d_self_work
+
+    nbte_batch *batch = nullptr;          // batch this problem is a member of
+    std::unique_ptr<nbte::Runner> solo;   // runner of stand-alone iterations
+    nbte_stats stats{};
+
+    ~nbte_problem();
+
+    Shape resolve_shape() const;
+    int cg_max_iter() const { return tuning.cg_max_iter > 0 ? tuning.cg_max_iter : 8; }
+    double cg_rtol() const { return tuning.cg_rtol > 0 ? tuning.cg_rtol : 1e-3; }
+    bool fp32() const { return precision == NBTE_PREC_MIXED; }
+    bool synthetic() const { return scheme != NBTE_SCHEME_SEQUENTIAL; }
+    int mom_lpc() const;
+
+    void build_host();
+    void upload_device();
+    void ensure_setup() {
+        build_host();
+        upload_device();
+    }
+    int64_t state_bytes(int prec) const;
+    void allocate_state(int prec);
+    int64_t device_bytes() const;
+    void make_view();
+    void prepare(const double *Q_cell, const nbte_solve_opts &o);
+    // device state: stop rule for the following iterations (clears the stop flag)
+    void set_controls(int stop, double tol, int max_iter);
+    int stop_mode = 0;
+    double stop_tol = 0.0;
+    int stop_max_iter = 0;
+    // bring the host state mirror up to date (waits for the runner's stream)
+    void sync_state();
+    void iterate(int n, bool check, double *res_out);
+    void read_result(nbte_result *out);
+    void collect_stats();
+    int cur_index() const { return (3 - hs.rot) % 3; }
+    int prev_index() const { return (cur_index() + 1) % 3; }
+};

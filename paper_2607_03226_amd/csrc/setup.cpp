@@ -158,9 +158,12 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
     pg.ref.assign((size_t)pg.maxin * DN, 0);
     pg.coef.assign((size_t)pg.maxin * DN, 0.0);
     pg.gptr.resize(sc.lvl_ptr.size());
+    pg.in_row.assign((size_t)m.NBF * D, -1);
     const bool staged = !sc.slot.empty();
+    std::vector<int32_t> pos(N);                 // position of a cell in direction i's order
     for (int i = 0; i < D; ++i) {
         const double *s = &q.s[3 * i];
+        for (int64_t k = 0; k < N; ++k) pos[sc.perm[(int64_t)i * N + k]] = (int32_t)k;
         const int32_t *slot_i = staged ? &sc.slot[(size_t)i * N] : nullptr;
         const int32_t *lp = &sc.lvl_ptr[sc.lvl_off[i]];
         int32_t *gp = &pg.gptr[sc.lvl_off[i]];
@@ -188,12 +191,13 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                             const int64_t bf = -(int64_t)n - 1;
                             const int64_t row = (int64_t)pg.ghost_src.size();
                             pg.ghost_src.push_back((bf * D + i) * (int64_t)B);
+                            pg.in_row[bf * D + i] = (int32_t)row;
                             r = rank < gcap ? -1 - rank : -kSpillBase - 1 - (int32_t)row;
                             ++rank;
                         } else if (slot_i && slot_i[n] >= 0) {
                             r = slot_i[n];                             // staged in LDS
                         } else {
-                            r = -(2 * kSpillBase + 2) - n;             // stored copy in HBM
+                            r = -(2 * kSpillBase + 2) - pos[n];        // stored copy in HBM
                         }
                         pg.ref[(size_t)j * DN + at] = r;
                         pg.coef[(size_t)j * DN + at] = -a;

@@ -1,4 +1,4 @@
-// Problem handles, the iteration driver and the C ABI (include/nbte.h).
+// Problem handles, the single-solve driver and their C ABI (include/nbte.h).
 //
 // One iteration (Methods, Eqs. (5)-(6) sequential, (7)-(12) synthetic; the
 // task split of Eq. (14) becomes one kernel over all band x direction systems):
@@ -8,7 +8,10 @@
 //      temperature, heat flux (Eq. (7));
 //   4. sequential: T_L <- that moment; synthetic: diffusion correction
 //      (Eq. (10)) solved by PCG, T_L <- moment + correction;
-//   5. FP64 residual max|dT_L| / max|T_L - T_ref|.
+//   5. FP64 residual max|dT_L| / max|T_L - T_ref| and the stop test, on the
+//      device.
+// A stand-alone problem iterates through a Runner of one member; batches
+// (batch.cpp) put many problems in one Runner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,8 +22,7 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
-#include "kernels.h"
+#include "problem.h"
 
 using namespace nbte;
 
@@ -29,26 +31,16 @@ struct nbte_mesh {
 };
 
 namespace {
-
 thread_local std::string g_last_error;
+}
+
+namespace nbte {
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 nbte_status fail(nbte_status code, const std::string &msg) {
     g_last_error = msg;
     return code;
-}
-
-template <class F>
-nbte_status guarded(F &&f) {
-    try {
-        g_last_error.clear();
-        return f();
-    } catch (const Error &e) {
-        return fail(e.code, e.what());
-    } catch (const std::bad_alloc &) {
-        return fail(NBTE_ERR_OUT_OF_MEMORY, "host allocation failed");
-    } catch (const std::exception &e) {
-        return fail(NBTE_ERR_INVALID_ARG, e.what());
-    }
 }
 
 void require_gfx950() {
@@ -62,585 +54,471 @@ void require_gfx950() {
         throw Error(NBTE_ERR_DEVICE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
 }
 
-enum Phase { PH_BC = 0, PH_SWEEP, PH_MOM, PH_SYN, PH_UPD, PH_END, PH_COUNT };
+}  // namespace nbte
 
-}  // namespace
+namespace {
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+}
 
-struct nbte_problem {
-    std::shared_ptr<Mesh> mesh;
-    hipStream_t stream = nullptr;
-    BandTable bands;
-    Quadrature quad;
-    std::vector<nbte_boundary> bcs;
-    bool have_bands = false, have_quad = false, have_bcs = false;
-    double T_ref = 300.0;
+nbte_problem::~nbte_problem() {
+    if (batch) batch_forget(batch, this);
+    solo.reset();
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+}
 
-    // cached setup (validity flags)
-    bool geom_ok = false, sched_ok = false, plan_ok = false, diff_ok = false, tables_ok = false;
-    bool sched_up = false, plan_up = false, diff_up = false;
-    Schedule sched;
-    SweepProgram prog;
-    BoundaryPlan plan;
-    DiffusionOperator diff;
+int nbte_problem::mom_lpc() const {
+    int lpc = 1;
+    while (lpc < bands.B && lpc < 64) lpc <<= 1;
+    return lpc;
+}
 
-    // device buffers
-    DevBuf d_nbr, d_S, d_invV, d_V;
-    DevBuf d_perm, d_lvl_ptr, d_lvl_off;
-    DevBuf d_Cw, d_src, d_vel, d_itau, d_dirs, d_w, d_qbias;
-    DevBuf d_bf_owner, d_bf_kind, d_mirror, d_bf_thw, d_bf_p, d_sdotS, d_win;
-    DevBuf d_Lrow, d_Lcol, d_Lval, d_Ldinv, d_dirrhs;
-    DevBuf d_g, d_inflow, d_Jw, d_Q;
-    DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta, d_maxbuf;
-    DevBuf d_pcg_r, d_pcg_z, d_pcg_p, d_pcg_Ap, d_pcg_part, d_pcg_scal;
-    int pcg_nblk = 1;
-
-    // state
-    bool prepared = false;
-    int precision = NBTE_PREC_FP64;
-    int scheme = NBTE_SCHEME_SYNTHETIC;
-    int cur = 0, prev = 1, spare = 2;  // indices into d_theta, always distinct
-    int iterations = 0;
-    double residual = INFINITY;
-    double heat_in = 0.0;
-    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0};
-    struct Shape { int bpb = 1, bpl = 1, block = 256, slots = 0, gcap = 0; } shape;
-    int slots_for_cap = -2;   // cap the current slot table was built for
-    DevBuf d_pcell, d_pslot, d_pref, d_pcoef, d_psout, d_pth, d_pq, d_gptr, d_gsrc, d_gval;
-    int prog_B = -1, prog_gcap = -1;
-    int time_phases = 0;
-
-    // HIP graphs of three iterations (the theta rotation has period 3), one per
-    // starting rotation; dropped by prepare (shape, scheme or buffers may change)
-    hipGraphExec_t graph_exec[3] = {nullptr, nullptr, nullptr};
-    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-    bool use_graphs = true;
-    hipStream_t own_stream = nullptr;   // used when the caller passes the null stream
-
-    void drop_graphs() {
-        for (int r = 0; r < 3; ++r) {
-            if (graph_exec[r]) (void)hipGraphExecDestroy(graph_exec[r]);
-            if (graph[r]) (void)hipGraphDestroy(graph[r]);
-            graph_exec[r] = nullptr;
-            graph[r] = nullptr;
-        }
+// Resolve the tuning into one sweep launch shape.  Defaults aim at two
+// workgroups per CU (bands split into blocks until D * blocks >= 512) and a
+// 64 KiB LDS budget for staged neighbour values.
+nbte_problem::Shape nbte_problem::resolve_shape() const {
+    Shape sh;
+    const int B = bands.B, D = quad.D;
+    int bpb = tuning.bands_per_block;
+    if (bpb <= 0) {
+        int nbb = std::max(1, std::min(B, (512 + D - 1) / D));
+        int want = (B + nbb - 1) / nbb;
+        bpb = 1;
+        while (bpb * 2 <= want) bpb *= 2;
     }
+    bpb = std::min(bpb, B);
+    int bpl = tuning.bands_per_lane > 0 ? tuning.bands_per_lane : 1;
+    while (bpl * 64 < bpb) bpl *= 2;          // at most 64 lanes per cell
+    if (bpl > 8) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block too large for 8 bands per lane");
+    int lanes = (bpb + bpl - 1) / bpl, lpc = 1;
+    while (lpc < lanes) lpc <<= 1;
+    int block = tuning.block_size > 0 ? tuning.block_size : 256;
+    block = std::min(std::max(block, lpc), 512);   // the sweep kernel is built for <= 512 threads
+    sh.bpb = bpb;
+    sh.bpl = bpl;
+    sh.block = block;
+    // the level tables and the two ghost buffers of a direction share the
+    // workgroup's LDS with the staged values; at most a quarter of the budget
+    // goes to ghosts, larger boundary levels read the rest from HBM
+    const int table = ((sched_ok ? sched.max_levels : 0) + 1) * 8;
+    const int total = tuning.lds_bytes == 0 ? 65536 : std::min(std::abs(tuning.lds_bytes), 65536);
+    sh.gcap = std::min(sched_ok ? sched.max_ghosts : 0, std::max(1, total / 4 / (2 * bpb * 8)));
+    const int ghosts = 2 * sh.gcap * bpb * 8;
+    if (table + ghosts > 65536 - 8 * bpb)
+        throw Error(NBTE_ERR_INVALID_ARG, "sweep level tables do not fit in LDS; use fewer bands per block");
+    const int budget = (tuning.lds_bytes == 0 ? 65536 : std::min(tuning.lds_bytes, 65536)) - table - ghosts;
+    sh.slots = tuning.lds_bytes < 0 ? 0 : std::max(budget, 0) / (bpb * 8);
+    return sh;
+}
 
-    // phase timing
-    std::vector<std::array<hipEvent_t, PH_COUNT>> events;
-    int events_used = 0;
-    nbte_stats stats{};
-    std::chrono::steady_clock::time_point t_wall0;
-
-    ~nbte_problem() {
-        drop_graphs();
-        for (auto &ev : events)
-            for (auto e : ev) (void)hipEventDestroy(e);
-        if (own_stream) (void)hipStreamDestroy(own_stream);
+// Host-side setup products (no device access): schedules, sweep program,
+// boundary plan, diffusion operator.  Throws the validation errors of the ABI.
+void nbte_problem::build_host() {
+    if (!have_bands || !have_quad || !have_bcs)
+        throw Error(NBTE_ERR_STATE, "set_bands, set_quadrature and set_boundaries must precede the solve");
+    const Mesh &m = *mesh;
+    if (!sched_ok) {
+        sched = build_schedule(m, quad);
+        sched_ok = true;
+        sched_up = false;
+        slots_for_cap = -2;
     }
-
-    DeviceView view() const {
-        DeviceView v{};
-        v.N = mesh->N;
-        v.F = mesh->F;
-        v.B = bands.B;
-        v.D = quad.D;
-        v.NBF = mesh->NBF;
-        v.nbr = d_nbr.as<int32_t>();
-        v.S = d_S.as<double>();
-        v.invV = d_invV.as<double>();
-        v.perm = d_perm.as<int32_t>();
-        v.lvl_ptr = d_lvl_ptr.as<int32_t>();
-        v.lvl_off = d_lvl_off.as<int32_t>();
-        v.maxin = prog.maxin;
-        v.max_levels = sched.max_levels;
-        v.max_ghosts = prog.max_ghosts;
-        v.n_ghost = (int64_t)prog.ghost_src.size();
-        v.gptr = d_gptr.as<int32_t>();
-        v.ghost_src = d_gsrc.as<int64_t>();
-        v.gval = d_gval.as<double>();
-        v.p_cell = d_pcell.as<int32_t>();
-        v.p_slot = d_pslot.as<int32_t>();
-        v.p_ref = d_pref.as<int32_t>();
-        v.p_coef = d_pcoef.as<double>();
-        v.p_sout = d_psout.as<double>();
-        v.p_th = d_pth.as<double>();
-        v.p_q = d_pq.as<double>();
-        v.theta_cell = nullptr;
-        v.Cw = d_Cw.as<double>();
-        v.src = d_src.as<double>();
-        v.vel = d_vel.as<double>();
-        v.inv_tau = d_itau.as<double>();
-        v.dirs = d_dirs.as<double>();
-        v.w = d_w.as<double>();
-        v.bf_owner = d_bf_owner.as<int32_t>();
-        v.bf_kind = d_bf_kind.as<int32_t>();
-        v.mirror = d_mirror.as<int32_t>();
-        v.bf_thw = d_bf_thw.as<double>();
-        v.bf_p = d_bf_p.as<double>();
-        v.sdotS = d_sdotS.as<double>();
-        v.win = d_win.as<double>();
-        v.g = d_g.ptr;
-        v.inflow = d_inflow.as<double>();
-        v.Jw = d_Jw.as<double>();
-        v.Q = d_Q.as<double>();
-        return v;
+    shape = resolve_shape();
+    if (slots_for_cap != shape.slots || prog_B != bands.B || prog_gcap != shape.gcap) {
+        if (shape.slots > 0) assign_slots(m, quad, sched, shape.slots);
+        else sched.slot.clear(), sched.max_slots = 0, sched.spilled = 0;
+        slots_for_cap = shape.slots;
+        prog = build_program(m, quad, sched, bands.B, shape.gcap);
+        prog_B = bands.B;
+        prog_gcap = shape.gcap;
+        sched_up = false;
     }
+    if (!plan_ok) {
+        plan = build_boundary_plan(m, quad, bcs, T_ref);
+        plan_ok = true;
+        plan_up = false;
+        diff_ok = false;
+    }
+    if (!plan.has_thermalizing)
+        throw Error(NBTE_ERR_ILL_POSED, "no thermalizing wall: the steady problem has no unique solution");
+    if (!diff_ok) {
+        diff = build_diffusion(m, bands, quad, plan);
+        diff_ok = true;
+        diff_up = false;
+    }
+}
 
-    // Resolve the tuning into one sweep launch shape.  Defaults aim at two
-    // workgroups per CU (bands split into blocks until D * blocks >= 512) and
-    // a 64 KiB LDS budget for staged neighbour values.
-    Shape resolve_shape() const {
-        Shape sh;
+void nbte_problem::upload_device() {
+    require_gfx950();
+    if (!stream) {
+        // the null stream cannot be captured into a graph; a blocking stream
+        // still orders with the caller's null-stream work
+        NBTE_HIP(hipStreamCreate(&own_stream));
+        stream = own_stream;
+    }
+    const Mesh &m = *mesh;
+    if (!geom_ok) {
+        upload(d_nbr, m.nbr, stream);
+        upload(d_V, m.V, stream);
+        upload(d_bf_owner, m.bf_owner, stream);
+        geom_ok = true;
+    }
+    if (!sched_up) {
+        upload(d_lvl_ptr, sched.lvl_ptr, stream);
+        upload(d_lvl_off, sched.lvl_off, stream);
+        upload(d_pcell, prog.cell, stream);
+        upload(d_pslot, prog.slot, stream);
+        upload(d_pref, prog.ref, stream);
+        upload(d_pcoef, prog.coef, stream);
+        upload(d_psout, prog.sout, stream);
+        upload(d_gptr, prog.gptr, stream);
+        upload(d_inrow, prog.in_row, stream);
+        d_pth.alloc(prog.cell.size() * sizeof(double));
+        d_pq.alloc(prog.cell.size() * sizeof(double));
+        sched_up = true;
+    }
+    if (!plan_up) {
+        upload(d_bf_kind, plan.kind, stream);
+        upload(d_mirror, plan.mirror, stream);
+        upload(d_bf_thw, plan.theta_w, stream);
+        upload(d_bf_p, plan.p, stream);
+        upload(d_sdotS, plan.sdotS, stream);
+        upload(d_win, plan.win, stream);
+        plan_up = true;
+    }
+    if (!tables_ok) {
         const int B = bands.B, D = quad.D;
-        int bpb = tuning.bands_per_block;
-        if (bpb <= 0) {
-            int nbb = std::max(1, std::min(B, (512 + D - 1) / D));
-            int want = (B + nbb - 1) / nbb;
-            bpb = 1;
-            while (bpb * 2 <= want) bpb *= 2;
+        std::vector<double> Cw(B), src(B), itau(B);
+        for (int l = 0; l < B; ++l) {
+            Cw[l] = bands.C[l] / quad.W;
+            src[l] = bands.C[l] / (bands.C_tot * quad.W);
+            itau[l] = 1.0 / bands.tau[l];
         }
-        bpb = std::min(bpb, B);
-        int bpl = tuning.bands_per_lane > 0 ? tuning.bands_per_lane : 1;
-        while (bpl * 64 < bpb) bpl *= 2;          // at most 64 lanes per cell
-        if (bpl > 8) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block too large for 8 bands per lane");
-        int lanes = (bpb + bpl - 1) / bpl, lpc = 1;
+        // q of a pure equilibrium field: theta * sum_l v_l C_l/W * sum_i w_i s_i (0 for a symmetric set)
+        std::vector<double> qb(3, 0.0);
+        double vcw = 0;
+        for (int l = 0; l < B; ++l) vcw += bands.v[l] * Cw[l];
+        for (int i = 0; i < D; ++i)
+            for (int ax = 0; ax < 3; ++ax) qb[ax] += quad.w[i] * quad.s[3 * i + ax];
+        for (double &x : qb) x *= vcw;
+        upload(d_Cw, Cw, stream);
+        upload(d_src, src, stream);
+        upload(d_vel, bands.v, stream);
+        upload(d_itau, itau, stream);
+        upload(d_dirs, quad.s, stream);
+        upload(d_w, quad.w, stream);
+        upload(d_qbias, qb, stream);
+        tables_ok = true;
+    }
+    if (!diff_up) {
+        std::vector<double> dinv(m.N);
+        for (int64_t c = 0; c < m.N; ++c) dinv[c] = 1.0 / diff.val[diff.row_ptr[c]];
+        upload(d_Lrow, diff.row_ptr, stream);
+        upload(d_Lcol, diff.col, stream);
+        upload(d_Lval, diff.val, stream);
+        upload(d_Ldinv, dinv, stream);
+        pcg_nblk = (int)std::min<int64_t>(256, cdiv(m.N, 256));
+        for (DevBuf *b : {&d_pcg_r, &d_pcg_z, &d_pcg_p, &d_pcg_Ap}) b->alloc(m.N * sizeof(double));
+        d_pcg_part.alloc(3 * 256 * sizeof(double));
+        d_pcg_scal.alloc(8 * sizeof(double));
+        diff_up = true;
+    }
+    NBTE_HIP(hipStreamSynchronize(stream));
+}
+
+int64_t nbte_problem::state_bytes(int prec) const {
+    const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
+    const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
+    const int64_t ghosts = prog_B > 0 ? (int64_t)prog.ghost_src.size() : NBF * D;   // incoming pairs
+    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * 8 + NBF * 8 + N * 8 * 10 + 1024;
+}
+
+void nbte_problem::allocate_state(int prec) {
+    const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
+    const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
+    d_g.alloc(D * N * B * es);
+    d_gval.alloc(std::max<int64_t>((int64_t)prog.ghost_src.size() * B, 1) * 8);
+    d_Jw.alloc(std::max<int64_t>(NBF, 1) * 8);
+    d_Q.alloc(N * 8);
+    for (auto &t : d_theta) t.alloc(N * 8);
+    d_theta_seq.alloc(N * 8);
+    d_thetaE.alloc(N * 8);
+    d_q.alloc(3 * N * 8);
+    d_rhs.alloc(N * 8);
+    d_delta.alloc(N * 8);
+    d_state.alloc(sizeof(SolveState));
+    d_view.alloc(sizeof(DeviceView));
+}
+
+int64_t nbte_problem::device_bytes() const {
+    int64_t s = 0;
+    for (const DevBuf *b :
+         {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pcell, &d_pslot, &d_pref, &d_pcoef, &d_psout, &d_pth,
+          &d_pq, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
+          &d_mirror, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_g, &d_gval,
+          &d_Jw, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
+          &d_pcg_r, &d_pcg_z, &d_pcg_p, &d_pcg_Ap, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work})
+        s += (int64_t)b->bytes;
+    return s;
+}
+
+void nbte_problem::make_view() {
+    DeviceView v{};
+    v.N = mesh->N;
+    v.F = mesh->F;
+    v.B = bands.B;
+    v.D = quad.D;
+    v.fp32 = fp32() ? 1 : 0;
+    v.NBF = mesh->NBF;
+    v.scheme = scheme;
+    v.mom_lpc = mom_lpc();
+    v.nbr = d_nbr.as<int32_t>();
+    v.V = d_V.as<double>();
+    v.maxin = prog.maxin;
+    v.max_levels = sched.max_levels;
+    {
+        int lanes = (shape.bpb + shape.bpl - 1) / shape.bpl, lpc = 1;
         while (lpc < lanes) lpc <<= 1;
-        int block = tuning.block_size > 0 ? tuning.block_size : 256;
-        block = std::min(std::max(block, lpc), 512);   // the sweep kernel is built for <= 512 threads
-        sh.bpb = bpb;
-        sh.bpl = bpl;
-        sh.block = block;
-        // the level tables and the two ghost buffers of a direction share the
-        // workgroup's LDS with the staged values; at most a quarter of the
-        // budget goes to ghosts, larger boundary levels read the rest from HBM
-        const int table = ((sched_ok ? sched.max_levels : 0) + 1) * 8;
-        const int total = tuning.lds_bytes == 0 ? 65536 : std::min(std::abs(tuning.lds_bytes), 65536);
-        sh.gcap = std::min(sched_ok ? sched.max_ghosts : 0, std::max(1, total / 4 / (2 * bpb * 8)));
-        const int ghosts = 2 * sh.gcap * bpb * 8;
-        if (table + ghosts > 65536 - 8 * bpb)
-            throw Error(NBTE_ERR_INVALID_ARG, "sweep level tables do not fit in LDS; use fewer bands per block");
-        const int budget = (tuning.lds_bytes == 0 ? 65536 : std::min(tuning.lds_bytes, 65536)) - table - ghosts;
-        sh.slots = tuning.lds_bytes < 0 ? 0 : std::max(budget, 0) / (bpb * 8);
-        return sh;
+        v.lpc = lpc;
     }
-    // The correction only has to capture the smooth error modes: 20 Jacobi-CG
-    // iterations leave the outer iteration count unchanged on every workload,
-    // eight cost at most a few percent more outer iterations.
-    int cg_max_iter() const { return tuning.cg_max_iter > 0 ? tuning.cg_max_iter : 8; }
-    double cg_rtol() const { return tuning.cg_rtol > 0 ? tuning.cg_rtol : 1e-3; }
+    v.bpb = shape.bpb;
+    v.gcap = shape.gcap;
+    v.lvl_ptr = d_lvl_ptr.as<int32_t>();
+    v.lvl_off = d_lvl_off.as<int32_t>();
+    v.gptr = d_gptr.as<int32_t>();
+    v.p_cell = d_pcell.as<int32_t>();
+    v.p_slot = d_pslot.as<int32_t>();
+    v.p_ref = d_pref.as<int32_t>();
+    v.p_coef = d_pcoef.as<double>();
+    v.p_sout = d_psout.as<double>();
+    v.p_th = d_pth.as<double>();
+    v.p_q = d_pq.as<double>();
+    v.Cw = d_Cw.as<double>();
+    v.src = d_src.as<double>();
+    v.vel = d_vel.as<double>();
+    v.inv_tau = d_itau.as<double>();
+    v.beta = bands.beta;
+    v.C_tot = bands.C_tot;
+    v.dirs = d_dirs.as<double>();
+    v.w = d_w.as<double>();
+    v.qbias = d_qbias.as<double>();
+    v.bf_owner = d_bf_owner.as<int32_t>();
+    v.bf_kind = d_bf_kind.as<int32_t>();
+    v.mirror = d_mirror.as<int32_t>();
+    v.in_row = d_inrow.as<int32_t>();
+    v.bf_thw = d_bf_thw.as<double>();
+    v.bf_p = d_bf_p.as<double>();
+    v.sdotS = d_sdotS.as<double>();
+    v.win = d_win.as<double>();
+    v.g = d_g.ptr;
+    v.gval = d_gval.as<double>();
+    v.Jw = d_Jw.as<double>();
+    for (int k = 0; k < 3; ++k) v.theta[k] = d_theta[k].as<double>();
+    v.theta_seq = d_theta_seq.as<double>();
+    v.thetaE = d_thetaE.as<double>();
+    v.q = d_q.as<double>();
+    v.rhs = d_rhs.as<double>();
+    v.delta = d_delta.as<double>();
+    v.state = d_state.as<SolveState>();
+    PcgWork &w = v.pcg;
+    w.n = mesh->N;
+    w.nblk = pcg_nblk;
+    w.max_iter = cg_max_iter();
+    w.rtol2 = cg_rtol() * cg_rtol();
+    w.row_ptr = d_Lrow.as<int32_t>();
+    w.col = d_Lcol.as<int32_t>();
+    w.val = d_Lval.as<double>();
+    w.dinv = d_Ldinv.as<double>();
+    w.r = d_pcg_r.as<double>();
+    w.z = d_pcg_z.as<double>();
+    w.p = d_pcg_p.as<double>();
+    w.Ap = d_pcg_Ap.as<double>();
+    w.partial = d_pcg_part.as<double>();
+    w.scal = d_pcg_scal.as<double>();
+    hv = v;
+}
 
-    PcgWork pcg() const {
-        PcgWork w{};
-        w.n = mesh->N;
-        w.nblk = pcg_nblk;
-        w.row_ptr = d_Lrow.as<int32_t>();
-        w.col = d_Lcol.as<int32_t>();
-        w.val = d_Lval.as<double>();
-        w.dinv = d_Ldinv.as<double>();
-        w.r = d_pcg_r.as<double>();
-        w.z = d_pcg_z.as<double>();
-        w.p = d_pcg_p.as<double>();
-        w.Ap = d_pcg_Ap.as<double>();
-        w.partial = d_pcg_part.as<double>();
-        w.scal = d_pcg_scal.as<double>();
-        return w;
+void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
+    if (batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member; remove it from the batch first");
+    if (o.precision != NBTE_PREC_FP64 && o.precision != NBTE_PREC_MIXED) throw Error(NBTE_ERR_INVALID_ARG, "bad precision");
+    if (o.scheme < 0 || o.scheme > 2) throw Error(NBTE_ERR_INVALID_ARG, "bad scheme");
+    if (!std::isfinite(o.T_ref)) throw Error(NBTE_ERR_INVALID_ARG, "bad T_ref");
+    if (o.T_ref != T_ref) {
+        T_ref = o.T_ref;
+        plan_ok = false;  // wall temperatures are stored relative to T_ref
     }
-
-    // Host-side setup products (no device access): schedules, boundary plan,
-    // diffusion operator.  Throws the validation errors of the ABI.
-    void build_host() {
-        if (!have_bands || !have_quad || !have_bcs)
-            throw Error(NBTE_ERR_STATE, "set_bands, set_quadrature and set_boundaries must precede the solve");
-        const Mesh &m = *mesh;
-        if (!sched_ok) {
-            sched = build_schedule(m, quad);
-            sched_ok = true;
-            sched_up = false;
-            slots_for_cap = -2;
+    const Mesh &m = *mesh;
+    std::vector<double> Q(m.N, 0.0);
+    if (Q_cell)
+        for (int64_t c = 0; c < m.N; ++c) {
+            if (!std::isfinite(Q_cell[c])) throw Error(NBTE_ERR_INVALID_ARG, "non-finite heat source");
+            Q[c] = Q_cell[c];
         }
-        shape = resolve_shape();
-        if (slots_for_cap != shape.slots || prog_B != bands.B || prog_gcap != shape.gcap) {
-            if (shape.slots > 0) assign_slots(m, quad, sched, shape.slots);
-            else sched.slot.clear(), sched.max_slots = 0, sched.spilled = 0;
-            slots_for_cap = shape.slots;
-            prog = build_program(m, quad, sched, bands.B, shape.gcap);
-            prog_B = bands.B;
-            prog_gcap = shape.gcap;
-            sched_up = false;
-        }
-        if (!plan_ok) {
-            plan = build_boundary_plan(m, quad, bcs, T_ref);
-            plan_ok = true;
-            plan_up = false;
-            diff_ok = false;
-        }
-        if (!plan.has_thermalizing)
-            throw Error(NBTE_ERR_ILL_POSED, "no thermalizing wall: the steady problem has no unique solution");
-        if (!diff_ok) {
-            diff = build_diffusion(m, bands, quad, plan);
-            diff_ok = true;
-            diff_up = false;
+    std::vector<double> t0;
+    if (o.T_init) {
+        t0.resize(m.N);
+        for (int64_t c = 0; c < m.N; ++c) {
+            if (!std::isfinite(o.T_init[c])) throw Error(NBTE_ERR_INVALID_ARG, "non-finite T_init");
+            t0[c] = o.T_init[c] - T_ref;
         }
     }
-
-    void upload_device() {
-        require_gfx950();
-        if (!stream) {
-            // the null stream cannot be captured into a graph; a blocking
-            // stream still orders with the caller's null-stream work
-            NBTE_HIP(hipStreamCreate(&own_stream));
-            stream = own_stream;
-        }
-        const Mesh &m = *mesh;
-        if (!geom_ok) {
-            std::vector<double> invV(m.N);
-            for (int64_t c = 0; c < m.N; ++c) invV[c] = 1.0 / m.V[c];
-            upload(d_nbr, m.nbr, stream);
-            upload(d_S, m.S, stream);
-            upload(d_invV, invV, stream);
-            upload(d_V, m.V, stream);
-            upload(d_bf_owner, m.bf_owner, stream);
-            geom_ok = true;
-        }
-        if (!sched_up) {
-            upload(d_perm, sched.perm, stream);
-            upload(d_lvl_ptr, sched.lvl_ptr, stream);
-            upload(d_lvl_off, sched.lvl_off, stream);
-            upload(d_pcell, prog.cell, stream);
-            upload(d_pslot, prog.slot, stream);
-            upload(d_pref, prog.ref, stream);
-            upload(d_pcoef, prog.coef, stream);
-            upload(d_psout, prog.sout, stream);
-            d_pth.alloc(prog.cell.size() * sizeof(double));
-            d_pq.alloc(prog.cell.size() * sizeof(double));
-            upload(d_gptr, prog.gptr, stream);
-            upload(d_gsrc, prog.ghost_src, stream);
-            d_gval.alloc(std::max<size_t>(prog.ghost_src.size() * bands.B, 1) * sizeof(double));
-            sched_up = true;
-        }
-        if (!plan_up) {
-            upload(d_bf_kind, plan.kind, stream);
-            upload(d_mirror, plan.mirror, stream);
-            upload(d_bf_thw, plan.theta_w, stream);
-            upload(d_bf_p, plan.p, stream);
-            upload(d_sdotS, plan.sdotS, stream);
-            upload(d_win, plan.win, stream);
-            plan_up = true;
-        }
-        if (!tables_ok) {
-            const int B = bands.B, D = quad.D;
-            std::vector<double> Cw(B), src(B), itau(B);
-            for (int l = 0; l < B; ++l) {
-                Cw[l] = bands.C[l] / quad.W;
-                src[l] = bands.C[l] / (bands.C_tot * quad.W);
-                itau[l] = 1.0 / bands.tau[l];
-            }
-            // q of a pure equilibrium field: theta * sum_l v_l C_l/W * sum_i w_i s_i (0 for a symmetric set)
-            std::vector<double> qb(3, 0.0);
-            double vcw = 0;
-            for (int l = 0; l < B; ++l) vcw += bands.v[l] * Cw[l];
-            for (int i = 0; i < D; ++i)
-                for (int ax = 0; ax < 3; ++ax) qb[ax] += quad.w[i] * quad.s[3 * i + ax];
-            for (double &x : qb) x *= vcw;
-            upload(d_Cw, Cw, stream);
-            upload(d_src, src, stream);
-            upload(d_vel, bands.v, stream);
-            upload(d_itau, itau, stream);
-            upload(d_dirs, quad.s, stream);
-            upload(d_w, quad.w, stream);
-            upload(d_qbias, qb, stream);
-            tables_ok = true;
-        }
-        if (!diff_up) {
-            std::vector<double> dinv(m.N);
-            for (int64_t c = 0; c < m.N; ++c) dinv[c] = 1.0 / diff.val[diff.row_ptr[c]];
-            upload(d_Lrow, diff.row_ptr, stream);
-            upload(d_Lcol, diff.col, stream);
-            upload(d_Lval, diff.val, stream);
-            upload(d_Ldinv, dinv, stream);
-            upload(d_dirrhs, diff.dir_rhs, stream);
-            pcg_nblk = (int)std::min<int64_t>(256, (m.N + 255) / 256);
-            for (DevBuf *b : {&d_pcg_r, &d_pcg_z, &d_pcg_p, &d_pcg_Ap}) b->alloc(m.N * sizeof(double));
-            d_pcg_part.alloc(3 * 256 * sizeof(double));
-            d_pcg_scal.alloc(8 * sizeof(double));
-            diff_up = true;
-        }
+    prepared = false;
+    ensure_setup();
+    precision = o.precision;
+    scheme = o.scheme;
+    time_phases = o.time_phases;
+    allocate_state(precision);
+    heat_in = 0.0;
+    for (int64_t c = 0; c < m.N; ++c) heat_in += m.V[c] * Q[c];
+    make_view();
+    NBTE_HIP(hipMemcpyAsync(d_view.ptr, &hv, sizeof(DeviceView), hipMemcpyHostToDevice, stream));
+    // work items of the single-solve launches: [one][PCG workgroups][flux workgroups]
+    {
+        const int nf = (int)cdiv(m.NBF, 4);
+        std::vector<WorkItem> wk;
+        wk.push_back({0, 0, 0, 1});
+        self_pcg = (int)wk.size();
+        for (int b = 0; b < pcg_nblk; ++b) wk.push_back({0, 0, b, pcg_nblk});
+        n_self_pcg = pcg_nblk;
+        self_flux = (int)wk.size();
+        for (int b = 0; b < nf; ++b) wk.push_back({0, 0, b, nf});
+        n_self_flux = nf;
+        upload(d_self_work, wk, stream);
         NBTE_HIP(hipStreamSynchronize(stream));
     }
-
-    void ensure_setup() {
-        build_host();
-        upload_device();
+    SolveState s0{};
+    s0.max_iter = o.max_iter;
+    s0.tol = o.tol;
+    NBTE_HIP(hipMemcpyAsync(d_state.ptr, &s0, sizeof(s0), hipMemcpyHostToDevice, stream));
+    NBTE_HIP(hipMemcpyAsync(d_Q.ptr, Q.data(), m.N * 8, hipMemcpyHostToDevice, stream));
+    launch_gather((int64_t)quad.D * m.N, d_pcell.as<int32_t>(), d_Q.as<double>(), d_pq.as<double>(), stream);
+    double *th0 = d_theta[0].as<double>();   // theta[cur] at rotation 0
+    if (o.T_init) {
+        NBTE_HIP(hipMemcpyAsync(th0, t0.data(), m.N * 8, hipMemcpyHostToDevice, stream));
+    } else {
+        // Fourier initial guess: L theta = V Qdot + wall data
+        std::vector<double> b(m.N);
+        for (int64_t c = 0; c < m.N; ++c) b[c] = m.V[c] * Q[c] + diff.dir_rhs[c];
+        NBTE_HIP(hipMemcpyAsync(d_rhs.ptr, b.data(), m.N * 8, hipMemcpyHostToDevice, stream));
+        const DeviceView *vp = d_view.as<DeviceView>();
+        const WorkItem *wk = d_self_work.as<WorkItem>();
+        if (m.N <= kPcgBlockMaxRows)
+            launch_pcg_block(vp, wk + self_one, 1, 1, stream);
+        else
+            launch_pcg_multi(vp, wk + self_pcg, n_self_pcg, wk + self_one, 1, 1,
+                             std::max(1000, (int)std::sqrt((double)m.N) * 20), stream);
     }
+    // g = 0 is equilibrium at theta^0; the stored g is relative to theta[prev]
+    NBTE_HIP(hipMemcpyAsync(d_theta[1].ptr, th0, m.N * 8, hipMemcpyDeviceToDevice, stream));
+    launch_fill_zero(d_g.ptr, d_g.bytes, stream);
+    launch_fill_zero(d_gval.ptr, d_gval.bytes, stream);
+    NBTE_HIP(hipGetLastError());
+    NBTE_HIP(hipStreamSynchronize(stream));
+    hs = s0;
+    stop_mode = 0;
+    stop_tol = o.tol;
+    stop_max_iter = o.max_iter;
+    if (!solo) solo = std::make_unique<Runner>(stream);
+    solo->set_members({this});
+    solo->set_timing(time_phases != 0);
+    solo->set_graphs(!tuning.no_graphs);
+    solo->reset_timing();
+    stats = nbte_stats{};
+    prepared = true;
+}
 
-    int64_t state_bytes(int prec) const {
-        const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
-        const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
-        return D * N * B * es + NBF * D * B * 8 + NBF * 8 + N * 8 * 12 + 64;
+void nbte_problem::set_controls(int stop, double tol, int max_iter) {
+    launch_set_controls(d_state.as<SolveState>(), stop, tol, max_iter, stream);
+    NBTE_HIP(hipGetLastError());
+    NBTE_HIP(hipStreamSynchronize(stream));
+    stop_mode = stop;
+    stop_tol = tol;
+    stop_max_iter = max_iter;
+    hs.done = 0;
+}
+
+void nbte_problem::sync_state() {
+    if (batch) batch_sync(batch);
+    else if (solo) solo->collect();
+}
+
+void nbte_problem::iterate(int n, bool check, double *res_out) {
+    if (!prepared) throw Error(NBTE_ERR_STATE, "nbte_prepare must precede nbte_iterate");
+    if (batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member; it iterates with nbte_batch_step");
+    if (stop_mode != 0 || hs.done) set_controls(0, stop_tol, stop_max_iter);
+    auto t0 = std::chrono::steady_clock::now();
+    solo->run(n);
+    if (check) {
+        solo->collect();
+        if (hs.done == NBTE_DONE_DIVERGED)
+            throw Error(NBTE_ERR_DIVERGED, "iteration diverged (non-finite temperature)");
+        if (res_out) *res_out = hs.residual;
     }
+    stats.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
 
-    void allocate_state(int prec) {
-        const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
-        const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
-        d_g.alloc(D * N * B * es);
-        d_inflow.alloc(std::max<int64_t>(NBF * D * B, 1) * 8);
-        d_Jw.alloc(std::max<int64_t>(NBF, 1) * 8);
-        d_Q.alloc(N * 8);
-        for (auto &t : d_theta) t.alloc(N * 8);
-        d_theta_seq.alloc(N * 8);
-        d_thetaE.alloc(N * 8);
-        d_q.alloc(3 * N * 8);
-        d_rhs.alloc(N * 8);
-        d_delta.alloc(N * 8);
-        d_maxbuf.alloc(2 * sizeof(unsigned long long));
-    }
-
-    int64_t device_bytes() const {
-        int64_t s = 0;
-        for (const DevBuf *b : {&d_nbr, &d_S, &d_invV, &d_V, &d_perm, &d_lvl_ptr, &d_lvl_off, &d_Cw, &d_src, &d_vel,
-                                &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind, &d_mirror, &d_bf_thw,
-                                &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_dirrhs, &d_g,
-                                &d_inflow, &d_Jw, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq,
-                                &d_thetaE, &d_q, &d_rhs, &d_delta, &d_maxbuf, &d_pcg_r, &d_pcg_z, &d_pcg_p,
-                                &d_pcg_Ap, &d_pcg_part, &d_pcg_scal, &d_pcell, &d_pslot, &d_pref, &d_pcoef,
-                                &d_psout, &d_pth, &d_pq, &d_gptr, &d_gsrc, &d_gval})
-            s += (int64_t)b->bytes;
-        return s;
-    }
-
-    void record(int iter_slot, Phase ph) {
-        if (!time_phases) return;
-        NBTE_HIP(hipEventRecord(events[iter_slot][ph], stream));
-    }
-
-    int next_event_slot() {
-        if (!time_phases) return 0;
-        if (events_used == (int)events.size()) {
-            std::array<hipEvent_t, PH_COUNT> ev;
-            for (auto &e : ev) NBTE_HIP(hipEventCreate(&e));
-            events.push_back(ev);
-        }
-        return events_used++;
-    }
-
-    void one_iteration() {
-        const bool fp32 = precision == NBTE_PREC_MIXED;
-        const DeviceView v = view();
-        const double *th = d_theta[cur].as<double>();
-        const double *th_prev = d_theta[prev].as<double>();
-        double *th_new = d_theta[spare].as<double>();
-        const int slot = next_event_slot();
-        record(slot, PH_BC);
-        launch_bc_inflow(v, fp32, th_prev, stream);
-        launch_ghost_gather(v, stream);
-        record(slot, PH_SWEEP);
-        launch_gather(v, th, d_pth.as<double>(), stream);
-        launch_sweep(v, fp32, th, shape.bpb, shape.bpl, shape.block, std::max(sched.max_slots, 1), shape.gcap,
-                     shape.slots == 0 || sched.spilled > 0, stream);
-        record(slot, PH_MOM);
-        const bool syn = scheme != NBTE_SCHEME_SEQUENTIAL;
-        if (syn) launch_wall_flux(v, fp32, th, stream);
-        launch_moments(v, fp32, th, bands.beta, bands.C_tot, d_V.as<double>(), d_qbias.as<double>(),
-                       d_theta_seq.as<double>(), d_thetaE.as<double>(), d_q.as<double>(),
-                       syn ? d_rhs.as<double>() : nullptr, stream);
-        record(slot, PH_SYN);
-        if (syn) launch_pcg(pcg(), d_rhs.as<double>(), d_delta.as<double>(), cg_rtol(), cg_max_iter(), stream);
-        record(slot, PH_UPD);
-        launch_reset_max(d_maxbuf.as<unsigned long long>(), stream);
-        const double *base = (scheme == NBTE_SCHEME_SYNTHETIC_LITERAL) ? th : d_theta_seq.as<double>();
-        launch_update(mesh->N, base, syn ? d_delta.as<double>() : nullptr, th, th_new,
-                      d_maxbuf.as<unsigned long long>(), stream);
-        record(slot, PH_END);
-        NBTE_HIP(hipGetLastError());
-        // rotate: previous <- current, current <- new; the old previous buffer
-        // (two iterations back) becomes the next scratch
-        const int old_prev = prev;
-        prev = cur;
-        cur = spare;
-        spare = old_prev;
-        ++iterations;
-    }
-
-    double read_residual() {
-        unsigned long long mb[2];
-        NBTE_HIP(hipMemcpyAsync(mb, d_maxbuf.ptr, sizeof(mb), hipMemcpyDeviceToHost, stream));
-        NBTE_HIP(hipStreamSynchronize(stream));
-        double md, mt;
-        std::memcpy(&md, &mb[0], 8);
-        std::memcpy(&mt, &mb[1], 8);
-        if (!std::isfinite(md) || !std::isfinite(mt)) throw Error(NBTE_ERR_DIVERGED, "iteration diverged (non-finite temperature)");
-        residual = mt > 0 ? md / mt : 0.0;
-        return residual;
-    }
-
-    void prepare(const double *Q_cell, const nbte_solve_opts &o) {
-        if (o.precision != NBTE_PREC_FP64 && o.precision != NBTE_PREC_MIXED) throw Error(NBTE_ERR_INVALID_ARG, "bad precision");
-        if (o.scheme < 0 || o.scheme > 2) throw Error(NBTE_ERR_INVALID_ARG, "bad scheme");
-        if (!std::isfinite(o.T_ref)) throw Error(NBTE_ERR_INVALID_ARG, "bad T_ref");
-        if (o.T_ref != T_ref) {
-            T_ref = o.T_ref;
-            plan_ok = false;  // wall temperatures are stored relative to T_ref
-        }
-        ensure_setup();
-        const Mesh &m = *mesh;
-        precision = o.precision;
-        scheme = o.scheme;
-        time_phases = o.time_phases;
-        allocate_state(precision);
-        std::vector<double> Q(m.N, 0.0);
-        heat_in = 0.0;
-        if (Q_cell) {
-            for (int64_t c = 0; c < m.N; ++c) {
-                if (!std::isfinite(Q_cell[c])) throw Error(NBTE_ERR_INVALID_ARG, "non-finite heat source");
-                Q[c] = Q_cell[c];
-                heat_in += m.V[c] * Q[c];
-            }
-        }
-        NBTE_HIP(hipMemcpyAsync(d_Q.ptr, Q.data(), m.N * 8, hipMemcpyHostToDevice, stream));
-        launch_gather(view(), d_Q.as<double>(), d_pq.as<double>(), stream);
-        cur = 0; prev = 1; spare = 2;
-        double *th0 = d_theta[0].as<double>();
-        if (o.T_init) {
-            std::vector<double> t0(m.N);
-            for (int64_t c = 0; c < m.N; ++c) {
-                if (!std::isfinite(o.T_init[c])) throw Error(NBTE_ERR_INVALID_ARG, "non-finite T_init");
-                t0[c] = o.T_init[c] - T_ref;
-            }
-            NBTE_HIP(hipMemcpyAsync(th0, t0.data(), m.N * 8, hipMemcpyHostToDevice, stream));
+void nbte_problem::read_result(nbte_result *out) {
+    if (!prepared) throw Error(NBTE_ERR_STATE, "nothing to read: call nbte_prepare first");
+    sync_state();
+    const Mesh &m = *mesh;
+    auto put = [&](double *dst, const double *src, int64_t n, double offset) {
+        if (!dst) return;
+        if (out_on_device) {
+            launch_affine(n, src, 1.0, offset, dst, stream);
         } else {
-            // Fourier initial guess: L theta = V Qdot + wall data
-            std::vector<double> b(m.N);
-            for (int64_t c = 0; c < m.N; ++c) b[c] = m.V[c] * Q[c] + diff.dir_rhs[c];
-            NBTE_HIP(hipMemcpyAsync(d_rhs.ptr, b.data(), m.N * 8, hipMemcpyHostToDevice, stream));
-            launch_pcg(pcg(), d_rhs.as<double>(), th0, 1e-12, std::max(1000, (int)std::sqrt((double)m.N) * 20), stream);
-        }
-        // g = 0 is equilibrium at theta^0; the stored g is relative to theta[prev]
-        NBTE_HIP(hipMemcpyAsync(d_theta[prev].ptr, th0, m.N * 8, hipMemcpyDeviceToDevice, stream));
-        launch_fill_zero(d_g.ptr, d_g.bytes, stream);
-        launch_fill_zero(d_inflow.ptr, d_inflow.bytes, stream);
-        NBTE_HIP(hipGetLastError());
-        NBTE_HIP(hipStreamSynchronize(stream));
-        iterations = 0;
-        residual = INFINITY;
-        events_used = 0;
-        drop_graphs();
-        stats = nbte_stats{};
-        prepared = true;
-    }
-
-    // rotation state 0..2 of (cur, prev, spare)
-    int rotation() const { return cur == 0 ? 0 : (cur == 2 ? 1 : 2); }
-
-    void run_graph_triple() {
-        const int r = rotation();
-        if (!graph_exec[r]) {
-            const int c0 = cur, p0 = prev, s0 = spare, it0 = iterations;
-            NBTE_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-            try {
-                for (int k = 0; k < 3; ++k) one_iteration();
-            } catch (...) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(stream, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            NBTE_HIP(hipStreamEndCapture(stream, &graph[r]));
-            NBTE_HIP(hipGraphInstantiate(&graph_exec[r], graph[r], nullptr, nullptr, 0));
-            cur = c0; prev = p0; spare = s0; iterations = it0;   // capture only recorded the work
-        }
-        NBTE_HIP(hipGraphLaunch(graph_exec[r], stream));
-        for (int k = 0; k < 3; ++k) {   // advance the rotation as the three iterations do
-            const int old_prev = prev;
-            prev = cur;
-            cur = spare;
-            spare = old_prev;
-        }
-        iterations += 3;
-    }
-
-    void iterate(int n, bool check, double *res_out) {
-        if (!prepared) throw Error(NBTE_ERR_STATE, "nbte_prepare must precede nbte_iterate");
-        auto t0 = std::chrono::steady_clock::now();
-        int k = 0;
-        if (use_graphs && !tuning.no_graphs && !time_phases)
-            for (; k + 3 <= n; k += 3) run_graph_triple();
-        for (; k < n; ++k) one_iteration();
-        if (check) {
-            double r = read_residual();
-            if (res_out) *res_out = r;
-        }
-        stats.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
-
-    void read_result(nbte_result *out) {
-        if (!prepared) throw Error(NBTE_ERR_STATE, "nothing to read: call nbte_prepare first");
-        const Mesh &m = *mesh;
-        const bool fp32 = precision == NBTE_PREC_MIXED;
-        const bool on_dev = out_on_device;
-        auto put = [&](double *dst, const double *src, int64_t n, double offset) {
-            if (!dst) return;
-            if (on_dev) {
-                launch_affine(n, src, 1.0, offset, dst, stream);
-            } else {
-                std::vector<double> h(n);
-                NBTE_HIP(hipMemcpyAsync(h.data(), src, n * 8, hipMemcpyDeviceToHost, stream));
-                NBTE_HIP(hipStreamSynchronize(stream));
-                for (int64_t k = 0; k < n; ++k) dst[k] = offset + h[k];
-            }
-        };
-        // theta of the last update is the current one; T and q belong to the
-        // last sweep, whose distribution is stored relative to theta[prev]
-        put(out->T_lattice, d_theta[cur].as<double>(), m.N, T_ref);
-        put(out->T, d_thetaE.as<double>(), m.N, T_ref);
-        put(out->q, d_q.as<double>(), 3 * m.N, 0.0);
-        // energy balance from the last sweep's face values
-        double defect = 0.0;
-        if (m.NBF > 0) {
-            launch_wall_flux(view(), fp32, d_theta[prev].as<double>(), stream);
-            std::vector<double> J(m.NBF);
-            NBTE_HIP(hipMemcpyAsync(J.data(), d_Jw.ptr, m.NBF * 8, hipMemcpyDeviceToHost, stream));
+            std::vector<double> h(n);
+            NBTE_HIP(hipMemcpyAsync(h.data(), src, n * 8, hipMemcpyDeviceToHost, stream));
             NBTE_HIP(hipStreamSynchronize(stream));
-            double net = 0, tot = 0;
-            for (double x : J) { net += x; tot += std::fabs(x); }
-            double scale = std::max(std::fabs(heat_in), 0.5 * tot);
-            defect = scale > 0 ? std::fabs(net - heat_in) / scale : 0.0;
+            for (int64_t k = 0; k < n; ++k) dst[k] = offset + h[k];
         }
+    };
+    // theta of the last update is the current one; T and q belong to the
+    // last sweep, whose distribution is stored relative to theta[prev]
+    put(out->T_lattice, d_theta[cur_index()].as<double>(), m.N, T_ref);
+    put(out->T, d_thetaE.as<double>(), m.N, T_ref);
+    put(out->q, d_q.as<double>(), 3 * m.N, 0.0);
+    // energy balance from the last sweep's face values
+    double defect = 0.0;
+    if (m.NBF > 0 && hs.iterations > 0) {
+        launch_flux(d_view.as<DeviceView>(), d_self_work.as<WorkItem>() + self_flux, n_self_flux, fp32(), 1, stream);
+        std::vector<double> J(m.NBF);
+        NBTE_HIP(hipMemcpyAsync(J.data(), d_Jw.ptr, m.NBF * 8, hipMemcpyDeviceToHost, stream));
         NBTE_HIP(hipStreamSynchronize(stream));
-        out->iterations = iterations;
-        out->residual = residual;
-        out->energy_defect = defect;
-    }
-
-    bool out_on_device = false;
-
-    void collect_stats() {
-        if (time_phases && events_used > 0) {
-            NBTE_HIP(hipStreamSynchronize(stream));
-            double acc[PH_COUNT] = {0};
-            for (int k = 0; k < events_used; ++k)
-                for (int ph = 0; ph < PH_END; ++ph) {
-                    float ms = 0;
-                    NBTE_HIP(hipEventElapsedTime(&ms, events[k][ph], events[k][ph + 1]));
-                    acc[ph] += ms;
-                }
-            stats.ms_bc = acc[PH_BC];
-            stats.ms_sweep = acc[PH_SWEEP];
-            stats.ms_moments = acc[PH_MOM];
-            stats.ms_synthetic = acc[PH_SYN];
-            stats.ms_update = acc[PH_UPD];
-            stats.sweep_launches = events_used;
+        double net = 0, tot = 0;
+        for (double x : J) {
+            net += x;
+            tot += std::fabs(x);
         }
-        stats.iterations = iterations;
-        stats.updates_per_sweep = mesh->N * (int64_t)bands.B * quad.D;
-        stats.max_levels = sched_ok ? sched.max_levels : 0;
-        stats.device_bytes = device_bytes();
-        stats.bands_per_block = shape.bpb;
-        stats.bands_per_lane = shape.bpl;
-        stats.block_size = shape.block;
-        stats.lds_slots = shape.slots > 0 ? sched.max_slots : 0;
-        stats.spilled_values = sched.spilled;
+        double scale = std::max(std::fabs(heat_in), 0.5 * tot);
+        defect = scale > 0 ? std::fabs(net - heat_in) / scale : 0.0;
     }
-};
+    NBTE_HIP(hipStreamSynchronize(stream));
+    out->iterations = hs.iterations;
+    out->residual = hs.iterations > 0 ? hs.residual : INFINITY;
+    out->energy_defect = defect;
+}
+
+void nbte_problem::collect_stats() {
+    if (prepared) sync_state();
+    if (solo && !batch) {
+        solo->harvest_timing();
+        stats.ms_bc = solo->phase_ms[PH_BC];
+        stats.ms_sweep = solo->phase_ms[PH_SWEEP];
+        stats.ms_moments = solo->phase_ms[PH_MOM];
+        stats.ms_synthetic = solo->phase_ms[PH_SYN];
+        stats.ms_update = solo->phase_ms[PH_UPD];
+        stats.sweep_launches = solo->timed_iterations;
+    }
+    stats.iterations = hs.iterations;
+    stats.updates_per_sweep = mesh->N * (int64_t)bands.B * quad.D;
+    stats.max_levels = sched_ok ? sched.max_levels : 0;
+    stats.device_bytes = device_bytes();
+    stats.bands_per_block = shape.bpb;
+    stats.bands_per_lane = shape.bpl;
+    stats.block_size = shape.block;
+    stats.lds_slots = shape.slots > 0 ? sched.max_slots : 0;
+    stats.spilled_values = sched.spilled;
+}
 
 // ============================================================================ ABI
 
@@ -689,15 +567,12 @@ nbte_status nbte_problem_create(const nbte_mesh *m, void *hip_stream, nbte_probl
     });
 }
 
-void nbte_problem_destroy(nbte_problem *p) {
-    if (!p) return;
-    (void)hipStreamSynchronize(p->stream);
-    delete p;
-}
+void nbte_problem_destroy(nbte_problem *p) { delete p; }
 
 nbte_status nbte_set_bands(nbte_problem *p, int32_t n_bands, const double *C, const double *v, const double *tau) {
     return guarded([&] {
         if (!p || !C || !v || !tau || n_bands <= 0) throw Error(NBTE_ERR_INVALID_ARG, "bad band table arguments");
+        if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member");
         BandTable b;
         b.B = n_bands;
         b.C.assign(C, C + n_bands);
@@ -722,6 +597,7 @@ nbte_status nbte_set_bands(nbte_problem *p, int32_t n_bands, const double *C, co
 nbte_status nbte_set_quadrature(nbte_problem *p, int32_t n_dirs, const double *s, const double *w) {
     return guarded([&] {
         if (!p || !s || !w || n_dirs <= 0) throw Error(NBTE_ERR_INVALID_ARG, "bad quadrature arguments");
+        if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member");
         Quadrature q;
         q.D = n_dirs;
         q.s.assign(s, s + 3 * (size_t)n_dirs);
@@ -746,6 +622,7 @@ nbte_status nbte_set_quadrature(nbte_problem *p, int32_t n_dirs, const double *s
 nbte_status nbte_set_boundaries(nbte_problem *p, int32_t n, const nbte_boundary *bcs) {
     return guarded([&] {
         if (!p || !bcs || n <= 0) throw Error(NBTE_ERR_INVALID_ARG, "bad boundary arguments");
+        if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member");
         std::vector<nbte_boundary> v(bcs, bcs + n);
         for (size_t k = 0; k < v.size(); ++k) {
             const auto &b = v[k];
@@ -773,7 +650,7 @@ void nbte_solve_opts_default(nbte_solve_opts *o) {
     o->T_ref = 300.0;
     o->tol = 1e-8;
     o->max_iter = 10000;
-    o->check_every = 1;
+    o->check_every = 8;
     o->T_init = nullptr;
     o->outputs_on_device = 0;
     o->time_phases = 0;
@@ -810,21 +687,22 @@ nbte_status nbte_solve_steady(nbte_problem *p, const double *Q_cell, const nbte_
         if (!(o->tol > 0) || o->max_iter <= 0) throw Error(NBTE_ERR_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
         p->prepare(Q_cell, *o);
         p->out_on_device = o->outputs_on_device != 0;
+        p->set_controls(1, o->tol, o->max_iter);
+        // the device stops the solve at its tolerance or max_iter; the host
+        // only polls, so the result does not depend on check_every
         const int every = std::max(1, o->check_every);
-        bool converged = false;
-        while (p->iterations < o->max_iter) {
-            const int n = std::min(every, o->max_iter - p->iterations);
-            double res = INFINITY;
-            p->iterate(n, true, &res);
-            if (res <= o->tol) {
-                converged = true;
-                break;
-            }
+        auto t0 = std::chrono::steady_clock::now();
+        for (int64_t polls = 0; polls <= (int64_t)o->max_iter / every + 2; ++polls) {
+            p->solo->run(every);
+            p->solo->collect();
+            if (p->hs.done) break;
         }
+        p->stats.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (out) p->read_result(out);
-        if (!converged)
-            return fail(NBTE_ERR_NOT_CONVERGED, "not converged after " + std::to_string(p->iterations) +
-                                                    " iterations (residual " + std::to_string(p->residual) + ")");
+        if (p->hs.done == NBTE_DONE_DIVERGED) return fail(NBTE_ERR_DIVERGED, "iteration diverged (non-finite temperature)");
+        if (p->hs.done != NBTE_DONE_CONVERGED)
+            return fail(NBTE_ERR_NOT_CONVERGED, "not converged after " + std::to_string(p->hs.iterations) +
+                                                    " iterations (residual " + std::to_string(p->hs.residual) + ")");
         return NBTE_OK;
     });
 }
@@ -835,10 +713,10 @@ nbte_status nbte_get_distribution(nbte_problem *p, int32_t band, int32_t dir, do
         if (!p->prepared) throw Error(NBTE_ERR_STATE, "no distribution yet");
         if (band < 0 || band >= p->bands.B || dir < 0 || dir >= p->quad.D)
             throw Error(NBTE_ERR_INVALID_ARG, "band or direction out of range");
+        p->sync_state();
         DevBuf tmp;
         tmp.alloc(p->mesh->N * 8);
-        launch_distribution(p->view(), p->precision == NBTE_PREC_MIXED, p->d_theta[p->prev].as<double>(), band, dir,
-                            tmp.as<double>(), p->stream);
+        launch_distribution(p->d_view.as<DeviceView>(), p->fp32(), band, dir, tmp.as<double>(), p->mesh->N, p->stream);
         NBTE_HIP(hipMemcpyAsync(out, tmp.ptr, p->mesh->N * 8, hipMemcpyDeviceToHost, p->stream));
         NBTE_HIP(hipStreamSynchronize(p->stream));
         return NBTE_OK;
@@ -888,6 +766,7 @@ nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t) {
         if (t->block_size != 0 && (t->block_size < 64 || t->block_size > 1024 || t->block_size % 64))
             throw Error(NBTE_ERR_INVALID_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
         if (t->cg_max_iter < 0 || !(t->cg_rtol >= 0)) throw Error(NBTE_ERR_INVALID_ARG, "bad CG settings");
+        if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member");
         p->tuning = *t;
         p->prepared = false;   // launch shape and slot table are rebuilt by the next prepare
         return NBTE_OK;
@@ -908,10 +787,12 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
         if (!p->have_bands || !p->have_quad) throw Error(NBTE_ERR_STATE, "bands and quadrature must be set");
         const Mesh &m = *p->mesh;
         const int64_t N = m.N, F = m.F, D = p->quad.D, NBF = m.NBF;
-        int64_t geo = N * F * (4 + 24) + N * 16 + NBF * 4;
-        int64_t sched = D * N * 4 + D * (N + 1) * 4 + D * N * (4 + 4 + 8 + 8 + 8 + (F - 1) * 12);
-        int64_t plan = NBF * (4 + 8 + 8 + 8 + 4 * D + 8 * D);
-        int64_t lh = N * (F + 1) * 12 + N * 8 * 7;
+        const int64_t mi = std::max<int64_t>(F - 1, 1);
+        const int64_t geo = N * F * 4 + N * 8 + NBF * 4;
+        // level tables (at most one level per cell), streams cell/slot/refs/coefs/outflow/theta/Q, inflow rows
+        const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * 12 + 8 + 8 + 8) + NBF * D * 4;
+        const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * D * (8 + 4);
+        const int64_t lh = N * (F + 1) * 12 + N * 8 * 5 + 256 * 3 * 8;
         *bytes = geo + sched + plan + lh + p->state_bytes(precision);
         return NBTE_OK;
     });

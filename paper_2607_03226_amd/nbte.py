@@ -58,6 +58,11 @@ class Stats(ct.Structure):
                 ("spilled_values", ct.c_int64)]
 
 
+class BatchInfo(ct.Structure):
+    _fields_ = [("members", ct.c_int32), ("budget_bytes", ct.c_int64), ("bytes_in_use", ct.c_int64),
+                ("iterations_launched", ct.c_int64)]
+
+
 class Tuning(ct.Structure):
     _fields_ = [("bands_per_block", ct.c_int32), ("bands_per_lane", ct.c_int32), ("block_size", ct.c_int32),
                 ("lds_bytes", ct.c_int32), ("cg_max_iter", ct.c_int32), ("cg_rtol", ct.c_double),
@@ -86,6 +91,13 @@ SIGNATURES = [
     ("nbte_set_tuning", ct.c_int32, [ct.c_void_p, ct.POINTER(Tuning)]),
     ("nbte_get_tuning", ct.c_int32, [ct.c_void_p, ct.POINTER(Tuning)]),
     ("nbte_problem_footprint", ct.c_int32, [ct.c_void_p, ct.c_int32, _i64]),
+    ("nbte_batch_create", ct.c_int32, [ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_void_p)]),
+    ("nbte_batch_destroy", None, [ct.c_void_p]),
+    ("nbte_batch_admit", ct.c_int32, [ct.c_void_p, ct.c_void_p, _d, ct.POINTER(SolveOpts)]),
+    ("nbte_batch_step", ct.c_int32, [ct.c_void_p, ct.c_int32]),
+    ("nbte_batch_poll", ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_void_p), ct.c_int32, _i32, _i32]),
+    ("nbte_batch_remove", ct.c_int32, [ct.c_void_p, ct.c_void_p]),
+    ("nbte_batch_get_info", ct.c_int32, [ct.c_void_p, ct.POINTER(BatchInfo)]),
     ("nbte_last_error", ct.c_char_p, []),
     ("nbte_version", ct.c_char_p, []),
 ]
@@ -228,7 +240,7 @@ def nbte_solve_opts_default():
     return o
 
 
-def make_opts(scheme="synthetic", precision="fp64", T_ref=300.0, tol=1e-8, max_iter=10000, check_every=1,
+def make_opts(scheme="synthetic", precision="fp64", T_ref=300.0, tol=1e-8, max_iter=10000, check_every=8,
               T_init=None, outputs_on_device=False, time_phases=False):
     o = nbte_solve_opts_default()
     o.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
@@ -337,6 +349,56 @@ def nbte_problem_footprint(p, precision="mixed"):
     return b.value
 
 
+class Batch:
+    """Owning wrapper of an nbte_batch handle; holds its members' wrappers."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.members = {}
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.nbte_batch_destroy(self.handle)
+            self.handle = None
+
+
+def nbte_batch_create(budget_bytes=0, stream=None):
+    h = ct.c_void_p()
+    _check(_lib.nbte_batch_create(_stream(stream), int(budget_bytes), ct.byref(h)))
+    return Batch(h)
+
+
+def nbte_batch_admit(b, p, Q_cell, opts):
+    Q = None if Q_cell is None else _f64(Q_cell)
+    _check(_lib.nbte_batch_admit(b.handle, p.handle, None if Q is None else _ptr(Q), ct.byref(opts)))
+    p._outputs_on_device = bool(opts.outputs_on_device)
+    b.members[p.handle.value] = p
+
+
+def nbte_batch_step(b, n):
+    _check(_lib.nbte_batch_step(b.handle, int(n)))
+
+
+def nbte_batch_poll(b):
+    """Returns (stopped member wrappers, number still running)."""
+    cap = max(len(b.members), 1)
+    arr = (ct.c_void_p * cap)()
+    nd, nr = ct.c_int32(0), ct.c_int32(0)
+    _check(_lib.nbte_batch_poll(b.handle, arr, cap, ct.byref(nd), ct.byref(nr)))
+    return [b.members[arr[k]] for k in range(nd.value)], nr.value
+
+
+def nbte_batch_remove(b, p):
+    _check(_lib.nbte_batch_remove(b.handle, p.handle))
+    b.members.pop(p.handle.value, None)
+
+
+def nbte_batch_get_info(b):
+    info = BatchInfo()
+    _check(_lib.nbte_batch_get_info(b.handle, ct.byref(info)))
+    return {k: getattr(info, k) for k, _ in BatchInfo._fields_}
+
+
 # --- convenience: a whole problem description in one call -------------------
 
 def build_problem(problem, stream=None):
@@ -352,7 +414,7 @@ def build_problem(problem, stream=None):
     return mesh, p
 
 
-def solve(problem, precision=None, scheme=None, tol=1e-8, max_iter=10000, check_every=1, T_init=None,
+def solve(problem, precision=None, scheme=None, tol=1e-8, max_iter=10000, check_every=8, T_init=None,
           stream=None, allow_not_converged=False, tuning=None):
     """tuning: None (library defaults), "auto" (autotuner cache, defaults if
     the workload was never tuned) or a dict of nbte_set_tuning arguments."""

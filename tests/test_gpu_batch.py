@@ -1,0 +1,150 @@
+"""GPU batches: many solves iterated together through the C ABI.
+
+A member of a batch runs the same kernels with the same per-solve reduction
+order as a stand-alone solve, so its result must be bitwise equal to the
+stand-alone result with the same options, whatever else is in the batch and
+whenever it was admitted.
+"""
+import numpy as np
+import pytest
+
+from workloads import configs as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _N():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_03226_amd import nbte
+    return nbte
+
+
+def _alone(N, p, precision, tol):
+    out = N.solve(p, precision=precision, scheme=p.scheme, tol=tol, max_iter=4000)
+    return out
+
+
+def _same(a, b):
+    assert a["iterations"] == b["iterations"], (a["iterations"], b["iterations"])
+    for k in ("T_lattice", "T", "q"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def _drain(N, batch, handles, step=8, limit=20000):
+    """Step until every member stopped; returns {id: result} read at stop time."""
+    results = {}
+    launched = 0
+    while len(results) < len(handles):
+        N.nbte_batch_step(batch, step)
+        launched += step
+        done, running = N.nbte_batch_poll(batch)
+        for h in done:
+            key = h.handle.value
+            if key not in results:
+                results[key] = N.nbte_read_result(h)
+                N.nbte_batch_remove(batch, h)
+        assert launched < limit
+    return results
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_batch_members_equal_their_standalone_solves(precision, tol):
+    N = _N()
+    probs = C.config4_small()
+    alone = [_alone(N, p, precision, tol) for p in probs]
+    batch = N.nbte_batch_create()
+    handles = []
+    keep = []
+    for p in probs:
+        mesh, h = N.build_problem(p)
+        keep.append(mesh)
+        N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision=precision, T_ref=p.T_ref,
+                                                       tol=tol, max_iter=4000))
+        handles.append(h)
+    res = _drain(N, batch, handles)
+    for h, a in zip(handles, alone):
+        _same(res[h.handle.value], a)
+
+
+def test_continuous_admission_mixed_precisions_and_schemes():
+    """Members admitted while others run, of both precisions and of the
+    sequential and synthetic schemes, each equal to its stand-alone solve."""
+    N = _N()
+    probs = C.config4_small() + [C.config1(), C.config2_small(), C.config3_small()]
+    specs = []
+    for j, p in enumerate(probs):
+        prec = "mixed" if j % 2 else "fp64"
+        tol = 1e-8 if prec == "mixed" else 1e-10
+        specs.append((p, prec, tol))
+    alone = [_alone(N, p, prec, tol) for p, prec, tol in specs]
+    batch = N.nbte_batch_create()
+    keep, handles, results = [], [], {}
+    pending = list(range(len(specs)))
+    launched = 0
+    while pending or len(results) < len(specs):
+        # admit two new requests every round while others are mid-solve
+        for _ in range(2):
+            if pending:
+                j = pending.pop(0)
+                p, prec, tol = specs[j]
+                mesh, h = N.build_problem(p)
+                keep.append(mesh)
+                N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision=prec, T_ref=p.T_ref,
+                                                               tol=tol, max_iter=4000))
+                h._index = j
+                handles.append(h)
+        N.nbte_batch_step(batch, 5)
+        launched += 5
+        done, _ = N.nbte_batch_poll(batch)
+        for h in done:
+            results[h._index] = N.nbte_read_result(h)
+            N.nbte_batch_remove(batch, h)
+        assert launched < 40000
+    for j, a in enumerate(alone):
+        _same(results[j], a)
+
+
+def test_admission_budget():
+    N = _N()
+    probs = C.config4_small()[:3]
+    handles, keep = [], []
+    for p in probs:
+        mesh, h = N.build_problem(p)
+        keep.append(mesh)
+        handles.append(h)
+    need = [N.nbte_problem_footprint(h, "mixed") for h in handles]
+    batch = N.nbte_batch_create(budget_bytes=need[0] + need[1] + need[2] // 2)
+    opts = lambda p: N.make_opts(scheme=p.scheme, precision="mixed", T_ref=p.T_ref, tol=1e-8, max_iter=4000)
+    N.nbte_batch_admit(batch, handles[0], probs[0].Q, opts(probs[0]))
+    N.nbte_batch_admit(batch, handles[1], probs[1].Q, opts(probs[1]))
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_batch_admit(batch, handles[2], probs[2].Q, opts(probs[2]))
+    assert e.value.status == N.ERR_OUT_OF_MEMORY
+    info = N.nbte_batch_get_info(batch)
+    assert info["members"] == 2 and info["bytes_in_use"] == need[0] + need[1]
+    # a member cannot be driven on its own
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_iterate(handles[0], 1)
+    assert e.value.status == N.ERR_STATE
+    N.nbte_batch_remove(batch, handles[0])
+    N.nbte_batch_admit(batch, handles[2], probs[2].Q, opts(probs[2]))
+    assert N.nbte_batch_get_info(batch)["members"] == 2
+    res = _drain(N, batch, handles[1:])
+    for h, p in zip(handles[1:], probs[1:]):
+        _same(res[h.handle.value], _alone(N, p, "mixed", 1e-8))
+
+
+def test_batch_stops_at_max_iter_and_reports_it():
+    N = _N()
+    p = C.config2_small()
+    mesh, h = N.build_problem(p)
+    batch = N.nbte_batch_create()
+    N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision="fp64", T_ref=p.T_ref, tol=1e-14,
+                                                   max_iter=7))
+    N.nbte_batch_step(batch, 20)
+    done, running = N.nbte_batch_poll(batch)
+    assert [d.handle.value for d in done] == [h.handle.value] and running == 0
+    out = N.nbte_read_result(h)
+    assert out["iterations"] == 7
