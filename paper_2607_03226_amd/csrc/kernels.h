@@ -12,6 +12,17 @@
 
 #include <cstdint>
 
+// Pointers in the descriptors are global-memory pointers.  Device code sees
+// them qualified with the global address space, so loads through pointers
+// read out of a descriptor compile to global (not flat) instructions: flat
+// loads would also count against the LDS wait counter and serialise the
+// sweep's prefetch pipeline.  Host code sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define NBTE_G __attribute__((address_space(1)))
+#else
+#define NBTE_G
+#endif
+
 namespace nbte {
 
 // Iteration state of one solve (device memory).
@@ -35,11 +46,11 @@ struct PcgWork {
     int32_t nblk;         // workgroups of the multi-workgroup form
     int32_t max_iter;
     double rtol2;         // stop when r.z <= rtol2 * r0.z0
-    const int32_t *row_ptr, *col;
-    const double *val, *dinv;
-    double *r, *z, *p, *Ap;
-    double *partial;      // 3 * nblk: two r.z buffers, p.Ap
-    double *scal;         // [-, rz0, -, -, converged flag, iterations]
+    const int32_t NBTE_G *row_ptr, *col;
+    const double NBTE_G *val, *dinv;
+    double NBTE_G *vec;          // 7 n: block form r, z, p, Ap; multi form r[2], w[2], s[2], p
+    double NBTE_G *partial;      // 4 * nblk: per parity the r.u and w.u partial sums
+    double NBTE_G *scal;         // [-, r0.u0, -, -, converged flag, iterations, alpha/gamma per parity (6..9)]
 };
 
 // Everything the kernels read and write of one solve, as raw device pointers.
@@ -53,8 +64,8 @@ struct DeviceView {
     int32_t scheme;  // NBTE_SCHEME_*
     int32_t mom_lpc; // lanes per cell of the reductions
     // mesh
-    const int32_t *nbr;     // N*F
-    const double *V;        // N
+    const int32_t NBTE_G *nbr;     // N*F
+    const double NBTE_G *V;        // N
     // sweep program: level-ordered streams, index i*N + k (see SweepProgram)
     int32_t maxin;
     int32_t max_levels;     // deepest level count over the directions
@@ -62,31 +73,31 @@ struct DeviceView {
     int32_t bpb;            // sweep bands per workgroup
     int32_t gcap;           // ghosts per level kept in LDS
     int32_t pad0;
-    const int32_t *lvl_ptr; // per direction L_i + 1 level offsets, concatenated
-    const int32_t *lvl_off; // D+1: start of direction i's entries in lvl_ptr
-    const int32_t *gptr;    // ghost offsets per level (layout of lvl_ptr)
-    const int32_t *p_cell, *p_slot, *p_ref;
-    const double *p_coef, *p_sout;
-    double *p_th;           // theta in level order, gathered every iteration
-    const double *p_q;      // heat source in level order, gathered at prepare
+    const int32_t NBTE_G *lvl_ptr; // per direction L_i + 1 level offsets, concatenated
+    const int32_t NBTE_G *lvl_off; // D+1: start of direction i's entries in lvl_ptr
+    const int32_t NBTE_G *gptr;    // ghost offsets per level (layout of lvl_ptr)
+    const int32_t NBTE_G *p_cell, *p_slot, *p_ref;
+    const double NBTE_G *p_coef, *p_sout;
+    double NBTE_G *p_th;           // theta in level order, gathered every iteration
+    const double NBTE_G *p_q;      // heat source in level order, gathered at prepare
     // bands: Cw = C/W, src = C/(C_tot W), v, inv_tau
-    const double *Cw, *src, *vel, *inv_tau;
+    const double NBTE_G *Cw, *src, *vel, *inv_tau;
     double beta, C_tot;     // sum C/tau, sum C
     // quadrature
-    const double *dirs;     // D*3
-    const double *w;        // D
-    const double *qbias;    // 3: q of a uniform unit equilibrium
+    const double NBTE_G *dirs;     // D*3
+    const double NBTE_G *w;        // D
+    const double NBTE_G *qbias;    // 3: q of a uniform unit equilibrium
     // boundary plan
-    const int32_t *bf_owner, *bf_kind, *mirror;
-    const int32_t *in_row;  // NBF*D: ghost row of an incoming (face, direction), -1 otherwise
-    const double *bf_thw, *bf_p, *sdotS, *win;
+    const int32_t NBTE_G *bf_owner, *bf_kind, *mirror;
+    const int32_t NBTE_G *in_row;  // NBF*D: ghost row of an incoming (face, direction), -1 otherwise
+    const double NBTE_G *bf_thw, *bf_p, *sdotS, *win;
     // state
-    void *g;                // D*N*B, FP32 or FP64: non-equilibrium part e - C theta/W
-    double *gval;           // n_ghost*B boundary inflow in sweep (ghost) order
-    double *Jw;             // NBF: net flux through each boundary face
-    double *theta[3];       // deviational lattice temperature, rotated by state->rot
-    double *theta_seq, *thetaE, *q, *rhs, *delta;
-    SolveState *state;
+    void NBTE_G *g;                // D*N*B, FP32 or FP64: non-equilibrium part e - C theta/W
+    double NBTE_G *gval;           // n_ghost*B boundary inflow in sweep (ghost) order
+    double NBTE_G *Jw;             // NBF: net flux through each boundary face
+    double NBTE_G *theta[3];       // deviational lattice temperature, rotated by state->rot
+    double NBTE_G *theta_seq, *thetaE, *q, *rhs, *delta;
+    SolveState NBTE_G *state;
     PcgWork pcg;
 };
 
@@ -103,7 +114,7 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 
 // Work tables of the elementwise kernels: items (solve, kind, local block,
 // blocks of this (solve, kind)), 256 threads each.
-//   stage:   kind 0 = boundary inflow, one thread per (boundary face, band);
+//   stage:   kind 0 = boundary inflow, one wave per boundary face;
 //            kind 1 = theta gathered into sweep order, one per stream entry
 //   flux:    net flow through each boundary face, four faces per workgroup
 //   moments: band x direction reductions, mom_lpc lanes per cell
@@ -129,12 +140,11 @@ size_t sweep_lds_bytes(int max_levels, int gcap, int bpb, int slots);
 //   mode 0: solve L delta = rhs (every iteration);
 //   mode 1: solve L theta[cur] = rhs (Fourier initial guess at prepare).
 // Block form: one 1024-thread workgroup runs the whole PCG of a solve (items
-// (solve, -, -, -)).  Multi-workgroup form: items (solve, -, local block,
-// nblk); max_iter is the largest PCG iteration count of the listed solves,
-// each solve stops at its own.
+// (solve, -, -, -)).  Multi-workgroup form (one reduction per iteration, so
+// one launch per iteration): items (solve, -, local block, nblk); max_iter
+// is the largest iteration count of the listed solves, each stops at its own.
 void launch_pcg_block(const DeviceView *vs, const WorkItem *wk, int n, int mode, hipStream_t st);
-void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, const WorkItem *wk_one, int n_one, int mode,
-                      int max_iter, hipStream_t st);
+void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, int mode, int max_iter, hipStream_t st);
 constexpr int64_t kPcgBlockMaxRows = 8192;   // larger systems use the multi-workgroup form
 
 // Iteration state: clear the stop flag and set the stop rule of a solve;

@@ -28,10 +28,18 @@ __device__ __forceinline__ double ld(const T *p, int64_t k) {
 }
 
 // theta buffers of a solve under its rotation
-__device__ __forceinline__ int th_cur(const SolveState *s) { return (3 - s->rot) % 3; }
-__device__ __forceinline__ const double *theta_cur(const DeviceView &v) { return v.theta[th_cur(v.state)]; }
-__device__ __forceinline__ const double *theta_prev(const DeviceView &v) { return v.theta[(th_cur(v.state) + 1) % 3]; }
-__device__ __forceinline__ double *theta_spare(const DeviceView &v) { return v.theta[(th_cur(v.state) + 2) % 3]; }
+__device__ __forceinline__ int th_cur(const SolveState NBTE_G *s) { return (3 - s->rot) % 3; }
+// selected without indexing the descriptor copy (a dynamic index would put it in scratch)
+__device__ __forceinline__ double NBTE_G *theta_at(const DeviceView &v, int k) {
+    return k == 0 ? v.theta[0] : (k == 1 ? v.theta[1] : v.theta[2]);
+}
+__device__ __forceinline__ const double NBTE_G *theta_cur(const DeviceView &v) { return theta_at(v, th_cur(v.state)); }
+__device__ __forceinline__ const double NBTE_G *theta_prev(const DeviceView &v) {
+    return theta_at(v, (th_cur(v.state) + 1) % 3);
+}
+__device__ __forceinline__ double NBTE_G *theta_spare(const DeviceView &v) {
+    return theta_at(v, (th_cur(v.state) + 2) % 3);
+}
 
 __device__ __forceinline__ double wave_sum(double x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
@@ -72,50 +80,97 @@ __global__ void k_fill_zero(uint32_t *p, size_t n) {
 //   partial       p specular + (1 - p) diffuse
 // written straight into the ghost row the sweep reads it from.
 // --------------------------------------------------------------------------
+// One wave per boundary face.  Lanes are (direction group, band) pairs:
+// BL = min(B, 64) bands per pass, JG = 64 / BL directions in flight per band,
+// so the loads of a pass are independent and the bands of one (direction,
+// cell) are read as one contiguous run.  The diffuse sums are reduced across
+// the direction groups through LDS in a fixed order.
 template <class T>
-__device__ void bc_inflow(const DeviceView &v, int64_t t) {
-    const int64_t bf = t / v.B;
-    const int lam = (int)(t - bf * v.B);
+__device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
+    const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
     const T *g = static_cast<const T *>(v.g);
     const double *sd = v.sdotS + bf * D;
     const int32_t *row = v.in_row + bf * D;
-    const double cw = v.Cw[lam];
+    const int BL = B < 64 ? B : 64;
+    const int JG = 64 / BL;
+    const int jg = lane / BL, ml = lane - jg * BL;
     if (v.bf_kind[bf] == NBTE_BC_THERMALIZING) {
-        const double val = cw * v.bf_thw[bf];
-        for (int i = 0; i < D; ++i)
-            if (row[i] >= 0) v.gval[(int64_t)row[i] * B + lam] = val;
+        const double thw = v.bf_thw[bf];
+        for (int l0 = 0; l0 < B; l0 += BL) {
+            const int lam = l0 + ml;
+            if (jg >= JG || lam >= B) continue;
+            const double val = v.Cw[lam] * thw;
+            for (int i = jg; i < D; i += JG) {
+                const int r = row[i];
+                if (r >= 0) v.gval[(int64_t)r * B + lam] = val;
+            }
+        }
         return;
     }
-    const double eq = cw * theta_prev(v)[c];
+    const double thp = theta_prev(v)[c];
     const double p = v.bf_p[bf];
-    double diff = 0.0;
-    if (p < 1.0) {
-        for (int j = 0; j < D; ++j)
-            if (sd[j] > 0.0) diff += v.w[j] * sd[j] * (ld(g, ((int64_t)j * N + c) * B + lam) + eq);
-        diff /= v.win[bf];
-    }
     const int32_t *mir = v.mirror + bf * D;
-    for (int i = 0; i < D; ++i) {
-        if (row[i] < 0) continue;
-        double val = (1.0 - p) * diff;
-        if (p > 0.0) val += p * (ld(g, ((int64_t)mir[i] * N + c) * B + lam) + eq);
-        v.gval[(int64_t)row[i] * B + lam] = val;
+    for (int l0 = 0; l0 < B; l0 += BL) {
+        const int lam = l0 + ml;
+        const bool on = jg < JG && lam < B;
+        const int lam_c = on ? lam : 0;
+        const double cw = v.Cw[lam_c];
+        const double eq = cw * thp;
+        double diff = 0.0;
+        if (p < 1.0) {
+            double acc = 0.0;
+            if (on) {
+#pragma unroll 4
+                for (int j = jg; j < D; j += JG) {
+                    const double a = sd[j];
+                    const double e = ld(g, ((int64_t)j * N + c) * B + lam_c) + eq;
+                    acc += a > 0.0 ? v.w[j] * a * e : 0.0;
+                }
+            }
+            red[lane] = acc;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+            for (int k = 0; k < JG; ++k) diff += red[k * BL + ml];
+            diff /= v.win[bf];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        }
+        if (!on) continue;
+        if (p > 0.0) {
+#pragma unroll 4
+            for (int i = jg; i < D; i += JG) {
+                const int r = row[i];
+                const int mi = mir[i] >= 0 ? mir[i] : 0;   // outgoing directions have no mirror entry
+                const double em = ld(g, ((int64_t)mi * N + c) * B + lam) + eq;
+                if (r >= 0) v.gval[(int64_t)r * B + lam] = (1.0 - p) * diff + p * em;
+            }
+        } else {
+            for (int i = jg; i < D; i += JG) {
+                const int r = row[i];
+                if (r >= 0) v.gval[(int64_t)r * B + lam] = diff;
+            }
+        }
     }
 }
 
 template <class T>
 __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    __shared__ double red[256];
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (v.state->done) return;
     const int64_t stride = (int64_t)it.c * blockDim.x;
     const int64_t t0 = (int64_t)it.b * blockDim.x + threadIdx.x;
     if (it.a == 0) {
-        const int64_t n = v.NBF * v.B;
-        for (int64_t t = t0; t < n; t += stride) bc_inflow<T>(v, t);
+        // faces b*4 + wave, b*4 + wave + 4*nblk, ...
+        const int wv = threadIdx.x >> 6;
+        for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4)
+            bc_face<T>(v, bf, red + 64 * wv);
     } else {
         const int64_t n = (int64_t)v.D * v.N;
         const double *th = theta_cur(v);
@@ -166,9 +221,12 @@ struct SweepRec {
 template <int MI>
 __device__ __forceinline__ void load_rec(SweepRec<MI> &r, const DeviceView &v, int64_t base, int64_t DN, int k,
                                          int kend) {
+    // the loads are issued on every path (a past-the-end record reads stream
+    // position 0 of the direction), so the number of loads in flight is the
+    // same on every path and a later wait on an older record can leave the
+    // younger prefetches outstanding
     r.ok = k < kend;
-    if (!r.ok) return;
-    const int64_t at = base + k;
+    const int64_t at = base + (r.ok ? k : 0);
     r.c = v.p_cell[at];
     r.mine = v.p_slot[at];
     r.sout = v.p_sout[at];
@@ -247,12 +305,13 @@ __device__ __forceinline__ void level_barrier() {
 
 // --------------------------------------------------------------------------
 // Pipeline per level l (after the barrier that ends level l-1):
-//   1. request the ghost values (boundary inflow) of level l+1 into registers;
-//   2. request the records of level l+2;
-//   3. compute level l from registers (records requested at level l-2), the
+//   1. request the records and the ghost values (boundary inflow) of level
+//      l+2 into registers;
+//   2. compute level l from registers (records requested at level l-2), the
 //      LDS ring (upwind values) and ghost buffer l&1 (stored during level l-1);
-//   4. store the ghost values of level l+1 into ghost buffer (l+1)&1;
-//   5. barrier.
+//   3. store the ghost values of level l+1 (requested at level l-1) into
+//      ghost buffer (l+1)&1;
+//   4. barrier.
 // Every wait is on loads issued before the current level's record requests.
 // The level loop is unrolled three ways so a record keeps its registers while
 // its loads are in flight (moving it would force the wait).
@@ -265,7 +324,7 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     //              [ring: slot x bands_per_block doubles]
     const WorkItem tk = wk[blockIdx.x];
     if (tk.solve < 0) return;   // padding of the XCD-ordered work list
-    const DeviceView &v = vs[tk.solve];
+    const DeviceView v = vs[tk.solve];   // a copy: fields stay in registers across the stores
     if (v.state->done) return;
     const int lpc = v.lpc;
     const int bands_per_block = v.bpb;
@@ -308,28 +367,34 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     }
     __syncthreads();
 
-    // ghost values of one level: entry e = q * bands_per_block + local band
-    double gv[kGhostPerThread];
-    auto ghost_load = [&](int l) {
-#pragma unroll
-        for (int m = 0; m < kGhostPerThread; ++m) gv[m] = 0.0;
-        if (l >= nlev) return;
-        const int g0 = gp(l), ne = min(gp(l + 1) - g0, gcap) * bands_per_block;
+    // ghost values of one level: entry e = q * bands_per_block + local band.
+    // They travel with the records of their level: requested two levels ahead
+    // into registers, stored into the level's LDS buffer at the end of the
+    // level before it.
+    struct Ghosts {
+        double v[kGhostPerThread];
+    };
+    auto ghost_load = [&](Ghosts &h, int l) {
+        // branch-free like load_rec: entries past the level read element 0
+        const int ll = l < nlev ? l : nlev - 1;
+        const int g0 = gp(ll), ne = l < nlev ? min(gp(ll + 1) - g0, gcap) * bands_per_block : 0;
 #pragma unroll
         for (int m = 0; m < kGhostPerThread; ++m) {
             const int e = threadIdx.x + m * blockDim.x;
             const int q = e / bands_per_block, lb = e - q * bands_per_block;
-            if (e < ne && lb < nb_here) gv[m] = v.gval[(int64_t)(g0 + q) * B + b0 + lb];
+            const bool ok = e < ne && lb < nb_here;
+            const double x = v.gval[ok ? (int64_t)(g0 + q) * B + b0 + lb : 0];
+            h.v[m] = ok ? x : 0.0;
         }
     };
-    auto ghost_store = [&](int l) {
+    auto ghost_store = [&](const Ghosts &h, int l) {
         if (l >= nlev) return;
         const int dst = gbuf0 + (l & 1) * gstride;
         const int g0 = gp(l), ne = min(gp(l + 1) - g0, gcap) * bands_per_block;
 #pragma unroll
         for (int m = 0; m < kGhostPerThread; ++m) {
             const int e = threadIdx.x + m * blockDim.x;
-            if (e < ne) sweep_lds[dst + e] = gv[m];
+            if (e < ne) sweep_lds[dst + e] = h.v[m];
         }
         // levels with more ghosts than the registers hold: direct copy
 #pragma nounroll
@@ -340,16 +405,19 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     };
 
     SweepRec<MI> q0[kItemsPerThread], q1[kItemsPerThread], q2[kItemsPerThread];
-    auto fetch = [&](SweepRec<MI> (&r)[kItemsPerThread], int l) {
+    Ghosts h0, h1, h2;
+    auto fetch = [&](SweepRec<MI> (&r)[kItemsPerThread], Ghosts &h, int l) {
+        const int ll = l < nlev ? l : nlev - 1;
+        const int kend = l < nlev ? lp(ll + 1) : 0;
 #pragma unroll
-        for (int p = 0; p < kItemsPerThread; ++p) {
-            if (l < nlev) load_rec(r[p], v, base, DN, lp(l) + slot + p * nslots, lp(l + 1));
-            else r[p].ok = false;
-        }
+        for (int p = 0; p < kItemsPerThread; ++p) load_rec(r[p], v, base, DN, lp(ll) + slot + p * nslots, kend);
+        ghost_load(h, l);
     };
-    auto step = [&](int l, SweepRec<MI> (&cur)[kItemsPerThread], SweepRec<MI> (&n2)[kItemsPerThread]) {
-        ghost_load(l + 1);
-        fetch(n2, l + 2);
+    // level l: request level l+2, compute level l, store the ghosts of level
+    // l+1 (requested during level l-1), barrier
+    auto step = [&](int l, SweepRec<MI> (&cur)[kItemsPerThread], const Ghosts &h1n,
+                    SweepRec<MI> (&n2)[kItemsPerThread], Ghosts &h2n) {
+        fetch(n2, h2n, l + 2);
         const int gcur = gbuf0 + (l & 1) * gstride;
 #pragma unroll
         for (int p = 0; p < kItemsPerThread; ++p)
@@ -362,21 +430,20 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
             load_rec(rx, v, base, DN, k, lp(l + 1));
             sweep_cell<T, MI, BPL>(rx, v, bc, gi, base, ring_off, gcur, bands_per_block, b0, lane, nb_here);
         }
-        ghost_store(l + 1);
+        ghost_store(h1n, l + 1);
         level_barrier<SPILL>();
     };
-    ghost_load(0);
-    ghost_store(0);
-    fetch(q0, 0);
-    fetch(q1, 1);
+    fetch(q0, h0, 0);
+    fetch(q1, h1, 1);
+    ghost_store(h0, 0);
     __syncthreads();
 #pragma nounroll
     for (int l = 0; l < nlev; l += 3) {
-        step(l, q0, q2);
+        step(l, q0, h1, q2, h2);
         if (l + 1 >= nlev) break;
-        step(l + 1, q1, q0);
+        step(l + 1, q1, h2, q0, h0);
         if (l + 2 >= nlev) break;
-        step(l + 2, q2, q1);
+        step(l + 2, q2, h0, q1, h1);
     }
 }
 #undef lp
@@ -402,14 +469,16 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
     const double th = (after ? theta_prev(v) : theta_cur(v))[c];
     const T *g = static_cast<const T *>(v.g);
     double acc = 0.0;
+    // both candidate values are loaded on every path (independent loads, four
+    // pairs in flight); directions with s.S = 0 contribute exactly zero
+#pragma unroll 4
     for (int t = lane; t < D * B; t += 64) {
         const int i = t / B, lam = t - i * B;
         const double sd = v.sdotS[bf * D + i];
         const int32_t row = v.in_row[bf * D + i];
-        double e;
-        if (row >= 0) e = v.gval[(int64_t)row * B + lam];
-        else if (sd > 0.0) e = ld(g, ((int64_t)i * N + c) * B + lam) + v.Cw[lam] * th;
-        else continue;
+        const double ein = v.gval[row >= 0 ? (int64_t)row * B + lam : 0];
+        const double eout = ld(g, ((int64_t)i * N + c) * B + lam) + v.Cw[lam] * th;
+        const double e = row >= 0 ? ein : (sd > 0.0 ? eout : 0.0);
         acc += v.vel[lam] * v.w[i] * sd * e;
     }
     acc = wave_sum(acc);
@@ -439,6 +508,8 @@ __global__ void __launch_bounds__(256) k_moments(const DeviceView *__restrict__ 
     if (c < N) {
         for (int lam = lane; lam < B; lam += lpc) {
             double sw = 0, s_x = 0, s_y = 0, s_z = 0;
+            // independent loads, eight directions in flight (summation order unchanged)
+#pragma unroll 8
             for (int i = 0; i < D; ++i) {
                 const double ww = v.w[i] * ld(g, ((int64_t)i * N + c) * B + lam);
                 sw += ww;
@@ -573,7 +644,7 @@ __global__ void k_distribution(const DeviceView *__restrict__ vp, int band, int 
 // --------------------------------------------------------------------------
 __device__ __forceinline__ bool pcg_skip(const DeviceView &v, int mode) { return mode == 0 && v.state->done; }
 __device__ __forceinline__ double *pcg_x(const DeviceView &v, int mode) {
-    return mode == 0 ? v.delta : v.theta[th_cur(v.state)];
+    return mode == 0 ? v.delta : theta_at(v, th_cur(v.state));
 }
 
 // Whole PCG in one workgroup (small systems): no launch per iteration, the
@@ -593,14 +664,15 @@ __global__ void __launch_bounds__(1024) k_pcg_block(const DeviceView *__restrict
     const int max_iter = max_o >= 0 ? max_o : w.max_iter;
     const int64_t n = w.n;
     const int nt = blockDim.x;
+    double *wr = w.vec, *wz = w.vec + n, *wp = w.vec + 2 * n, *wAp = w.vec + 3 * n;
     double acc = 0.0;
     for (int64_t r = threadIdx.x; r < n; r += nt) {
         const double bi = b[r];
         x[r] = 0.0;
-        w.r[r] = bi;
+        wr[r] = bi;
         const double zi = w.dinv[r] * bi;
-        w.z[r] = zi;
-        w.p[r] = zi;
+        wz[r] = zi;
+        wp[r] = zi;
         acc += bi * zi;
     }
     double rz = block_sum(acc, lds);
@@ -611,25 +683,25 @@ __global__ void __launch_bounds__(1024) k_pcg_block(const DeviceView *__restrict
             acc = 0.0;
             for (int64_t r = threadIdx.x; r < n; r += nt) {
                 double ap = 0.0;
-                for (int32_t k = w.row_ptr[r]; k < w.row_ptr[r + 1]; ++k) ap += w.val[k] * w.p[w.col[k]];
-                w.Ap[r] = ap;
-                acc += w.p[r] * ap;
+                for (int32_t k = w.row_ptr[r]; k < w.row_ptr[r + 1]; ++k) ap += w.val[k] * wp[w.col[k]];
+                wAp[r] = ap;
+                acc += wp[r] * ap;
             }
             const double alpha = rz / block_sum(acc, lds);
             acc = 0.0;
             for (int64_t r = threadIdx.x; r < n; r += nt) {
-                x[r] += alpha * w.p[r];
-                const double rn = w.r[r] - alpha * w.Ap[r];
-                w.r[r] = rn;
+                x[r] += alpha * wp[r];
+                const double rn = wr[r] - alpha * wAp[r];
+                wr[r] = rn;
                 const double zn = w.dinv[r] * rn;
-                w.z[r] = zn;
+                wz[r] = zn;
                 acc += rn * zn;
             }
             const double rz_new = block_sum(acc, lds);
             if (!(rz_new > rtol2 * rz0)) { ++it; break; }
             const double beta = rz_new / rz;
             rz = rz_new;
-            for (int64_t r = threadIdx.x; r < n; r += nt) w.p[r] = w.z[r] + beta * w.p[r];
+            for (int64_t r = threadIdx.x; r < n; r += nt) wp[r] = wz[r] + beta * wp[r];
             __syncthreads();
         }
     }
@@ -639,100 +711,66 @@ __global__ void __launch_bounds__(1024) k_pcg_block(const DeviceView *__restrict
     }
 }
 
-// Multi-workgroup form: two launches per PCG iteration; every workgroup of a
-// solve re-sums that solve's per-workgroup partials in the same order, so all
-// see identical scalars and the result is bitwise reproducible.
-// The converged flag is read once per workgroup and broadcast through LDS, so
-// every thread takes the same early exit (a uniform return before any barrier).
-__device__ bool block_flag_set(const double *flag, double *lds) {
-    __syncthreads();
-    if (threadIdx.x == 0) lds[15] = *flag;
-    __syncthreads();
-    const bool set = lds[15] != 0.0;
-    __syncthreads();
-    return set;
-}
-
+// Multi-workgroup form: conjugate gradients with a single reduction per
+// iteration (the Chronopoulos-Gear arrangement of preconditioned CG: the two
+// inner products (r, u) and (w, u) of u = M^-1 r, w = A u are taken together),
+// one launch per iteration.  With gamma_k = (r_k, u_k), delta_k = (w_k, u_k):
+//   beta_k = gamma_k / gamma_{k-1},  alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+//   p_k = u_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}  (s = A p)
+//   x += alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k,  u_{k+1} = M^-1 r_{k+1},  w_{k+1} = A u_{k+1}
+// (beta_0 = 0, alpha_0 = gamma_0 / delta_0).  A row's SpMV needs u_{k+1} of its
+// neighbours, recomputed from their old r, w, s (kept in the other buffer of
+// each pair), so no grid-wide synchronisation is needed inside a launch.
+// Every workgroup of a solve re-sums that solve's partials in the same order:
+// all see identical scalars and the result is bitwise reproducible.  The
+// iteration stops (for every later launch too, through a sticky flag) once
+// gamma_k <= rtol2 gamma_0.
 __device__ double sum_partials(const double *p, int n, double *lds) {
     double x = (threadIdx.x < (unsigned)n) ? p[threadIdx.x] : 0.0;
     return block_sum(x, lds);
 }
 
-__global__ void __launch_bounds__(256) k_pcg_init(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+__global__ void __launch_bounds__(256) k_cg1_init(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
                                                   int mode) {
     __shared__ double lds[16];
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (pcg_skip(v, mode)) return;
     const PcgWork &w = v.pcg;
+    const int64_t n = w.n;
     const double *b = v.rhs;
     double *x = pcg_x(v, mode);
-    double acc = 0.0;
-    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < w.n; r += (int64_t)w.nblk * blockDim.x) {
+    double *r0 = w.vec, *w0 = w.vec + 2 * n, *s1 = w.vec + 5 * n, *pp = w.vec + 6 * n;
+    double ga = 0.0, de = 0.0;
+    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < n; r += (int64_t)w.nblk * blockDim.x) {
         const double bi = b[r];
+        const double u = w.dinv[r] * bi;
+        double au = 0.0;
+        for (int32_t k = w.row_ptr[r]; k < w.row_ptr[r + 1]; ++k) {
+            const int32_t j = w.col[k];
+            au += w.val[k] * (w.dinv[j] * b[j]);
+        }
         x[r] = 0.0;
-        w.r[r] = bi;
-        const double zi = w.dinv[r] * bi;
-        w.z[r] = zi;
-        acc += bi * zi;
+        r0[r] = bi;
+        w0[r] = au;
+        s1[r] = 0.0;
+        pp[r] = 0.0;
+        ga += bi * u;
+        de += au * u;
     }
-    acc = block_sum(acc, lds);
-    if (threadIdx.x == 0) w.partial[it.b] = acc;
-}
-
-// one workgroup per solve
-__global__ void __launch_bounds__(256) k_pcg_rz0(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
-                                                 int mode) {
-    __shared__ double lds[16];
-    const DeviceView &v = vs[wk[blockIdx.x].solve];
-    if (pcg_skip(v, mode)) return;
-    const PcgWork &w = v.pcg;
-    const double rz0 = sum_partials(w.partial, w.nblk, lds);
+    ga = block_sum(ga, lds);
+    de = block_sum(de, lds);
     if (threadIdx.x == 0) {
-        w.scal[1] = rz0;
-        w.scal[4] = 0.0;   // converged flag, sticky once set
-        w.scal[5] = 0.0;
+        w.partial[it.b] = ga;
+        w.partial[w.nblk + it.b] = de;
+        if (it.b == 0) {
+            w.scal[4] = 0.0;
+            w.scal[5] = 0.0;
+        }
     }
 }
 
-// iteration k, part 1: beta, p = z + beta p, Ap = A z + beta Ap, partial p.Ap
-__global__ void __launch_bounds__(256) k_pcg_dir(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
-                                                 int mode, int k, double rtol2_o, int max_o) {
-    __shared__ double lds[16];
-    const WorkItem it = wk[blockIdx.x];
-    const DeviceView &v = vs[it.solve];
-    if (pcg_skip(v, mode)) return;
-    const PcgWork &w = v.pcg;
-    const int max_iter = max_o >= 0 ? max_o : w.max_iter;
-    if (k >= max_iter) return;
-    if (block_flag_set(&w.scal[4], lds)) return;
-    const double rtol2 = rtol2_o >= 0 ? rtol2_o : w.rtol2;
-    const double *prz_new = w.partial + (k & 1) * w.nblk;
-    const double *prz_old = w.partial + ((k + 1) & 1) * w.nblk;
-    double *ppap = w.partial + 2 * w.nblk;
-    const double rz = sum_partials(prz_new, w.nblk, lds);
-    const double rz0 = w.scal[1];
-    if (!(rz > rtol2 * rz0)) {   // converged (or zero right-hand side)
-        if (it.b == 0 && threadIdx.x == 0) w.scal[4] = 1.0;
-        return;
-    }
-    const double beta = (k == 0) ? 0.0 : rz / sum_partials(prz_old, w.nblk, lds);
-    double acc = 0.0;
-    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < w.n; r += (int64_t)w.nblk * blockDim.x) {
-        double az = 0.0;
-        for (int32_t kk = w.row_ptr[r]; kk < w.row_ptr[r + 1]; ++kk) az += w.val[kk] * w.z[w.col[kk]];
-        const double pn = (k == 0) ? w.z[r] : w.z[r] + beta * w.p[r];
-        const double apn = (k == 0) ? az : az + beta * w.Ap[r];
-        w.p[r] = pn;
-        w.Ap[r] = apn;
-        acc += pn * apn;
-    }
-    acc = block_sum(acc, lds);
-    if (threadIdx.x == 0) ppap[it.b] = acc;
-}
-
-// iteration k, part 2: alpha, x += alpha p, r -= alpha Ap, z = M^-1 r, partial r.z
-__global__ void __launch_bounds__(256) k_pcg_step(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+__global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
                                                   int mode, int k, double rtol2_o, int max_o) {
     __shared__ double lds[16];
     const WorkItem it = wk[blockIdx.x];
@@ -741,29 +779,69 @@ __global__ void __launch_bounds__(256) k_pcg_step(const DeviceView *__restrict__
     const PcgWork &w = v.pcg;
     const int max_iter = max_o >= 0 ? max_o : w.max_iter;
     if (k >= max_iter) return;
-    if (block_flag_set(&w.scal[4], lds)) return;
+    // the flag is read once per workgroup and broadcast through LDS, so every
+    // thread takes the same (uniform) exit
+    __syncthreads();
+    if (threadIdx.x == 0) lds[15] = w.scal[4];
+    __syncthreads();
+    if (lds[15] != 0.0) return;
+    __syncthreads();
     const double rtol2 = rtol2_o >= 0 ? rtol2_o : w.rtol2;
-    const double *prz_new = w.partial + (k & 1) * w.nblk;
-    double *prz_next = w.partial + ((k + 1) & 1) * w.nblk;
-    const double *ppap = w.partial + 2 * w.nblk;
-    const double rz = sum_partials(prz_new, w.nblk, lds);
-    const double rz0 = w.scal[1];
-    if (!(rz > rtol2 * rz0)) return;
-    const double alpha = rz / sum_partials(ppap, w.nblk, lds);
-    double *x = pcg_x(v, mode);
-    double acc = 0.0;
-    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < w.n; r += (int64_t)w.nblk * blockDim.x) {
-        x[r] += alpha * w.p[r];
-        const double rn = w.r[r] - alpha * w.Ap[r];
-        w.r[r] = rn;
-        const double zn = w.dinv[r] * rn;
-        w.z[r] = zn;
-        acc += rn * zn;
+    const int64_t n = w.n;
+    const int cur = k & 1, nxt = cur ^ 1;
+    const double *pin = w.partial + cur * 2 * w.nblk;
+    double *pout = w.partial + nxt * 2 * w.nblk;
+    const double gamma = sum_partials(pin, w.nblk, lds);
+    const double delta = sum_partials(pin + w.nblk, w.nblk, lds);
+    const double gamma0 = k == 0 ? gamma : w.scal[1];
+    if (!(gamma > rtol2 * gamma0)) {   // converged (or zero right-hand side)
+        if (it.b == 0 && threadIdx.x == 0) w.scal[4] = 1.0;
+        return;
     }
-    acc = block_sum(acc, lds);
+    double alpha, beta;
+    if (k == 0) {
+        beta = 0.0;
+        alpha = gamma / delta;
+    } else {
+        const double alpha_old = w.scal[6 + 2 * nxt], gamma_old = w.scal[7 + 2 * nxt];
+        beta = gamma / gamma_old;
+        alpha = gamma / (delta - beta * gamma / alpha_old);
+    }
+    const double *rk = w.vec + cur * n, *wk_ = w.vec + (2 + cur) * n, *sk1 = w.vec + (4 + nxt) * n;
+    double *rn = w.vec + nxt * n, *wn = w.vec + (2 + nxt) * n, *sk = w.vec + (4 + cur) * n, *pp = w.vec + 6 * n;
+    double *x = pcg_x(v, mode);
+    double ga = 0.0, de = 0.0;
+    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < n; r += (int64_t)w.nblk * blockDim.x) {
+        const double ui = w.dinv[r] * rk[r];
+        const double pi = ui + beta * pp[r];
+        const double si = wk_[r] + beta * sk1[r];
+        pp[r] = pi;
+        sk[r] = si;
+        x[r] += alpha * pi;
+        const double ri = rk[r] - alpha * si;
+        rn[r] = ri;
+        const double un = w.dinv[r] * ri;
+        double au = 0.0;
+        for (int32_t q = w.row_ptr[r]; q < w.row_ptr[r + 1]; ++q) {
+            const int32_t j = w.col[q];
+            const double sj = wk_[j] + beta * sk1[j];
+            au += w.val[q] * (w.dinv[j] * (rk[j] - alpha * sj));
+        }
+        wn[r] = au;
+        ga += ri * un;
+        de += au * un;
+    }
+    ga = block_sum(ga, lds);
+    de = block_sum(de, lds);
     if (threadIdx.x == 0) {
-        prz_next[it.b] = acc;
-        if (it.b == 0) w.scal[5] = k + 1;
+        pout[it.b] = ga;
+        pout[w.nblk + it.b] = de;
+        if (it.b == 0) {
+            if (k == 0) w.scal[1] = gamma;
+            w.scal[6 + 2 * cur] = alpha;
+            w.scal[7 + 2 * cur] = gamma;
+            w.scal[5] = k + 1;
+        }
     }
 }
 
@@ -852,17 +930,13 @@ void launch_pcg_block(const DeviceView *vs, const WorkItem *wk, int n, int mode,
     hipLaunchKernelGGL(k_pcg_block, dim3(n), dim3(1024), 0, st, vs, wk, mode, rtol2_o, max_o);
 }
 
-void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, const WorkItem *wk_one, int n_one, int mode,
-                      int max_iter, hipStream_t st) {
+void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, int mode, int max_iter, hipStream_t st) {
     if (n <= 0) return;
     const double rtol2_o = mode == 1 ? 1e-24 : -1.0;
     const int max_o = mode == 1 ? max_iter : -1;
-    hipLaunchKernelGGL(k_pcg_init, dim3(n), dim3(256), 0, st, vs, wk, mode);
-    hipLaunchKernelGGL(k_pcg_rz0, dim3(n_one), dim3(256), 0, st, vs, wk_one, mode);
-    for (int k = 0; k < max_iter; ++k) {
-        hipLaunchKernelGGL(k_pcg_dir, dim3(n), dim3(256), 0, st, vs, wk, mode, k, rtol2_o, max_o);
-        hipLaunchKernelGGL(k_pcg_step, dim3(n), dim3(256), 0, st, vs, wk, mode, k, rtol2_o, max_o);
-    }
+    hipLaunchKernelGGL(k_cg1_init, dim3(n), dim3(256), 0, st, vs, wk, mode);
+    for (int k = 0; k < max_iter; ++k)
+        hipLaunchKernelGGL(k_cg1_iter, dim3(n), dim3(256), 0, st, vs, wk, mode, k, rtol2_o, max_o);
 }
 
 void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, hipStream_t st) {

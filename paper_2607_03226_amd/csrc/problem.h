@@ -71,7 +71,6 @@ class Runner {
         int kind;              // see the enum in runner.cpp
         bool fp32 = false;
         int off = 0, n = 0;    // work items [off, off + n)
-        int off1 = 0, n1 = 0;  // second table (PCG: one item per solve)
         int maxin = 0, bpl = 1, block = 256, iters = 0;
         bool spill = false;
         size_t lds = 0;
@@ -130,7 +129,7 @@ struct nbte_problem {
     nbte::DevBuf d_Lrow, d_Lcol, d_Lval, d_Ldinv;
     nbte::DevBuf d_g, d_gval, d_Jw, d_Q;
     nbte::DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta;
-    nbte::DevBuf d_pcg_r, d_pcg_z, d_pcg_p, d_pcg_Ap, d_pcg_part, d_pcg_scal;
+    nbte::DevBuf d_pcg_vec, d_pcg_part, d_pcg_scal;
     nbte::DevBuf d_view, d_state, d_self_work;
     int pcg_nblk = 1;
 

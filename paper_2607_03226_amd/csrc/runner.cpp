@@ -103,7 +103,7 @@ void Runner::build() {
         L.fp32 = f;
         L.off = (int)work.size();
         each(f, [&](int s, nbte_problem &p) {
-            const int64_t nb0 = std::min<int64_t>(cdiv(p.mesh->NBF * p.bands.B, 256), 1024);
+            const int64_t nb0 = std::min<int64_t>(cdiv(p.mesh->NBF, 4), 2048);   // a wave per face
             const int64_t nb1 = std::min<int64_t>(cdiv((int64_t)p.quad.D * p.mesh->N, 256), 2048);
             for (int64_t b = 0; b < nb0; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb0});
             for (int64_t b = 0; b < nb1; ++b) work.push_back({s, 1, (int32_t)b, (int32_t)nb1});
@@ -220,14 +220,7 @@ void Runner::build() {
             for (int b = 0; b < p.pcg_nblk; ++b) work.push_back({s, 0, b, p.pcg_nblk});
             G.iters = std::max(G.iters, p.cg_max_iter());
         }
-        G.n = (int)work.size() - G.off;
-        G.off1 = (int)work.size();
-        for (int s = 0; s < M; ++s) {
-            const nbte_problem &p = *members_[s];
-            if (p.synthetic() && p.mesh->N > kPcgBlockMaxRows) work.push_back({s, 0, 0, 1});
-        }
-        G.n1 = (int)work.size() - G.off1;
-        if (G.n > 0) seq_.push_back(G);
+        close(G);
     }
 
     mark(PH_UPD);
@@ -278,7 +271,7 @@ void Runner::enqueue_iteration(int slot) {
             case K_MOM: launch_moments(vs, wk + L.off, L.n, L.fp32, stream_); break;
             case K_PCG_BLOCK: launch_pcg_block(vs, wk + L.off, L.n, 0, stream_); break;
             case K_PCG_MULTI:
-                launch_pcg_multi(vs, wk + L.off, L.n, wk + L.off1, L.n1, 0, L.iters, stream_);
+                launch_pcg_multi(vs, wk + L.off, L.n, 0, L.iters, stream_);
                 break;
             case K_UPDATE: launch_update(vs, wk + L.off, L.n, stream_); break;
             case K_FINISH: launch_finish(vs, wk + L.off, L.n, stream_); break;

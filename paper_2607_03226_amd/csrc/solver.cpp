@@ -218,9 +218,9 @@ void nbte_problem::upload_device() {
         upload(d_Lval, diff.val, stream);
         upload(d_Ldinv, dinv, stream);
         pcg_nblk = (int)std::min<int64_t>(256, cdiv(m.N, 256));
-        for (DevBuf *b : {&d_pcg_r, &d_pcg_z, &d_pcg_p, &d_pcg_Ap}) b->alloc(m.N * sizeof(double));
-        d_pcg_part.alloc(3 * 256 * sizeof(double));
-        d_pcg_scal.alloc(8 * sizeof(double));
+        d_pcg_vec.alloc(7 * m.N * sizeof(double));
+        d_pcg_part.alloc(4 * 256 * sizeof(double));
+        d_pcg_scal.alloc(16 * sizeof(double));
         diff_up = true;
     }
     NBTE_HIP(hipStreamSynchronize(stream));
@@ -257,7 +257,7 @@ int64_t nbte_problem::device_bytes() const {
           &d_pq, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
           &d_mirror, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_g, &d_gval,
           &d_Jw, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
-          &d_pcg_r, &d_pcg_z, &d_pcg_p, &d_pcg_Ap, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work})
+          &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -329,10 +329,7 @@ void nbte_problem::make_view() {
     w.col = d_Lcol.as<int32_t>();
     w.val = d_Lval.as<double>();
     w.dinv = d_Ldinv.as<double>();
-    w.r = d_pcg_r.as<double>();
-    w.z = d_pcg_z.as<double>();
-    w.p = d_pcg_p.as<double>();
-    w.Ap = d_pcg_Ap.as<double>();
+    w.vec = d_pcg_vec.as<double>();
     w.partial = d_pcg_part.as<double>();
     w.scal = d_pcg_scal.as<double>();
     hv = v;
@@ -405,8 +402,8 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
         if (m.N <= kPcgBlockMaxRows)
             launch_pcg_block(vp, wk + self_one, 1, 1, stream);
         else
-            launch_pcg_multi(vp, wk + self_pcg, n_self_pcg, wk + self_one, 1, 1,
-                             std::max(1000, (int)std::sqrt((double)m.N) * 20), stream);
+            launch_pcg_multi(vp, wk + self_pcg, n_self_pcg, 1, std::max(1000, (int)std::sqrt((double)m.N) * 20),
+                             stream);
     }
     // g = 0 is equilibrium at theta^0; the stored g is relative to theta[prev]
     NBTE_HIP(hipMemcpyAsync(d_theta[1].ptr, th0, m.N * 8, hipMemcpyDeviceToDevice, stream));
@@ -792,7 +789,7 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
         // level tables (at most one level per cell), streams cell/slot/refs/coefs/outflow/theta/Q, inflow rows
         const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * 12 + 8 + 8 + 8) + NBF * D * 4;
         const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * D * (8 + 4);
-        const int64_t lh = N * (F + 1) * 12 + N * 8 * 5 + 256 * 3 * 8;
+        const int64_t lh = N * (F + 1) * 12 + N * 8 * 8 + 256 * 4 * 8;
         *bytes = geo + sched + plan + lh + p->state_bytes(precision);
         return NBTE_OK;
     });

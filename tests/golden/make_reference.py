@@ -5,7 +5,7 @@ tests/golden/<name>_reference.npz with the converged T_L, T and q at a seeded
 sample of cells plus the global error scales (max |T_L - T_ref|, max |T - T_ref|,
 max ||q||) and the oracle's iteration count, residual and energy defect.
 
-Usage: python tests/golden/make_reference.py config2 [config3]
+Usage: python tests/golden/make_reference.py config2 [config3] [porous_10k]
 """
 import os
 import sys
@@ -19,11 +19,18 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 from workloads import configs as C  # noqa: E402
 
-MAKERS = {"config2": C.config2, "config3": C.config3}
+MAKERS = {
+    "config2": C.config2,
+    "config3": C.config3,
+    # porous film above the one-workgroup PCG limit of the GPU path (all cells stored)
+    "porous_10k": lambda: C.porous_problem(4242, n_lo=9000, n_hi=11000),
+}
+SAMPLE = {"porous_10k": 1 << 30}
 
 
 def make(name, n_sample=4096, tol=1e-12, defect_tol=1e-10, time_limit=None):
     p = MAKERS[name]()
+    n_sample = SAMPLE.get(name, n_sample)
     t0 = time.time()
     r = oracle.solve(p, tol=tol, defect_tol=defect_tol, max_iter=100000, verbose=True, time_limit=time_limit)
     idx = np.sort(np.random.default_rng(12345).choice(p.n_cells, size=min(n_sample, p.n_cells), replace=False))
