@@ -72,7 +72,7 @@ struct DeviceView {
     int32_t lpc;            // sweep lanes per cell
     int32_t bpb;            // sweep bands per workgroup
     int32_t gcap;           // ghosts per level kept in LDS
-    int32_t pad0;
+    int32_t lstride;        // LDS stride (doubles) of one staged value's bands
     const int32_t NBTE_G *lvl_ptr; // per direction L_i + 1 level offsets, concatenated
     const int32_t NBTE_G *lvl_off; // D+1: start of direction i's entries in lvl_ptr
     const int32_t NBTE_G *gptr;    // ghost offsets per level (layout of lvl_ptr)
@@ -130,11 +130,18 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
 
 // One sweep launch over a work list (solve, direction, band block).  All
 // items share the kernel variant (storage type, fan-in bound maxin, bands per
-// lane, spill mode) and the workgroup size; lds_bytes is the largest LDS need
-// among their solves.
-void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool spill,
+// lane, mode) and the workgroup size; lds_bytes is the largest LDS need among
+// their solves.  mode: 0 every upwind value in LDS; 1 some boundary inflow
+// read from HBM (levels with more ghosts than the LDS buffer holds); 2 some
+// values spilled to HBM (LDS budget too small).  one: one lane per cell
+// (bpl = bands per block, up to 8); otherwise bpl is 1, 2 or 4.
+void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
                   int block, size_t lds_bytes, hipStream_t st);
-size_t sweep_lds_bytes(int max_levels, int gcap, int bpb, int slots);
+size_t sweep_lds_bytes(int max_levels, int gcap, int lstride, int slots);
+// LDS stride (doubles) of a staged value's bands: they are contiguous, so
+// two-band blocks are read with 16-byte LDS loads (padding the stride to an
+// odd count, to spread random slots over the banks, measured slower)
+inline int sweep_lds_stride(int bpb) { return bpb; }
 
 // PCG of the synthetic correction for a list of solves.
 //   mode 0: solve L delta = rhs (every iteration);

@@ -202,8 +202,8 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
 extern __shared__ double sweep_lds[];
 extern __shared__ int sweep_ldsi[];   // the same memory viewed as ints (level tables)
 
-constexpr int kGhostPerThread = 4;    // ghost values a thread prefetches per level
-constexpr int kItemsPerThread = 2;    // cells per thread and level with prefetched records
+constexpr int kGhostPerThread = 2;    // ghost values a thread prefetches per level
+constexpr int kPrefetch = 4;          // passes whose records are in flight ahead of the computed one
 // record references: >= 0 LDS slot; [-kSpill, -1] ghost of the level in LDS (rank);
 // [-2 kSpill, -kSpill - 1] ghost read from HBM (row); below: spilled cell
 constexpr int32_t kSpill = 1 << 24;
@@ -250,7 +250,7 @@ struct BandConst {
 
 template <class T, int MI, int BPL>
 __device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceView &v, const BandConst<BPL> &bc,
-                                           T *gi, int64_t base, int ring_off, int gbuf_off, int bands_per_block,
+                                           T *gi, int64_t base, int ring_off, int gbuf_off, int ls,
                                            int b0, int lane, int nb_here) {
     const int B = v.B;
 #pragma unroll
@@ -267,9 +267,9 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceVi
             const int rf = r.ref[j];
             double up;
             if (rf >= 0) {
-                up = sweep_lds[ring_off + rf * bands_per_block + lb];
+                up = sweep_lds[ring_off + rf * ls + lb];
             } else if (rf >= -kSpill) {
-                up = sweep_lds[gbuf_off + (-1 - rf) * bands_per_block + lb];
+                up = sweep_lds[gbuf_off + (-1 - rf) * ls + lb];
             } else if (rf >= -2 * kSpill) {
                 up = v.gval[(int64_t)(-kSpill - 1 - rf) * B + lam];   // ghost beyond the LDS capacity
             } else {
@@ -284,7 +284,46 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceVi
         const double vel = bc.vel[jb];
         const double e = (cw * r.th * itau + r.Q * bc.src[jb] + vel * gain) / (itau + vel * r.sout);
         gi[(int64_t)r.c * B + lam] = static_cast<T>(e - cw * r.th);
-        if (r.mine >= 0) sweep_lds[ring_off + r.mine * bands_per_block + lb] = e;
+        if (r.mine >= 0) sweep_lds[ring_off + r.mine * ls + lb] = e;
+    }
+}
+
+// The common case: every upwind reference is an LDS slot or a ghost kept in
+// LDS (no spilled values, no ghost beyond the LDS capacity).  Branch-free:
+// one LDS offset per reference shared by the bands, unused references
+// (coefficient 0) masked by a select, past-the-end records computed but not
+// stored, so the items of a thread interleave.
+template <class T, int MI, int BPL>
+__device__ __forceinline__ void sweep_cell_lds(const SweepRec<MI> &r, const BandConst<BPL> &bc, T *gi, int B,
+                                               int ring_off, int gbuf_off, int ls, int b0, int lane,
+                                               int nb_here) {
+    int off[MI];
+#pragma unroll
+    for (int j = 0; j < MI; ++j) {
+        const int rf = r.ref[j];
+        off[j] = rf >= 0 ? ring_off + rf * ls : gbuf_off + (-1 - rf) * ls;
+    }
+    T *gc = gi + (int64_t)r.c * B + b0;
+    const int mine = ring_off + r.mine * ls;
+#pragma unroll
+    for (int jb = 0; jb < BPL; ++jb) {
+        const int lb = lane * BPL + jb;
+        const bool on = r.ok && lb < nb_here;
+        const int lr = lb < ls ? lb : ls - 1;   // lanes past the block read in range
+        const double cw = bc.cw[jb];
+        const double itau = bc.itau[jb];
+        double gain = 0.0;
+#pragma unroll
+        for (int j = 0; j < MI; ++j) {
+            const double up = sweep_lds[off[j] + lr];
+            gain += r.cf[j] != 0.0 ? r.cf[j] * up : 0.0;
+        }
+        const double vel = bc.vel[jb];
+        const double e = (cw * r.th * itau + r.Q * bc.src[jb] + vel * gain) / (itau + vel * r.sout);
+        if (on) {
+            gc[lb] = static_cast<T>(e - cw * r.th);
+            if (r.mine >= 0) sweep_lds[mine + lb] = e;
+        }
     }
 }
 
@@ -292,6 +331,11 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceVi
 // sweep is read back by it, so the barrier only has to order LDS; the fences
 // are restricted to the LDS address space.  With spilled values the full
 // workgroup fence also orders the global stores.
+// sweep kernel modes: references only in LDS; LDS plus ghosts read from HBM;
+// plus spilled values (stored copies read back, so the level barrier orders
+// global memory too)
+enum SweepMode { kModeLds = 0, kModeHbmGhost = 1, kModeSpill = 2 };
+
 template <bool SPILL>
 __device__ __forceinline__ void level_barrier() {
     if constexpr (SPILL) {
@@ -304,24 +348,26 @@ __device__ __forceinline__ void level_barrier() {
 }
 
 // --------------------------------------------------------------------------
-// Pipeline per level l (after the barrier that ends level l-1):
-//   1. request the records and the ghost values (boundary inflow) of level
-//      l+2 into registers;
-//   2. compute level l from registers (records requested at level l-2), the
-//      LDS ring (upwind values) and ghost buffer l&1 (stored during level l-1);
-//   3. store the ghost values of level l+1 (requested at level l-1) into
-//      ghost buffer (l+1)&1;
-//   4. barrier.
-// Every wait is on loads issued before the current level's record requests.
-// The level loop is unrolled three ways so a record keeps its registers while
-// its loads are in flight (moving it would force the wait).
+// Pipeline: the cells of a direction are processed in passes (up to one
+// cell per slot, all of one level).  While pass q is computed from registers
+// (records requested kPrefetch passes earlier), the LDS ring (upwind values)
+// and the level's ghost buffer, the records of pass q + kPrefetch are
+// requested.  Every wait is on loads issued at least kPrefetch passes
+// earlier; past-the-end requests read valid positions so the number of loads
+// in flight is the same on every path.  The step ring is unrolled so a record
+// keeps its registers while its loads are in flight (moving it would force
+// the wait).
 // --------------------------------------------------------------------------
-template <class T, int MI, int BPL, bool SPILL>
+template <class T, int MI, int BPL, int MODE, bool ONE>
 __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs,
                                                 const WorkItem *__restrict__ wk) {
+    // ONE: one lane per cell (it sweeps all BPL bands of the block), so the
+    // band of a register is the same on every lane and the band constants are
+    // workgroup-uniform (scalar loads, scalar registers)
     // dynamic LDS: [lvl_ptr | gptr of this direction: 2 (max_levels + 1) ints]
-    //              [ghost buffers: 2 x gcap x bands_per_block doubles]
-    //              [ring: slot x bands_per_block doubles]
+    //              [ghost buffers: 2 x gcap x ls doubles]
+    //              [ring: slot x ls doubles]
+    // ls = LDS stride of one staged value's bands
     const WorkItem tk = wk[blockIdx.x];
     if (tk.solve < 0) return;   // padding of the XCD-ordered work list
     const DeviceView v = vs[tk.solve];   // a copy: fields stay in registers across the stores
@@ -331,9 +377,9 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     const int gcap = v.gcap;
     const int i = tk.a;
     const int b0 = tk.b * bands_per_block;
-    const int slot = threadIdx.x / lpc;
-    const int lane = threadIdx.x % lpc;
-    const int nslots = blockDim.x / lpc;
+    const int slot = ONE ? (int)threadIdx.x : (int)threadIdx.x / lpc;
+    const int lane = ONE ? 0 : (int)threadIdx.x % lpc;
+    const int nslots = ONE ? (int)blockDim.x : (int)blockDim.x / lpc;
     const int64_t N = v.N;
     const int B = v.B;
     const int64_t DN = (int64_t)v.D * N;
@@ -345,7 +391,8 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
 #define lp(t) sweep_ldsi[(t)]
 #define gp(t) sweep_ldsi[ML + (t)]
     const int gbuf0 = ML;                               // 2*ML ints = ML doubles
-    const int gstride = gcap * bands_per_block;         // ghosts of a level kept in LDS (rank < gcap)
+    const int ls = v.lstride;
+    const int gstride = gcap * ls;                      // ghosts of a level kept in LDS (rank < gcap)
     const int ring_off = gbuf0 + 2 * gstride;
     {
         const int32_t *glp = v.lvl_ptr + v.lvl_off[i];
@@ -367,17 +414,24 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     }
     __syncthreads();
 
-    // ghost values of one level: entry e = q * bands_per_block + local band.
-    // They travel with the records of their level: requested two levels ahead
-    // into registers, stored into the level's LDS buffer at the end of the
-    // level before it.
+    // The sweep of a direction as a sequence of passes: pass = up to nslots
+    // cells of one level, one cell per slot.  Records are requested
+    // kPrefetch passes ahead into a ring of kPrefetch + 1 register sets, so
+    // wide levels (many passes) and narrow ones (one pass each) hide the
+    // load latency alike.  A barrier ends each level.  Ghost values (boundary
+    // inflow) of a level ride with the records of its first pass and are
+    // stored into the level's LDS buffer just before the level starts.
     struct Ghosts {
         double v[kGhostPerThread];
     };
-    auto ghost_load = [&](Ghosts &h, int l) {
+    struct Set {
+        SweepRec<MI> r;
+        Ghosts h;
+    };
+    auto ghost_load = [&](Ghosts &h, int l, bool first) {
         // branch-free like load_rec: entries past the level read element 0
         const int ll = l < nlev ? l : nlev - 1;
-        const int g0 = gp(ll), ne = l < nlev ? min(gp(ll + 1) - g0, gcap) * bands_per_block : 0;
+        const int g0 = gp(ll), ne = (first && l < nlev) ? min(gp(ll + 1) - g0, gcap) * bands_per_block : 0;
 #pragma unroll
         for (int m = 0; m < kGhostPerThread; ++m) {
             const int e = threadIdx.x + m * blockDim.x;
@@ -388,62 +442,72 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
         }
     };
     auto ghost_store = [&](const Ghosts &h, int l) {
-        if (l >= nlev) return;
         const int dst = gbuf0 + (l & 1) * gstride;
         const int g0 = gp(l), ne = min(gp(l + 1) - g0, gcap) * bands_per_block;
 #pragma unroll
         for (int m = 0; m < kGhostPerThread; ++m) {
             const int e = threadIdx.x + m * blockDim.x;
-            if (e < ne) sweep_lds[dst + e] = h.v[m];
+            const int q = e / bands_per_block, lb = e - q * bands_per_block;
+            if (e < ne) sweep_lds[dst + q * ls + lb] = h.v[m];
         }
         // levels with more ghosts than the registers hold: direct copy
 #pragma nounroll
         for (int e = threadIdx.x + kGhostPerThread * blockDim.x; e < ne; e += blockDim.x) {
             const int q = e / bands_per_block, lb = e - q * bands_per_block;
-            sweep_lds[dst + e] = lb < nb_here ? v.gval[(int64_t)(g0 + q) * B + b0 + lb] : 0.0;
+            sweep_lds[dst + q * ls + lb] = lb < nb_here ? v.gval[(int64_t)(g0 + q) * B + b0 + lb] : 0.0;
         }
     };
-
-    SweepRec<MI> q0[kItemsPerThread], q1[kItemsPerThread], q2[kItemsPerThread];
-    Ghosts h0, h1, h2;
-    auto fetch = [&](SweepRec<MI> (&r)[kItemsPerThread], Ghosts &h, int l) {
-        const int ll = l < nlev ? l : nlev - 1;
-        const int kend = l < nlev ? lp(ll + 1) : 0;
-#pragma unroll
-        for (int p = 0; p < kItemsPerThread; ++p) load_rec(r[p], v, base, DN, lp(ll) + slot + p * nslots, kend);
-        ghost_load(h, l);
-    };
-    // level l: request level l+2, compute level l, store the ghosts of level
-    // l+1 (requested during level l-1), barrier
-    auto step = [&](int l, SweepRec<MI> (&cur)[kItemsPerThread], const Ghosts &h1n,
-                    SweepRec<MI> (&n2)[kItemsPerThread], Ghosts &h2n) {
-        fetch(n2, h2n, l + 2);
-        const int gcur = gbuf0 + (l & 1) * gstride;
-#pragma unroll
-        for (int p = 0; p < kItemsPerThread; ++p)
-            if (cur[p].ok)
-                sweep_cell<T, MI, BPL>(cur[p], v, bc, gi, base, ring_off, gcur, bands_per_block, b0, lane, nb_here);
-        // cells beyond kItemsPerThread per slot in a very wide level: no prefetch
-#pragma nounroll
-        for (int k = lp(l) + slot + kItemsPerThread * nslots; k < lp(l + 1); k += nslots) {
-            SweepRec<MI> rx;
-            load_rec(rx, v, base, DN, k, lp(l + 1));
-            sweep_cell<T, MI, BPL>(rx, v, bc, gi, base, ring_off, gcur, bands_per_block, b0, lane, nb_here);
+    // pass cursors (uniform): level and first position of the pass
+    int lf = 0, kf = lp(0);   // next pass to request
+    int lc = 0, kc = lp(0);   // next pass to compute
+    auto fetch = [&](Set &st) {
+        const bool live = lf < nlev;
+        const int kend = live ? lp(lf + 1) : 0;
+        load_rec(st.r, v, base, DN, kf + slot, kend);
+        ghost_load(st.h, lf, live && kf == lp(lf));
+        if (live) {
+            kf += nslots;
+            if (kf >= kend) {
+                ++lf;
+                kf = lp(lf);
+            }
         }
-        ghost_store(h1n, l + 1);
-        level_barrier<SPILL>();
     };
-    fetch(q0, h0, 0);
-    fetch(q1, h1, 1);
-    ghost_store(h0, 0);
+    // compute the pass in `cur`, request a new pass into `nxt` (the set
+    // computed last, now free); returns false when the sweep is done
+    auto step = [&](Set &cur, Set &nxt, const Set &after) -> bool {
+        fetch(nxt);
+        const int gcur = gbuf0 + (lc & 1) * gstride;
+        if constexpr (MODE == kModeLds)
+            sweep_cell_lds<T, MI, BPL>(cur.r, bc, gi, B, ring_off, gcur, ls, b0, lane, nb_here);
+        else if (cur.r.ok)
+            sweep_cell<T, MI, BPL>(cur.r, v, bc, gi, base, ring_off, gcur, ls, b0, lane, nb_here);
+        kc += nslots;
+        if (kc >= lp(lc + 1)) {   // level done
+            ++lc;
+            if (lc < nlev) {
+                kc = lp(lc);
+                ghost_store(after.h, lc);   // the next pass opens level lc
+            }
+            level_barrier<MODE == kModeSpill>();
+        }
+        return lc < nlev;
+    };
+    Set s0, s1, s2, s3, s4;
+    static_assert(kPrefetch == 4, "the step ring below is written for four passes in flight");
+    fetch(s0);
+    fetch(s1);
+    fetch(s2);
+    fetch(s3);
+    ghost_store(s0.h, 0);
     __syncthreads();
 #pragma nounroll
-    for (int l = 0; l < nlev; l += 3) {
-        step(l, q0, h1, q2, h2);
-        if (l + 1 >= nlev) break;
-        step(l + 1, q1, h2, q0, h0);
-        if (l + 2 >= nlev) break;
-        step(l + 2, q2, h0, q1, h1);
+    while (true) {
+        if (!step(s0, s4, s1)) break;
+        if (!step(s1, s0, s2)) break;
+        if (!step(s2, s1, s3)) break;
+        if (!step(s3, s2, s4)) break;
+        if (!step(s4, s3, s0)) break;
     }
 }
 #undef lp
@@ -845,31 +909,40 @@ __global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__
     }
 }
 
-template <class T, int MI, bool SPILL>
-void dispatch_sweep_bpl(const DeviceView *vs, const WorkItem *wk, int n, int bpl, int block, size_t lds,
+template <class T, int MI, int MODE>
+void dispatch_sweep_bpl(const DeviceView *vs, const WorkItem *wk, int n, int bpl, bool one, int block, size_t lds,
                         hipStream_t st) {
     dim3 grid(n);
+    if (one) {
+        switch (bpl) {
+            case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, MODE, true>), grid, dim3(block), lds, st, vs, wk); break;
+            case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, MODE, true>), grid, dim3(block), lds, st, vs, wk); break;
+            case 4: hipLaunchKernelGGL((k_sweep<T, MI, 4, MODE, true>), grid, dim3(block), lds, st, vs, wk); break;
+            default: hipLaunchKernelGGL((k_sweep<T, MI, 8, MODE, true>), grid, dim3(block), lds, st, vs, wk); break;
+        }
+        return;
+    }
     switch (bpl) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, SPILL>), grid, dim3(block), lds, st, vs, wk); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, SPILL>), grid, dim3(block), lds, st, vs, wk); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, MI, 4, SPILL>), grid, dim3(block), lds, st, vs, wk); break;
-        default: hipLaunchKernelGGL((k_sweep<T, MI, 8, SPILL>), grid, dim3(block), lds, st, vs, wk); break;
+        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, MODE, false>), grid, dim3(block), lds, st, vs, wk); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, MODE, false>), grid, dim3(block), lds, st, vs, wk); break;
+        default: hipLaunchKernelGGL((k_sweep<T, MI, 4, MODE, false>), grid, dim3(block), lds, st, vs, wk); break;
     }
 }
 
+template <class T, int MODE>
+void dispatch_sweep_mi(const DeviceView *vs, const WorkItem *wk, int n, int maxin, int bpl, bool one, int block,
+                       size_t lds, hipStream_t st) {
+    if (maxin <= 2) dispatch_sweep_bpl<T, 2, MODE>(vs, wk, n, bpl, one, block, lds, st);
+    else if (maxin == 3) dispatch_sweep_bpl<T, 3, MODE>(vs, wk, n, bpl, one, block, lds, st);
+    else dispatch_sweep_bpl<T, 5, MODE>(vs, wk, n, bpl, one, block, lds, st);
+}
+
 template <class T>
-void dispatch_sweep(const DeviceView *vs, const WorkItem *wk, int n, int maxin, int bpl, bool spill, int block,
-                    size_t lds, hipStream_t st) {
-    const int mi = maxin <= 2 ? 2 : (maxin == 3 ? 3 : 5);
-    if (spill) {
-        if (mi == 2) dispatch_sweep_bpl<T, 2, true>(vs, wk, n, bpl, block, lds, st);
-        else if (mi == 3) dispatch_sweep_bpl<T, 3, true>(vs, wk, n, bpl, block, lds, st);
-        else dispatch_sweep_bpl<T, 5, true>(vs, wk, n, bpl, block, lds, st);
-    } else {
-        if (mi == 2) dispatch_sweep_bpl<T, 2, false>(vs, wk, n, bpl, block, lds, st);
-        else if (mi == 3) dispatch_sweep_bpl<T, 3, false>(vs, wk, n, bpl, block, lds, st);
-        else dispatch_sweep_bpl<T, 5, false>(vs, wk, n, bpl, block, lds, st);
-    }
+void dispatch_sweep(const DeviceView *vs, const WorkItem *wk, int n, int maxin, int bpl, bool one, int mode,
+                    int block, size_t lds, hipStream_t st) {
+    if (mode == kModeLds) dispatch_sweep_mi<T, kModeLds>(vs, wk, n, maxin, bpl, one, block, lds, st);
+    else if (mode == kModeHbmGhost) dispatch_sweep_mi<T, kModeHbmGhost>(vs, wk, n, maxin, bpl, one, block, lds, st);
+    else dispatch_sweep_mi<T, kModeSpill>(vs, wk, n, maxin, bpl, one, block, lds, st);
 }
 
 }  // namespace
@@ -909,18 +982,18 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
     hipLaunchKernelGGL(k_finish, dim3((n + 63) / 64), dim3(64), 0, st, vs, wk, n);
 }
 
-size_t sweep_lds_bytes(int max_levels, int gcap, int bpb, int slots) {
-    return (size_t)(max_levels + 1) * sizeof(double)             // two int level tables
-           + (size_t)2 * gcap * bpb * sizeof(double)              // ghost buffers
-           + (size_t)std::max(slots, 1) * bpb * sizeof(double);   // staged values
+size_t sweep_lds_bytes(int max_levels, int gcap, int ls, int slots) {
+    return (size_t)(max_levels + 1) * sizeof(double)            // two int level tables
+           + (size_t)2 * gcap * ls * sizeof(double)              // ghost buffers
+           + (size_t)std::max(slots, 1) * ls * sizeof(double);   // staged values
 }
 
-void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool spill,
+void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
                   int block, size_t lds_bytes, hipStream_t st) {
     if (n <= 0) return;
     if (bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8) bpl = 1;
-    if (fp32) dispatch_sweep<float>(vs, wk, n, maxin, bpl, spill, block, lds_bytes, st);
-    else dispatch_sweep<double>(vs, wk, n, maxin, bpl, spill, block, lds_bytes, st);
+    if (fp32) dispatch_sweep<float>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st);
+    else dispatch_sweep<double>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st);
 }
 
 void launch_pcg_block(const DeviceView *vs, const WorkItem *wk, int n, int mode, hipStream_t st) {

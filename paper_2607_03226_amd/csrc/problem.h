@@ -72,7 +72,8 @@ class Runner {
         bool fp32 = false;
         int off = 0, n = 0;    // work items [off, off + n)
         int maxin = 0, bpl = 1, block = 256, iters = 0;
-        bool spill = false;
+        int mode = 0;   // sweep kernel mode (launch_sweep)
+        bool one = false;   // one lane per cell
         size_t lds = 0;
     };
     void build();

@@ -114,13 +114,14 @@ void Runner::build() {
     mark(PH_SWEEP);
     {
         // group by kernel variant; inside a group, XCD-aware longest-first order
-        using Key = std::tuple<int, int, int, int, int>;   // fp32, maxin class, bpl, spill, block
+        using Key = std::tuple<int, int, int, int, int, int>;   // fp32, maxin class, bpl, mode, block, one
         std::map<Key, std::vector<int>> groups;
         for (int s = 0; s < M; ++s) {
             const nbte_problem &p = *members_[s];
             const int mi = p.prog.maxin <= 2 ? 2 : (p.prog.maxin == 3 ? 3 : 5);
             const bool spill = p.shape.slots == 0 || p.sched.spilled > 0;
-            groups[Key(p.fp32() ? 1 : 0, mi, p.shape.bpl, spill ? 1 : 0, p.shape.block)].push_back(s);
+            const int mode = spill ? 2 : (p.prog.max_ghosts > p.shape.gcap ? 1 : 0);
+            groups[Key(p.fp32() ? 1 : 0, mi, p.shape.bpl, mode, p.shape.block, p.hv.lpc == 1 ? 1 : 0)].push_back(s);
         }
         for (auto &kv : groups) {
             struct Unit {
@@ -134,7 +135,7 @@ void Runner::build() {
                 const int nbb = (int)cdiv(p.bands.B, p.shape.bpb);
                 const int lpc = p.hv.lpc;
                 const int nslots = std::max(1, p.shape.block / lpc);
-                lds = std::max(lds, sweep_lds_bytes(p.sched.max_levels, p.shape.gcap, p.shape.bpb,
+                lds = std::max(lds, sweep_lds_bytes(p.sched.max_levels, p.shape.gcap, p.hv.lstride,
                                                     std::max(p.sched.max_slots, 1)));
                 for (int i = 0; i < p.quad.D; ++i) {
                     // passes over the cells of direction i: one per level and slot row
@@ -164,7 +165,8 @@ void Runner::build() {
             L.fp32 = std::get<0>(kv.first) != 0;
             L.maxin = std::get<1>(kv.first);
             L.bpl = std::get<2>(kv.first);
-            L.spill = std::get<3>(kv.first) != 0;
+            L.mode = std::get<3>(kv.first);
+            L.one = std::get<5>(kv.first) != 0;
             L.block = std::get<4>(kv.first);
             L.lds = lds;
             L.off = (int)work.size();
@@ -265,7 +267,7 @@ void Runner::enqueue_iteration(int slot) {
                 break;
             case K_STAGE: launch_stage(vs, wk + L.off, L.n, L.fp32, stream_); break;
             case K_SWEEP:
-                launch_sweep(vs, wk + L.off, L.n, L.fp32, L.maxin, L.bpl, L.spill, L.block, L.lds, stream_);
+                launch_sweep(vs, wk + L.off, L.n, L.fp32, L.maxin, L.bpl, L.one, L.mode, L.block, L.lds, stream_);
                 break;
             case K_FLUX: launch_flux(vs, wk + L.off, L.n, L.fp32, 0, stream_); break;
             case K_MOM: launch_moments(vs, wk + L.off, L.n, L.fp32, stream_); break;

@@ -92,6 +92,12 @@ nbte_problem::Shape nbte_problem::resolve_shape() const {
     if (bpl > 8) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block too large for 8 bands per lane");
     int lanes = (bpb + bpl - 1) / bpl, lpc = 1;
     while (lpc < lanes) lpc <<= 1;
+    if (lpc > 1 && bpl > 4) {   // eight bands per lane only with one lane per cell
+        bpl = 4;
+        lanes = (bpb + bpl - 1) / bpl;
+        lpc = 1;
+        while (lpc < lanes) lpc <<= 1;
+    }
     int block = tuning.block_size > 0 ? tuning.block_size : 256;
     block = std::min(std::max(block, lpc), 512);   // the sweep kernel is built for <= 512 threads
     sh.bpb = bpb;
@@ -101,13 +107,14 @@ nbte_problem::Shape nbte_problem::resolve_shape() const {
     // workgroup's LDS with the staged values; at most a quarter of the budget
     // goes to ghosts, larger boundary levels read the rest from HBM
     const int table = ((sched_ok ? sched.max_levels : 0) + 1) * 8;
+    const int ls = sweep_lds_stride(bpb);
     const int total = tuning.lds_bytes == 0 ? 65536 : std::min(std::abs(tuning.lds_bytes), 65536);
-    sh.gcap = std::min(sched_ok ? sched.max_ghosts : 0, std::max(1, total / 4 / (2 * bpb * 8)));
-    const int ghosts = 2 * sh.gcap * bpb * 8;
-    if (table + ghosts > 65536 - 8 * bpb)
+    sh.gcap = std::min(sched_ok ? sched.max_ghosts : 0, std::max(1, total / 4 / (2 * ls * 8)));
+    const int ghosts = 2 * sh.gcap * ls * 8;
+    if (table + ghosts > 65536 - 8 * ls)
         throw Error(NBTE_ERR_INVALID_ARG, "sweep level tables do not fit in LDS; use fewer bands per block");
     const int budget = (tuning.lds_bytes == 0 ? 65536 : std::min(tuning.lds_bytes, 65536)) - table - ghosts;
-    sh.slots = tuning.lds_bytes < 0 ? 0 : std::max(budget, 0) / (bpb * 8);
+    sh.slots = tuning.lds_bytes < 0 ? 0 : std::max(budget, 0) / (ls * 8);
     return sh;
 }
 
@@ -283,6 +290,7 @@ void nbte_problem::make_view() {
     }
     v.bpb = shape.bpb;
     v.gcap = shape.gcap;
+    v.lstride = sweep_lds_stride(shape.bpb);
     v.lvl_ptr = d_lvl_ptr.as<int32_t>();
     v.lvl_off = d_lvl_off.as<int32_t>();
     v.gptr = d_gptr.as<int32_t>();

@@ -43,12 +43,17 @@ def lookup(problem, precision):
 
 
 def candidates(B):
+    """Launch shapes to time: bands per workgroup, bands per lane (several lanes
+    per cell, or one lane per cell sweeping every band of the block) and
+    workgroup size."""
     bpbs = [b for b in (1, 2, 4, 8, 16, 32) if b <= B] + ([B] if B not in (1, 2, 4, 8, 16, 32) and B <= 64 else [])
     out = []
-    for bpb, bpl, block in itertools.product(bpbs, (1, 2, 4), (128, 256, 512)):
-        if bpl > bpb or (bpb + bpl - 1) // bpl > 64:
-            continue
-        out.append({"bands_per_block": bpb, "bands_per_lane": bpl, "block_size": block, "lds_bytes": 0})
+    for bpb, block in itertools.product(bpbs, (128, 256, 512)):
+        bpls = {1, 2, 4} | ({bpb} if bpb <= 8 else set())
+        for bpl in sorted(bpls):
+            if bpl > bpb or (bpb + bpl - 1) // bpl > 64:
+                continue
+            out.append({"bands_per_block": bpb, "bands_per_lane": bpl, "block_size": block, "lds_bytes": 0})
     return out
 
 

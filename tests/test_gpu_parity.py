@@ -161,6 +161,7 @@ def test_one_sweep_full_size_sampled_systems(which, precision, bar):
 SHAPES = [  # (bands_per_block, bands_per_lane, block_size, lds_bytes)
     (1, 1, 64, 0), (2, 1, 256, 0), (4, 2, 512, 0), (5, 1, 1024, 0), (5, 4, 128, 0),
     (3, 1, 256, -1), (2, 2, 64, 256),   # no staging; a tiny LDS budget that spills
+    (5, 8, 256, 0), (4, 4, 512, 0), (2, 2, 128, 0),   # one lane per cell sweeping every band of its block
 ]
 
 
