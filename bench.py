@@ -18,7 +18,9 @@ Also reported on the same line:
                 stopping rule), with their error against the stored oracle
                 reference when one exists.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2|config3|config1]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config1..config5]
+  config4: the 64-solve batch (time to converge, batched vs one by one);
+  config5: the serving stream (p50/p99 latency, solves/s).
 """
 import argparse
 import hashlib
@@ -44,6 +46,82 @@ def log(msg):
 def workload(name):
     from workloads import configs as C
     return {"config1": C.config1, "config2": C.config2, "config3": C.config3}[name]()
+
+
+def problem_shape(N, tune, p, precision, h):
+    shape = tune.lookup(p, precision)
+    if shape:
+        N.nbte_set_tuning(h, **shape)
+    return shape
+
+
+def bench_batch(args, N, tune):
+    """Config 4: 64 independent porous-film solves in one batch (one launch per
+    kernel per iteration for all of them) against the same solves one by one."""
+    import torch
+    from workloads import configs as C
+    probs = C.config4()
+    log(f"bench: {len(probs)} porous solves, {sum(p.n_cells for p in probs)} cells")
+    ups = [p.updates_per_sweep for p in probs]
+    tol, max_iter = 1e-8, 20000
+    out = {}
+    for prec in ("mixed", "fp64"):
+        batch = N.nbte_batch_create()
+        keep = []
+        for p in probs:
+            mesh, h = N.build_problem(p)
+            problem_shape(N, tune, p, prec, h)
+            keep.append((mesh, h))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p, (mesh, h) in zip(probs, keep):
+            N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision=prec, T_ref=p.T_ref, tol=tol,
+                                                          max_iter=max_iter))
+        t_setup = time.perf_counter() - t0
+        iters = {}
+        while len(iters) < len(probs):
+            N.nbte_batch_step(batch, 8)
+            done, _ = N.nbte_batch_poll(batch)
+            for h in done:
+                if h.handle.value not in iters:
+                    iters[h.handle.value] = N.nbte_read_result(h)["iterations"]
+                    N.nbte_batch_remove(batch, h)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        total = sum(u * iters[h.handle.value] for u, (m, h) in zip(ups, keep))
+        out[f"batched_{prec}"] = {"seconds": dt, "setup_s": t_setup, "updates": total, "updates_per_s": total / dt,
+                                  "iterations_max": max(iters.values()), "iterations_sum": sum(iters.values())}
+        log(f"bench: batched {prec}: {out[f'batched_{prec}']}")
+        del batch, keep
+    # the same solves one after the other (FP64, per solve)
+    t0 = time.perf_counter()
+    for p in probs:
+        N.solve(p, precision="fp64", scheme=p.scheme, tol=tol, max_iter=max_iter, tuning="auto")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["sequential_fp64"] = {"seconds": dt}
+    out["speedup_batched_mixed_vs_sequential_fp64"] = dt / out["batched_mixed"]["seconds"]
+    log(f"bench: one by one fp64: {dt:.3f} s")
+    return out
+
+
+def bench_serving(args, N):
+    """Config 5: Poisson request stream, continuous batching with admission by
+    device-memory footprint; p50/p99 latency and solves/s."""
+    import torch
+    from paper_2607_03226_amd import serve
+    from workloads import configs as C
+    reqs = [C.serving_request(5000 + j) for j in range(args.requests)]
+    cal = [C.serving_request(9000 + j) for j in range(max(4, args.requests // 3))]
+    budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
+    rate = 0.8 * serve.calibrate(cal, budget, tol=1e-8, tuning="auto")
+    arrivals = C.poisson_arrivals(len(reqs), rate, seed=5)
+    log(f"bench: serving {len(reqs)} requests at {rate:.3f} /s (0.8 x saturated), budget {budget / 2**30:.0f} GiB")
+    served, summary = serve.serve(reqs, arrivals, budget, tol=1e-8, tuning="auto")
+    summary["arrival_rate_per_s"] = rate
+    summary["updates"] = sum(p.updates_per_sweep * s.iterations for p, s in zip(reqs, served))
+    log(f"bench: serving {summary}")
+    return summary
 
 
 def sweep_algorithmic_bytes(p, precision):
@@ -110,7 +188,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config3", "config4", "config5"])
+    ap.add_argument("--requests", type=int, default=24, help="config5: number of requests")
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
@@ -138,11 +217,27 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}), flush=True)
         return
     from paper_2607_03226_amd import nbte as N
+    from paper_2607_03226_amd import tune
+
+    if args.workload in ("config4", "config5"):
+        t0 = time.perf_counter()
+        extra = bench_batch(args, N, tune) if args.workload == "config4" else bench_serving(args, N)
+        dt = time.perf_counter() - t0
+        if args.workload == "config4":
+            value, name = extra["batched_mixed"]["updates_per_s"], "porous_films_64_B8_D32"
+        else:
+            value, name = extra["updates"] / extra["span_s"], f"serving_stream_{args.requests}"
+        line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": None, "warmup": None,
+                "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f32-stored/f32-sweep/f64-reductions", "data": "synthetic",
+                "config": {"workload": name}, "roofline": None, "cpu_baseline": None,
+                args.workload == "config4" and "batch" or "serving": extra, "seconds": dt}
+        print(json.dumps(line), flush=True)
+        return
 
     p = workload(args.workload)
     log(f"bench: workload {p.name} N={p.n_cells} B={p.n_bands} D={p.n_dirs} precision {args.precision}")
     mesh, h = N.build_problem(p)
-    from paper_2607_03226_amd import tune
     shape = tune.lookup(p, args.precision)
     if shape:
         N.nbte_set_tuning(h, **shape)
@@ -210,7 +305,7 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32-stored/f64-arith" if args.precision == "mixed" else "f64",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-stored/f32-sweep/f64-reductions" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": p.name, "cells": p.n_cells, "bands": p.n_bands, "directions": p.n_dirs,
                    "cell_type": p.cell_type, "scheme": p.scheme, "precision": args.precision,

@@ -131,6 +131,7 @@ void assign_slots(const Mesh &m, const Quadrature &q, Schedule &sc, int cap);
 struct SweepProgram {
     int maxin = 0;
     std::vector<int32_t> cell, slot, ref;   // ref: maxin * D*N
+    std::vector<int32_t> upc;               // maxin * D*N: upwind cell (own cell for inflow / unused)
     std::vector<double> coef, sout;         // coef: maxin * D*N
     // Ghosts: the boundary inflow values a level needs, in sweep order.
     // gptr has the layout of lvl_ptr (per direction L_i + 1 entries, absolute

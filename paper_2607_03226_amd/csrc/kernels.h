@@ -77,9 +77,12 @@ struct DeviceView {
     const int32_t NBTE_G *lvl_off; // D+1: start of direction i's entries in lvl_ptr
     const int32_t NBTE_G *gptr;    // ghost offsets per level (layout of lvl_ptr)
     const int32_t NBTE_G *p_cell, *p_slot, *p_ref;
-    const double NBTE_G *p_coef, *p_sout;
-    double NBTE_G *p_th;           // theta in level order, gathered every iteration
-    const double NBTE_G *p_q;      // heat source in level order, gathered at prepare
+    const int32_t NBTE_G *p_upc;   // maxin*D*N: upwind cell of each reference (the cell itself for inflow)
+    // in the storage type T of g (FP64, or FP32 for the mixed path):
+    // coefficients |a|, outflow sums, heat source (gathered at prepare) and
+    // the equilibrium-imbalance term D (every iteration)
+    const void NBTE_G *t_coef, *t_sout, *t_q;
+    void NBTE_G *t_dc;
     // bands: Cw = C/W, src = C/(C_tot W), v, inv_tau
     const double NBTE_G *Cw, *src, *vel, *inv_tau;
     double beta, C_tot;     // sum C/tau, sum C
@@ -93,7 +96,8 @@ struct DeviceView {
     const double NBTE_G *bf_thw, *bf_p, *sdotS, *win;
     // state
     void NBTE_G *g;                // D*N*B, FP32 or FP64: non-equilibrium part e - C theta/W
-    double NBTE_G *gval;           // n_ghost*B boundary inflow in sweep (ghost) order
+    void NBTE_G *gval;             // n_ghost*B boundary inflow in sweep (ghost) order, type T, as the
+                                   // deviation from equilibrium at the sweep's theta of the owner cell
     double NBTE_G *Jw;             // NBF: net flux through each boundary face
     double NBTE_G *theta[3];       // deviational lattice temperature, rotated by state->rot
     double NBTE_G *theta_seq, *thetaE, *q, *rhs, *delta;
@@ -115,7 +119,7 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 // Work tables of the elementwise kernels: items (solve, kind, local block,
 // blocks of this (solve, kind)), 256 threads each.
 //   stage:   kind 0 = boundary inflow, one wave per boundary face;
-//            kind 1 = theta gathered into sweep order, one per stream entry
+//            kind 1 = equilibrium-imbalance term D of every stream entry
 //   flux:    net flow through each boundary face, four faces per workgroup
 //   moments: band x direction reductions, mom_lpc lanes per cell
 //   update:  theta update and residual maxima (grid-stride over the cells)
@@ -137,7 +141,7 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
 // (bpl = bands per block, up to 8); otherwise bpl is 1, 2 or 4.
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
                   int block, size_t lds_bytes, hipStream_t st);
-size_t sweep_lds_bytes(int max_levels, int gcap, int lstride, int slots);
+size_t sweep_lds_bytes(int max_levels, int gcap, int lstride, int slots, int elem_bytes);
 // LDS stride (doubles) of a staged value's bands: they are contiguous, so
 // two-band blocks are read with 16-byte LDS loads (padding the stride to an
 // odd count, to spread random slots over the banks, measured slower)
@@ -162,8 +166,8 @@ void launch_collect_states(const DeviceView *vs, int n, SolveState *out, hipStre
 // Single-solve helpers (outside the iteration).
 // out[k] = offset + scale * in[k]
 void launch_affine(int64_t n, const double *in, double scale, double offset, double *out, hipStream_t st);
-// out[at] = in[p_cell[at]] over the D*N stream entries
-void launch_gather(int64_t n, const int32_t *idx, const double *in, double *out, hipStream_t st);
+// out[at] = in[idx[at]] over n entries, converted to FP32 (fp32) or kept FP64
+void launch_gather(int64_t n, const int32_t *idx, const double *in, void *out, bool fp32, hipStream_t st);
 // e(band, dir, c) of the last sweep of a solve
 void launch_distribution(const DeviceView *v, bool fp32, int band, int dir, double *out, int64_t N, hipStream_t st);
 

@@ -70,7 +70,8 @@ __global__ void k_fill_zero(uint32_t *p, size_t n) {
 }
 
 // --------------------------------------------------------------------------
-// stage: lagged boundary inflow (kind 0) and theta in sweep order (kind 1)
+// stage: lagged boundary inflow (kind 0) and the sweep's equilibrium-imbalance
+// term (kind 1)
 //
 // Boundary inflow of an incoming (face f, direction i), from the previous
 // distribution of the owner cell (Methods, boundary conditions):
@@ -78,7 +79,9 @@ __global__ void k_fill_zero(uint32_t *p, size_t n) {
 //   specular      e of the mirror direction
 //   diffuse       sum_out w (s.S) e / sum_in w |s.S|
 //   partial       p specular + (1 - p) diffuse
-// written straight into the ghost row the sweep reads it from.
+// written straight into the ghost row the sweep reads it from, as the
+// deviation from the equilibrium C theta_c / W of the owner cell at the
+// theta of the coming sweep (the form the sweep works in).
 // --------------------------------------------------------------------------
 // One wave per boundary face.  Lanes are (direction group, band) pairs:
 // BL = min(B, 64) bands per pass, JG = 64 / BL directions in flight per band,
@@ -92,8 +95,10 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
     const T *g = static_cast<const T *>(v.g);
+    T *gv = static_cast<T *>(v.gval);
     const double *sd = v.sdotS + bf * D;
     const int32_t *row = v.in_row + bf * D;
+    const double thc = theta_cur(v)[c];   // theta of the coming sweep
     const int BL = B < 64 ? B : 64;
     const int JG = 64 / BL;
     const int jg = lane / BL, ml = lane - jg * BL;
@@ -102,10 +107,10 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
         for (int l0 = 0; l0 < B; l0 += BL) {
             const int lam = l0 + ml;
             if (jg >= JG || lam >= B) continue;
-            const double val = v.Cw[lam] * thw;
+            const T val = static_cast<T>(v.Cw[lam] * thw - v.Cw[lam] * thc);
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
-                if (r >= 0) v.gval[(int64_t)r * B + lam] = val;
+                if (r >= 0) gv[(int64_t)r * B + lam] = val;
             }
         }
         return;
@@ -119,6 +124,7 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
         const int lam_c = on ? lam : 0;
         const double cw = v.Cw[lam_c];
         const double eq = cw * thp;
+        const double eqc = cw * thc;
         double diff = 0.0;
         if (p < 1.0) {
             double acc = 0.0;
@@ -147,12 +153,12 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
                 const int r = row[i];
                 const int mi = mir[i] >= 0 ? mir[i] : 0;   // outgoing directions have no mirror entry
                 const double em = ld(g, ((int64_t)mi * N + c) * B + lam) + eq;
-                if (r >= 0) v.gval[(int64_t)r * B + lam] = (1.0 - p) * diff + p * em;
+                if (r >= 0) gv[(int64_t)r * B + lam] = static_cast<T>((1.0 - p) * diff + p * em - eqc);
             }
         } else {
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
-                if (r >= 0) v.gval[(int64_t)r * B + lam] = diff;
+                if (r >= 0) gv[(int64_t)r * B + lam] = static_cast<T>(diff - eqc);
             }
         }
     }
@@ -172,9 +178,22 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
         for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4)
             bc_face<T>(v, bf, red + 64 * wv);
     } else {
+        // D = sum_j |a_j| (theta_up_j - theta_c): the closed cell's
+        // sum_{a<0} |a| - sum_{a>0} a vanishes (divergence theorem, to the
+        // rounding of the face vectors), so D needs no outflow term and is
+        // exactly zero for a uniform theta.  The differences are taken in
+        // FP64, then weighted by the sweep's coefficients.
         const int64_t n = (int64_t)v.D * v.N;
+        const int MI = v.maxin;
         const double *th = theta_cur(v);
-        for (int64_t t = t0; t < n; t += stride) v.p_th[t] = th[v.p_cell[t]];
+        const T *cf = static_cast<const T *>(v.t_coef);
+        T *dc = static_cast<T *>(v.t_dc);
+        for (int64_t t = t0; t < n; t += stride) {
+            const double thc = th[v.p_cell[t]];
+            double acc = 0.0;
+            for (int j = 0; j < MI; ++j) acc += static_cast<double>(cf[j * n + t]) * (th[v.p_upc[j * n + t]] - thc);
+            dc[t] = static_cast<T>(acc);
+        }
     }
 }
 
@@ -185,12 +204,13 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
 //   e_c = (e0_l/tau_l + S_l + v_l sum_{a<0} |a| e_up) / (1/tau_l + v_l sum_{a>0} a),
 //   a = (s_i . S_cf) / V_c,
 // e_up = value of the upwind neighbour computed earlier in this sweep, or the
-// boundary inflow.  Everything a cell needs comes from the direction's
-// level-ordered streams (cell, coefficients, upwind references, theta, Qdot):
-// independent coalesced loads, no pointer chasing.  Upwind values are staged
-// in LDS (FP64) in host-assigned slots; a value without a slot is read back
-// from its stored copy.  A workgroup barrier separates levels; it orders the
-// LDS and HBM writes of level k before the reads of level k+1.
+// boundary inflow (computed in the deviation form g below).  Everything a
+// cell needs comes from the direction's level-ordered streams (cell,
+// coefficients, upwind references, imbalance term D, Qdot): independent
+// coalesced loads, no pointer chasing.  Upwind values are staged in LDS (in
+// the storage type) in host-assigned slots; a value without a slot is read
+// back from its stored copy.  A workgroup barrier separates levels; it orders
+// the LDS and HBM writes of level k before the reads of level k+1.
 //
 // Workgroup -> (solve, direction, band block) through the work table; the
 // host orders it so that the band blocks of one direction land on the same
@@ -201,6 +221,7 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
 // pointers passed around), so every access stays in the LDS address space.
 extern __shared__ double sweep_lds[];
 extern __shared__ int sweep_ldsi[];   // the same memory viewed as ints (level tables)
+extern __shared__ float sweep_ldsf[];  // ... and as floats (FP32 staged values)
 
 constexpr int kGhostPerThread = 2;    // ghost values a thread prefetches per level
 constexpr int kPrefetch = 4;          // passes whose records are in flight ahead of the computed one
@@ -208,18 +229,28 @@ constexpr int kPrefetch = 4;          // passes whose records are in flight ahea
 // [-2 kSpill, -kSpill - 1] ghost read from HBM (row); below: spilled cell
 constexpr int32_t kSpill = 1 << 24;
 
+// The sweep works in the deviation from local equilibrium,
+//   g_c = e_c - C_l theta_c / W,
+// which turns the upwind update into
+//   g_c = (Q_c S_l + v_l (sum_j |a_j| g_up_j + (C_l/W) D_c)) / (1/tau_l + v_l sum_{a>0} a),
+//   D_c = sum_j |a_j| theta_up_j - (sum_{a>0} a) theta_c = sum_j |a_j| (theta_up_j - theta_c)
+// (g_up of a boundary inflow is taken against theta_c; the second form of D
+// uses sum_{a<0} |a| = sum_{a>0} a of a closed cell).  g is small wherever
+// theta is smooth, so the FP32 form of the mixed path rounds relative to the
+// deviation, not to e; the FP64 path runs the same form in FP64.
+
 // One cell's sweep record (a position of a direction's level-ordered streams).
-template <int MI>
+template <class T, int MI>
 struct SweepRec {
     int c, mine;
     int ref[MI];
-    double cf[MI];
-    double sout, th, Q;
+    T cf[MI];
+    T sout, dc, q;
     bool ok;
 };
 
-template <int MI>
-__device__ __forceinline__ void load_rec(SweepRec<MI> &r, const DeviceView &v, int64_t base, int64_t DN, int k,
+template <class T, int MI>
+__device__ __forceinline__ void load_rec(SweepRec<T, MI> &r, const DeviceView &v, int64_t base, int64_t DN, int k,
                                          int kend) {
     // the loads are issued on every path (a past-the-end record reads stream
     // position 0 of the direction), so the number of loads in flight is the
@@ -227,15 +258,16 @@ __device__ __forceinline__ void load_rec(SweepRec<MI> &r, const DeviceView &v, i
     // younger prefetches outstanding
     r.ok = k < kend;
     const int64_t at = base + (r.ok ? k : 0);
+    const T NBTE_G *coef = static_cast<const T NBTE_G *>(v.t_coef);
     r.c = v.p_cell[at];
     r.mine = v.p_slot[at];
-    r.sout = v.p_sout[at];
-    r.th = v.p_th[at];
-    r.Q = v.p_q[at];
+    r.sout = static_cast<const T NBTE_G *>(v.t_sout)[at];
+    r.dc = static_cast<const T NBTE_G *>(v.t_dc)[at];
+    r.q = static_cast<const T NBTE_G *>(v.t_q)[at];
 #pragma unroll
     for (int j = 0; j < MI; ++j) {
         r.ref[j] = v.p_ref[j * DN + at];
-        r.cf[j] = v.p_coef[j * DN + at];
+        r.cf[j] = coef[j * DN + at];
     }
 }
 
@@ -243,48 +275,64 @@ __device__ __forceinline__ void load_rec(SweepRec<MI> &r, const DeviceView &v, i
 // the sweep never waits on a load issued in the same level, because a wait on
 // any load also waits for every older one (the vector memory counter is in
 // order), which would drain the prefetched records.
-template <int BPL>
+template <class T, int BPL>
 struct BandConst {
-    double cw[BPL], itau[BPL], vel[BPL], src[BPL];
+    T cw[BPL], itau[BPL], vel[BPL], src[BPL];
 };
 
+// LDS views of the staged values: element k of the sweep's type
+template <class T>
+__device__ __forceinline__ T lds_get(int k);
+template <>
+__device__ __forceinline__ double lds_get<double>(int k) { return sweep_lds[k]; }
+template <>
+__device__ __forceinline__ float lds_get<float>(int k) { return sweep_ldsf[k]; }
+template <class T>
+__device__ __forceinline__ void lds_put(int k, T x);
+template <>
+__device__ __forceinline__ void lds_put<double>(int k, double x) { sweep_lds[k] = x; }
+template <>
+__device__ __forceinline__ void lds_put<float>(int k, float x) { sweep_ldsf[k] = x; }
+
+// the update's quotient: IEEE division in FP64, reciprocal (1 ulp) in FP32
+__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+__device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 template <class T, int MI, int BPL>
-__device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceView &v, const BandConst<BPL> &bc,
+__device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const DeviceView &v, const BandConst<T, BPL> &bc,
                                            T *gi, int64_t base, int ring_off, int gbuf_off, int ls,
                                            int b0, int lane, int nb_here) {
     const int B = v.B;
+    const T NBTE_G *gval = static_cast<const T NBTE_G *>(v.gval);
 #pragma unroll
     for (int jb = 0; jb < BPL; ++jb) {
         const int lb = lane * BPL + jb;
         if (lb >= nb_here) break;
         const int lam = b0 + lb;
-        const double cw = bc.cw[jb];
-        const double itau = bc.itau[jb];
-        double gain = 0.0;
+        T gain = 0;
 #pragma unroll
         for (int j = 0; j < MI; ++j) {
-            if (r.cf[j] == 0.0) continue;
+            if (r.cf[j] == T(0)) continue;
             const int rf = r.ref[j];
-            double up;
+            T up;
             if (rf >= 0) {
-                up = sweep_lds[ring_off + rf * ls + lb];
+                up = lds_get<T>(ring_off + rf * ls + lb);
             } else if (rf >= -kSpill) {
-                up = sweep_lds[gbuf_off + (-1 - rf) * ls + lb];
+                up = lds_get<T>(gbuf_off + (-1 - rf) * ls + lb);
             } else if (rf >= -2 * kSpill) {
-                up = v.gval[(int64_t)(-kSpill - 1 - rf) * B + lam];   // ghost beyond the LDS capacity
+                up = gval[(int64_t)(-kSpill - 1 - rf) * B + lam];   // ghost beyond the LDS capacity
             } else {
                 // value without an LDS slot: its stored copy, located through
                 // the neighbour's position in this direction's streams
-                const int64_t at = base + (-(2 * kSpill + 2) - rf);
-                const int n = v.p_cell[at];
-                up = ld(gi, (int64_t)n * B + lam) + cw * v.p_th[at];
+                const int n = v.p_cell[base + (-(2 * kSpill + 2) - rf)];
+                up = gi[(int64_t)n * B + lam];
             }
             gain += r.cf[j] * up;
         }
-        const double vel = bc.vel[jb];
-        const double e = (cw * r.th * itau + r.Q * bc.src[jb] + vel * gain) / (itau + vel * r.sout);
-        gi[(int64_t)r.c * B + lam] = static_cast<T>(e - cw * r.th);
-        if (r.mine >= 0) sweep_lds[ring_off + r.mine * ls + lb] = e;
+        const T vel = bc.vel[jb];
+        const T g = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
+        gi[(int64_t)r.c * B + lam] = g;
+        if (r.mine >= 0) lds_put<T>(ring_off + r.mine * ls + lb, g);
     }
 }
 
@@ -294,7 +342,7 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<MI> &r, const DeviceVi
 // (coefficient 0) masked by a select, past-the-end records computed but not
 // stored, so the items of a thread interleave.
 template <class T, int MI, int BPL>
-__device__ __forceinline__ void sweep_cell_lds(const SweepRec<MI> &r, const BandConst<BPL> &bc, T *gi, int B,
+__device__ __forceinline__ void sweep_cell_lds(const SweepRec<T, MI> &r, const BandConst<T, BPL> &bc, T *gi, int B,
                                                int ring_off, int gbuf_off, int ls, int b0, int lane,
                                                int nb_here) {
     int off[MI];
@@ -310,19 +358,17 @@ __device__ __forceinline__ void sweep_cell_lds(const SweepRec<MI> &r, const Band
         const int lb = lane * BPL + jb;
         const bool on = r.ok && lb < nb_here;
         const int lr = lb < ls ? lb : ls - 1;   // lanes past the block read in range
-        const double cw = bc.cw[jb];
-        const double itau = bc.itau[jb];
-        double gain = 0.0;
+        T gain = 0;
 #pragma unroll
         for (int j = 0; j < MI; ++j) {
-            const double up = sweep_lds[off[j] + lr];
-            gain += r.cf[j] != 0.0 ? r.cf[j] * up : 0.0;
+            const T up = lds_get<T>(off[j] + lr);
+            gain += r.cf[j] != T(0) ? r.cf[j] * up : T(0);
         }
-        const double vel = bc.vel[jb];
-        const double e = (cw * r.th * itau + r.Q * bc.src[jb] + vel * gain) / (itau + vel * r.sout);
+        const T vel = bc.vel[jb];
+        const T g = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
         if (on) {
-            gc[lb] = static_cast<T>(e - cw * r.th);
-            if (r.mine >= 0) sweep_lds[mine + lb] = e;
+            gc[lb] = g;
+            if (r.mine >= 0) lds_put<T>(mine + lb, g);
         }
     }
 }
@@ -390,7 +436,7 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     const int ML = v.max_levels + 1;
 #define lp(t) sweep_ldsi[(t)]
 #define gp(t) sweep_ldsi[ML + (t)]
-    const int gbuf0 = ML;                               // 2*ML ints = ML doubles
+    const int gbuf0 = (2 * ML * (int)sizeof(int)) / (int)sizeof(T);   // first element after the tables
     const int ls = v.lstride;
     const int gstride = gcap * ls;                      // ghosts of a level kept in LDS (rank < gcap)
     const int ring_off = gbuf0 + 2 * gstride;
@@ -403,15 +449,16 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
             gp(t) = ggp[t];
         }
     }
-    BandConst<BPL> bc;
+    BandConst<T, BPL> bc;
 #pragma unroll
     for (int jb = 0; jb < BPL; ++jb) {
         const int lam = min(b0 + lane * BPL + jb, B - 1);
-        bc.cw[jb] = v.Cw[lam];
-        bc.itau[jb] = v.inv_tau[lam];
-        bc.vel[jb] = v.vel[lam];
-        bc.src[jb] = v.src[lam];
+        bc.cw[jb] = static_cast<T>(v.Cw[lam]);
+        bc.itau[jb] = static_cast<T>(v.inv_tau[lam]);
+        bc.vel[jb] = static_cast<T>(v.vel[lam]);
+        bc.src[jb] = static_cast<T>(v.src[lam]);
     }
+    const T NBTE_G *gval = static_cast<const T NBTE_G *>(v.gval);
     __syncthreads();
 
     // The sweep of a direction as a sequence of passes: pass = up to nslots
@@ -422,10 +469,10 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     // inflow) of a level ride with the records of its first pass and are
     // stored into the level's LDS buffer just before the level starts.
     struct Ghosts {
-        double v[kGhostPerThread];
+        T v[kGhostPerThread];
     };
     struct Set {
-        SweepRec<MI> r;
+        SweepRec<T, MI> r;
         Ghosts h;
     };
     auto ghost_load = [&](Ghosts &h, int l, bool first) {
@@ -437,8 +484,8 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
             const int e = threadIdx.x + m * blockDim.x;
             const int q = e / bands_per_block, lb = e - q * bands_per_block;
             const bool ok = e < ne && lb < nb_here;
-            const double x = v.gval[ok ? (int64_t)(g0 + q) * B + b0 + lb : 0];
-            h.v[m] = ok ? x : 0.0;
+            const T x = gval[ok ? (int64_t)(g0 + q) * B + b0 + lb : 0];
+            h.v[m] = ok ? x : T(0);
         }
     };
     auto ghost_store = [&](const Ghosts &h, int l) {
@@ -448,13 +495,13 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
         for (int m = 0; m < kGhostPerThread; ++m) {
             const int e = threadIdx.x + m * blockDim.x;
             const int q = e / bands_per_block, lb = e - q * bands_per_block;
-            if (e < ne) sweep_lds[dst + q * ls + lb] = h.v[m];
+            if (e < ne) lds_put<T>(dst + q * ls + lb, h.v[m]);
         }
         // levels with more ghosts than the registers hold: direct copy
 #pragma nounroll
         for (int e = threadIdx.x + kGhostPerThread * blockDim.x; e < ne; e += blockDim.x) {
             const int q = e / bands_per_block, lb = e - q * bands_per_block;
-            sweep_lds[dst + q * ls + lb] = lb < nb_here ? v.gval[(int64_t)(g0 + q) * B + b0 + lb] : 0.0;
+            lds_put<T>(dst + q * ls + lb, lb < nb_here ? gval[(int64_t)(g0 + q) * B + b0 + lb] : T(0));
         }
     };
     // pass cursors (uniform): level and first position of the pass
@@ -532,6 +579,7 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
     const int c = v.bf_owner[bf];
     const double th = (after ? theta_prev(v) : theta_cur(v))[c];
     const T *g = static_cast<const T *>(v.g);
+    const T *gv = static_cast<const T *>(v.gval);
     double acc = 0.0;
     // both candidate values are loaded on every path (independent loads, four
     // pairs in flight); directions with s.S = 0 contribute exactly zero
@@ -540,7 +588,7 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
         const int i = t / B, lam = t - i * B;
         const double sd = v.sdotS[bf * D + i];
         const int32_t row = v.in_row[bf * D + i];
-        const double ein = v.gval[row >= 0 ? (int64_t)row * B + lam : 0];
+        const double ein = ld(gv, row >= 0 ? (int64_t)row * B + lam : 0) + v.Cw[lam] * th;
         const double eout = ld(g, ((int64_t)i * N + c) * B + lam) + v.Cw[lam] * th;
         const double e = row >= 0 ? ein : (sd > 0.0 ? eout : 0.0);
         acc += v.vel[lam] * v.w[i] * sd * e;
@@ -686,9 +734,10 @@ __global__ void k_affine(int64_t n, const double *in, double scale, double offse
     if (k < n) out[k] = offset + scale * in[k];
 }
 
-__global__ void k_gather(int64_t n, const int32_t *idx, const double *in, double *out) {
+template <class T>
+__global__ void k_gather(int64_t n, const int32_t *idx, const double *in, T *out) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k < n) out[k] = in[idx[k]];
+    if (k < n) out[k] = static_cast<T>(in[idx[k]]);
 }
 
 // e of the last sweep: stored g relative to the theta that sweep used (prev)
@@ -982,10 +1031,10 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
     hipLaunchKernelGGL(k_finish, dim3((n + 63) / 64), dim3(64), 0, st, vs, wk, n);
 }
 
-size_t sweep_lds_bytes(int max_levels, int gcap, int ls, int slots) {
-    return (size_t)(max_levels + 1) * sizeof(double)            // two int level tables
-           + (size_t)2 * gcap * ls * sizeof(double)              // ghost buffers
-           + (size_t)std::max(slots, 1) * ls * sizeof(double);   // staged values
+size_t sweep_lds_bytes(int max_levels, int gcap, int ls, int slots, int es) {
+    return (size_t)(max_levels + 1) * 2 * sizeof(int)    // two int level tables
+           + (size_t)2 * gcap * ls * es                  // ghost buffers
+           + (size_t)std::max(slots, 1) * ls * es;       // staged values
 }
 
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
@@ -1026,9 +1075,11 @@ void launch_affine(int64_t n, const double *in, double scale, double offset, dou
     hipLaunchKernelGGL(k_affine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, in, scale, offset, out);
 }
 
-void launch_gather(int64_t n, const int32_t *idx, const double *in, double *out, hipStream_t st) {
+void launch_gather(int64_t n, const int32_t *idx, const double *in, void *out, bool fp32, hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, idx, in, out);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (fp32) hipLaunchKernelGGL(k_gather<float>, grid, dim3(256), 0, st, n, idx, in, static_cast<float *>(out));
+    else hipLaunchKernelGGL(k_gather<double>, grid, dim3(256), 0, st, n, idx, in, static_cast<double *>(out));
 }
 
 void launch_distribution(const DeviceView *v, bool fp32, int band, int dir, double *out, int64_t N, hipStream_t st) {

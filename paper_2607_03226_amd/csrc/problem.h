@@ -124,7 +124,10 @@ struct nbte_problem {
 
     // device buffers
     nbte::DevBuf d_nbr, d_V;
-    nbte::DevBuf d_lvl_ptr, d_lvl_off, d_gptr, d_pcell, d_pslot, d_pref, d_pcoef, d_psout, d_pth, d_pq, d_inrow;
+    nbte::DevBuf d_lvl_ptr, d_lvl_off, d_gptr, d_pcell, d_pslot, d_pref, d_pupc, d_inrow;
+    nbte::DevBuf d_tcoef, d_tsout;   // coefficients and outflow sums in the storage type
+    nbte::DevBuf d_tq, d_tdc;        // heat source and imbalance term in sweep order (storage type)
+    int coef_prec = -1;              // precision d_tcoef / d_tsout were uploaded in
     nbte::DevBuf d_Cw, d_src, d_vel, d_itau, d_dirs, d_w, d_qbias;
     nbte::DevBuf d_bf_owner, d_bf_kind, d_mirror, d_bf_thw, d_bf_p, d_sdotS, d_win;
     nbte::DevBuf d_Lrow, d_Lcol, d_Lval, d_Ldinv;

@@ -136,7 +136,7 @@ void Runner::build() {
                 const int lpc = p.hv.lpc;
                 const int nslots = std::max(1, p.shape.block / lpc);
                 lds = std::max(lds, sweep_lds_bytes(p.sched.max_levels, p.shape.gcap, p.hv.lstride,
-                                                    std::max(p.sched.max_slots, 1)));
+                                                    std::max(p.sched.max_slots, 1), p.fp32() ? 4 : 8));
                 for (int i = 0; i < p.quad.D; ++i) {
                     // passes over the cells of direction i: one per level and slot row
                     int64_t passes = 0;

@@ -156,6 +156,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
     pg.slot.resize(DN);
     pg.sout.resize(DN);
     pg.ref.assign((size_t)pg.maxin * DN, 0);
+    pg.upc.assign((size_t)pg.maxin * DN, 0);
     pg.coef.assign((size_t)pg.maxin * DN, 0.0);
     pg.gptr.resize(sc.lvl_ptr.size());
     pg.in_row.assign((size_t)m.NBF * D, -1);
@@ -175,6 +176,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                 const int64_t at = (int64_t)i * N + k;
                 const int32_t c = sc.perm[at];
                 pg.cell[at] = c;
+                for (int j = 0; j < pg.maxin; ++j) pg.upc[(size_t)j * DN + at] = c;
                 pg.slot[at] = slot_i ? slot_i[c] : -1;
                 const double iv = 1.0 / m.V[c];
                 double sout = 0.0;
@@ -200,6 +202,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                             r = -(2 * kSpillBase + 2) - pos[n];        // stored copy in HBM
                         }
                         pg.ref[(size_t)j * DN + at] = r;
+                        if (n >= 0) pg.upc[(size_t)j * DN + at] = n;
                         pg.coef[(size_t)j * DN + at] = -a;
                         ++j;
                     }

@@ -108,13 +108,14 @@ nbte_problem::Shape nbte_problem::resolve_shape() const {
     // goes to ghosts, larger boundary levels read the rest from HBM
     const int table = ((sched_ok ? sched.max_levels : 0) + 1) * 8;
     const int ls = sweep_lds_stride(bpb);
+    const int es = fp32() ? 4 : 8;   // staged values are held in the storage type
     const int total = tuning.lds_bytes == 0 ? 65536 : std::min(std::abs(tuning.lds_bytes), 65536);
-    sh.gcap = std::min(sched_ok ? sched.max_ghosts : 0, std::max(1, total / 4 / (2 * ls * 8)));
-    const int ghosts = 2 * sh.gcap * ls * 8;
-    if (table + ghosts > 65536 - 8 * ls)
+    sh.gcap = std::min(sched_ok ? sched.max_ghosts : 0, std::max(1, total / 4 / (2 * ls * es)));
+    const int ghosts = 2 * sh.gcap * ls * es;
+    if (table + ghosts > 65536 - es * ls)
         throw Error(NBTE_ERR_INVALID_ARG, "sweep level tables do not fit in LDS; use fewer bands per block");
     const int budget = (tuning.lds_bytes == 0 ? 65536 : std::min(tuning.lds_bytes, 65536)) - table - ghosts;
-    sh.slots = tuning.lds_bytes < 0 ? 0 : std::max(budget, 0) / (ls * 8);
+    sh.slots = tuning.lds_bytes < 0 ? 0 : std::max(budget, 0) / (ls * es);
     return sh;
 }
 
@@ -176,12 +177,10 @@ void nbte_problem::upload_device() {
         upload(d_pcell, prog.cell, stream);
         upload(d_pslot, prog.slot, stream);
         upload(d_pref, prog.ref, stream);
-        upload(d_pcoef, prog.coef, stream);
-        upload(d_psout, prog.sout, stream);
+        upload(d_pupc, prog.upc, stream);
+        coef_prec = -1;
         upload(d_gptr, prog.gptr, stream);
         upload(d_inrow, prog.in_row, stream);
-        d_pth.alloc(prog.cell.size() * sizeof(double));
-        d_pq.alloc(prog.cell.size() * sizeof(double));
         sched_up = true;
     }
     if (!plan_up) {
@@ -237,14 +236,28 @@ int64_t nbte_problem::state_bytes(int prec) const {
     const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
     const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
     const int64_t ghosts = prog_B > 0 ? (int64_t)prog.ghost_src.size() : NBF * D;   // incoming pairs
-    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * 8 + NBF * 8 + N * 8 * 10 + 1024;
+    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + NBF * 8 + N * 8 * 10 + 1024;
 }
 
 void nbte_problem::allocate_state(int prec) {
     const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
     const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
     d_g.alloc(D * N * B * es);
-    d_gval.alloc(std::max<int64_t>((int64_t)prog.ghost_src.size() * B, 1) * 8);
+    d_gval.alloc(std::max<int64_t>((int64_t)prog.ghost_src.size() * B, 1) * es);
+    d_tq.alloc(D * N * es);
+    d_tdc.alloc(D * N * es);
+    if (coef_prec != prec) {
+        if (prec == NBTE_PREC_MIXED) {
+            std::vector<float> fc(prog.coef.begin(), prog.coef.end()), fs(prog.sout.begin(), prog.sout.end());
+            upload(d_tcoef, fc, stream);
+            upload(d_tsout, fs, stream);
+            NBTE_HIP(hipStreamSynchronize(stream));   // the host copies go out of scope
+        } else {
+            upload(d_tcoef, prog.coef, stream);
+            upload(d_tsout, prog.sout, stream);
+        }
+        coef_prec = prec;
+    }
     d_Jw.alloc(std::max<int64_t>(NBF, 1) * 8);
     d_Q.alloc(N * 8);
     for (auto &t : d_theta) t.alloc(N * 8);
@@ -260,8 +273,8 @@ void nbte_problem::allocate_state(int prec) {
 int64_t nbte_problem::device_bytes() const {
     int64_t s = 0;
     for (const DevBuf *b :
-         {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pcell, &d_pslot, &d_pref, &d_pcoef, &d_psout, &d_pth,
-          &d_pq, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
+         {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pcell, &d_pslot, &d_pref, &d_pupc, &d_tcoef,
+          &d_tsout, &d_tq, &d_tdc, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
           &d_mirror, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_g, &d_gval,
           &d_Jw, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work})
@@ -297,10 +310,11 @@ void nbte_problem::make_view() {
     v.p_cell = d_pcell.as<int32_t>();
     v.p_slot = d_pslot.as<int32_t>();
     v.p_ref = d_pref.as<int32_t>();
-    v.p_coef = d_pcoef.as<double>();
-    v.p_sout = d_psout.as<double>();
-    v.p_th = d_pth.as<double>();
-    v.p_q = d_pq.as<double>();
+    v.p_upc = d_pupc.as<int32_t>();
+    v.t_coef = d_tcoef.ptr;
+    v.t_sout = d_tsout.ptr;
+    v.t_q = d_tq.ptr;
+    v.t_dc = d_tdc.ptr;
     v.Cw = d_Cw.as<double>();
     v.src = d_src.as<double>();
     v.vel = d_vel.as<double>();
@@ -319,7 +333,7 @@ void nbte_problem::make_view() {
     v.sdotS = d_sdotS.as<double>();
     v.win = d_win.as<double>();
     v.g = d_g.ptr;
-    v.gval = d_gval.as<double>();
+    v.gval = d_gval.ptr;
     v.Jw = d_Jw.as<double>();
     for (int k = 0; k < 3; ++k) v.theta[k] = d_theta[k].as<double>();
     v.theta_seq = d_theta_seq.as<double>();
@@ -368,8 +382,8 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
         }
     }
     prepared = false;
+    precision = o.precision;   // the launch shape's LDS budget depends on it
     ensure_setup();
-    precision = o.precision;
     scheme = o.scheme;
     time_phases = o.time_phases;
     allocate_state(precision);
@@ -396,7 +410,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     s0.tol = o.tol;
     NBTE_HIP(hipMemcpyAsync(d_state.ptr, &s0, sizeof(s0), hipMemcpyHostToDevice, stream));
     NBTE_HIP(hipMemcpyAsync(d_Q.ptr, Q.data(), m.N * 8, hipMemcpyHostToDevice, stream));
-    launch_gather((int64_t)quad.D * m.N, d_pcell.as<int32_t>(), d_Q.as<double>(), d_pq.as<double>(), stream);
+    launch_gather((int64_t)quad.D * m.N, d_pcell.as<int32_t>(), d_Q.as<double>(), d_tq.ptr, fp32(), stream);
     double *th0 = d_theta[0].as<double>();   // theta[cur] at rotation 0
     if (o.T_init) {
         NBTE_HIP(hipMemcpyAsync(th0, t0.data(), m.N * 8, hipMemcpyHostToDevice, stream));
@@ -794,8 +808,10 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
         const int64_t N = m.N, F = m.F, D = p->quad.D, NBF = m.NBF;
         const int64_t mi = std::max<int64_t>(F - 1, 1);
         const int64_t geo = N * F * 4 + N * 8 + NBF * 4;
-        // level tables (at most one level per cell), streams cell/slot/refs/coefs/outflow/theta/Q, inflow rows
-        const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * 12 + 8 + 8 + 8) + NBF * D * 4;
+        // level tables (at most one level per cell); streams cell, slot, refs, upwind cells, coefficients
+        // and outflow sums (storage type); inflow rows
+        const int64_t es = precision == NBTE_PREC_MIXED ? 4 : 8;
+        const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * (8 + es) + es) + NBF * D * 4;
         const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * D * (8 + 4);
         const int64_t lh = N * (F + 1) * 12 + N * 8 * 8 + 256 * 4 * 8;
         *bytes = geo + sched + plan + lh + p->state_bytes(precision);

@@ -1,0 +1,148 @@
+"""Serving loop: continuous batching of steady-solve requests over the C ABI.
+
+Requests arrive over time.  Each is set up on the host (mesh, band table,
+quadrature, boundaries: the per-geometry setup counts in its latency) and
+admitted into the running batch as soon as its device footprint fits the
+budget (nbte_batch_admit refuses it otherwise and it waits, first come first
+served).  Every step advances all running solves together (one launch per
+kernel for all of them, replayed from a HIP graph); a solve leaves the batch
+as soon as the device stops it at its tolerance, and its result is read while
+the others keep running.  New requests are set up and admitted while the
+enqueued step runs on the GPU.
+
+serve() returns per-request latency (finish - arrival), p50/p99 and the
+throughput in solves/s.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import nbte as N
+
+
+@dataclass
+class Served:
+    index: int
+    name: str
+    arrival: float
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    iterations: int = 0
+    residual: float = float("nan")
+    converged: bool = False
+    result: dict = field(default=None, repr=False)
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+def percentile(x, q):
+    x = np.sort(np.asarray(x, dtype=float))
+    if len(x) == 0:
+        return float("nan")
+    return float(np.percentile(x, q))
+
+
+def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_iter=20000, step=8,
+          keep_results=False, tuning=None, clock=time.perf_counter, log=None):
+    """Run the request stream.
+
+    requests  list of problem descriptions (see nbte.build_problem)
+    arrivals  arrival times in seconds from the start (non-decreasing)
+    budget    device bytes the running solves may hold together
+    tuning    None, "auto" (autotuner cache) or a dict of launch-shape settings
+    Returns (list of Served, summary dict).
+    """
+    n = len(requests)
+    batch = N.nbte_batch_create(budget_bytes)
+    served = [Served(j, requests[j].name, float(arrivals[j])) for j in range(n)]
+    queue = collections.deque()
+    handles = {}                # handle value -> (index, mesh, problem handle)
+    next_arrival = 0
+    done_count = 0
+    t0 = clock()
+
+    def now():
+        return clock() - t0
+
+    built = {}                  # host setup of waiting requests, kept across admission attempts
+
+    def admit_waiting():
+        while queue:
+            j = queue[0]
+            p = requests[j]
+            if j not in built:
+                mesh, h = N.build_problem(p)
+                if tuning == "auto":
+                    from . import tune
+                    shape = tune.lookup(p, precision)
+                    if shape:
+                        N.nbte_set_tuning(h, **shape)
+                elif tuning:
+                    N.nbte_set_tuning(h, **tuning)
+                built[j] = (mesh, h)
+            mesh, h = built[j]
+            opts = N.make_opts(scheme=p.scheme, precision=precision, T_ref=p.T_ref, tol=tol, max_iter=max_iter)
+            try:
+                N.nbte_batch_admit(batch, h, p.Q, opts)
+            except N.NbteError as e:
+                if e.status != N.ERR_OUT_OF_MEMORY:
+                    raise
+                if not handles:
+                    raise RuntimeError(f"request {j} ({p.name}) does not fit the budget even alone") from e
+                return              # wait for running solves to leave
+            queue.popleft()
+            del built[j]
+            handles[h.handle.value] = (j, mesh, h)
+            served[j].admitted = now()
+            if log:
+                log(f"serve: t={served[j].admitted:.3f} s admitted {j} {p.name}")
+
+    while done_count < n:
+        t = now()
+        while next_arrival < n and arrivals[next_arrival] <= t:
+            queue.append(next_arrival)
+            next_arrival += 1
+        if not handles:
+            admit_waiting()
+            if not handles:
+                if next_arrival < n:
+                    time.sleep(max(0.0, arrivals[next_arrival] - now()))
+                continue
+        N.nbte_batch_step(batch, step)          # asynchronous
+        admit_waiting()                          # host setup overlaps the step on the GPU
+        finished, _ = N.nbte_batch_poll(batch)
+        for h in finished:
+            j, mesh, hh = handles.pop(h.handle.value)
+            out = N.nbte_read_result(h)
+            N.nbte_batch_remove(batch, h)
+            s = served[j]
+            s.finished = now()
+            s.iterations = out["iterations"]
+            s.residual = out["residual"]
+            s.converged = bool(out["residual"] <= tol)
+            if keep_results:
+                s.result = {k: out[k] for k in ("T_lattice", "T", "q", "iterations", "residual", "energy_defect")}
+            done_count += 1
+            if log:
+                log(f"serve: t={s.finished:.3f} s finished {j} {s.name} in {s.iterations} iterations, "
+                    f"latency {s.latency:.3f} s")
+            del mesh, hh
+    lat = [s.latency for s in served]
+    span = max(s.finished for s in served) - min(s.arrival for s in served)
+    summary = {"requests": n, "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+               "mean_s": float(np.mean(lat)), "solves_per_s": n / span if span > 0 else float("inf"),
+               "span_s": span, "all_converged": all(s.converged for s in served),
+               "budget_bytes": int(budget_bytes)}
+    return served, summary
+
+
+def calibrate(requests, budget_bytes, **kw):
+    """Saturated throughput: every request arrives at t = 0."""
+    _, summary = serve(requests, np.zeros(len(requests)), budget_bytes, **kw)
+    return summary["solves_per_s"]

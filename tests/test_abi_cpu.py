@@ -170,4 +170,9 @@ def test_footprint_scales_with_precision():
     N.nbte_set_quadrature(h, p.s, p.w)
     f32 = N.nbte_problem_footprint(h, "mixed")
     f64 = N.nbte_problem_footprint(h, "fp64")
-    assert f64 - f32 == p.n_cells * p.n_bands * p.n_dirs * 4
+    # the mixed path holds the distribution, the boundary inflow and the
+    # sweep's real-valued streams (coefficients, outflow sum, source, D) in
+    # FP32: 4 bytes less per value
+    ndn = p.n_cells * p.n_dirs
+    halved = p.n_cells * p.n_bands * p.n_dirs * 4
+    assert halved < f64 - f32 <= halved + ndn * (6 + 3) * 4 + p.n_bands * len(p.bfaces) * p.n_dirs * 4

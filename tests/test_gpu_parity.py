@@ -85,8 +85,12 @@ CASES = [
     ("config4_small_3", lambda: C.config4_small()[3], "synthetic"),
     # above the one-workgroup PCG limit: the multi-workgroup correction solver
     ("porous_10k", lambda: C.porous_problem(4242, n_lo=9000, n_hi=11000), "synthetic"),
-    # full-size 3D box against the stored oracle reference (sampled cells)
+    # full-size workloads against the stored oracle references (sampled cells)
     ("config2", C.config2, "synthetic"),
+    ("config3", C.config3, "synthetic"),
+    # requests of the serving stream (reduced cell counts)
+    ("serving_5001", lambda: C.serving_request(5001, size_scale=0.03), "synthetic"),
+    ("serving_5007", lambda: C.serving_request(5007, size_scale=0.03), "synthetic"),
 ]
 
 
@@ -143,18 +147,24 @@ def _one_sweep_check(p, precision, systems, bar):
         e_gpu = N.nbte_get_distribution(h, b, i)
         err = np.max(np.abs(e_gpu - ref[(b, i)])) / np.max(np.abs(ref[(b, i)]))
         worst = max(worst, err)
-    return worst
+    return worst, N.nbte_get_stats(h)["max_levels"]
 
 
-@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("mixed", 1e-6)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("which", ["config2", "config3"])
-def test_one_sweep_full_size_sampled_systems(which, precision, bar):
+def test_one_sweep_full_size_sampled_systems(which, precision):
+    """One sweep from a rough theta (smooth field plus noise).  FP64: 1e-12.
+    Mixed: the sweep runs in FP32; each upwind update rounds at most seven
+    times (three products of the gain, numerator, denominator, reciprocal and
+    product) and passes its error on with a weight below one, so along a
+    path of L levels the relative error stays below 7 L 2^-24."""
     p = C.config2() if which == "config2" else C.config3()
     rng = np.random.default_rng(7)
     systems = [(int(rng.integers(p.n_bands)), int(rng.integers(p.n_dirs))) for _ in range(12)]
     systems += [(0, 0), (p.n_bands - 1, p.n_dirs - 1)]
-    worst = _one_sweep_check(p, precision, systems, bar)
-    _log(f"{which}/one_sweep/{precision}", {"err_e": worst, "systems": len(systems)})
+    worst, levels = _one_sweep_check(p, precision, systems, None)
+    bar = 1e-12 if precision == "fp64" else 7 * levels * 2.0 ** -24
+    _log(f"{which}/one_sweep/{precision}", {"err_e": worst, "systems": len(systems), "bar": bar})
     assert worst < bar
 
 

@@ -155,10 +155,10 @@ def config4(n_solves=64, seed=4, **kw):
 # 5: serving stream
 # ----------------------------------------------------------------------------
 
-def _rect_request(rng, seed):
+def _rect_request(rng, seed, size_scale=1.0):
     L = np.exp(rng.uniform(np.log(100), np.log(2000))) * NM
     aspect = np.exp(rng.uniform(np.log(0.5), np.log(2.0)))
-    N = int(np.exp(rng.uniform(np.log(2000), np.log(40000))))
+    N = int(size_scale * np.exp(rng.uniform(np.log(2000), np.log(40000))))
     nx = max(4, int(round(np.sqrt(N * aspect))))
     ny = max(4, int(round(N / nx)))
     xyz, cells, bf, tags = M.structured_quad(np.linspace(0, L * aspect, nx + 1), np.linspace(0, L, ny + 1))
@@ -171,9 +171,9 @@ def _rect_request(rng, seed):
     return "rect2d", 2, xyz, "quad4", cells, bf, tags, bounds, s, w, cen, centre, L
 
 
-def _box_request(rng, seed):
+def _box_request(rng, seed, size_scale=1.0):
     L = np.exp(rng.uniform(np.log(100), np.log(2000))) * NM
-    N = int(np.exp(rng.uniform(np.log(10000), np.log(200000))))
+    N = int(size_scale * np.exp(rng.uniform(np.log(10000), np.log(200000))))
     n = max(4, int(round(N ** (1 / 3))))
     xs = np.linspace(0, L, n + 1)
     xyz, cells = M.structured_hex(xs, xs, xs)
@@ -189,8 +189,8 @@ def _box_request(rng, seed):
     return "box3d", 3, xyz, "hex8", cells, bf, tags, bounds, s, w, cen, np.array([L / 2, L / 2, L]), L
 
 
-def _finfet_request(rng, seed):
-    N = int(np.exp(rng.uniform(np.log(10000), np.log(200000))))
+def _finfet_request(rng, seed, size_scale=1.0):
+    N = int(size_scale * np.exp(rng.uniform(np.log(10000), np.log(200000))))
     scale = (N / 144480.0) ** (1 / 3)
     xs, ys, zs = finfet_grid(scale)
 
@@ -209,13 +209,14 @@ def _finfet_request(rng, seed):
     return "finfet", 3, xyz, "tet4", cells, bf, tags, bounds, s, w, cen, np.array([100, 100, 140]) * NM, 100 * NM
 
 
-def serving_request(seed, families=("rect2d", "box3d", "finfet")):
+def serving_request(seed, families=("rect2d", "box3d", "finfet"), size_scale=1.0):
     """One solve request of the serving stream: family uniform over the three,
-    bands U{8..32}, Gaussian hot spot with peak log-uniform in [1e16, 1e19] W/m^3."""
+    bands U{8..32}, Gaussian hot spot with peak log-uniform in [1e16, 1e19] W/m^3.
+    size_scale < 1 shrinks the cell-count ranges (test sizes)."""
     rng = np.random.default_rng(seed)
     fam = families[int(rng.integers(0, len(families)))]
     gen = {"rect2d": _rect_request, "box3d": _box_request, "finfet": _finfet_request}[fam]
-    kind, dim, xyz, ct, cells, bf, tags, bounds, s, w, cen, centre, L = gen(rng, seed)
+    kind, dim, xyz, ct, cells, bf, tags, bounds, s, w, cen, centre, L = gen(rng, seed, size_scale)
     B = int(rng.integers(8, 33))
     C, v, tau = bose_einstein_bands(rng, B)
     q0 = np.exp(rng.uniform(np.log(1e16), np.log(1e19)))
