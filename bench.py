@@ -125,17 +125,21 @@ def bench_serving(args, N):
 
 
 def sweep_algorithmic_bytes(p, precision):
-    """Compulsory HBM bytes of one sweep launch: every stored distribution
-    value written once, boundary inflow and per-cell data read once."""
+    """Compulsory HBM bytes of one sweep launch: every distribution value
+    written once; the level-ordered streams of every (direction, cell) read
+    once (cell, slot, up to F-1 upwind references, their coefficients, the
+    outflow sum, the imbalance term D and the source, the real-valued ones in
+    the storage type); the boundary inflow of every incoming (face, direction)
+    read once.  Returns (bytes per launch, bytes per update)."""
     es = 4 if precision == "mixed" else 8
     N, B, D = p.n_cells, p.n_bands, p.n_dirs
     F = {"tri3": 3, "quad4": 4, "tet4": 4, "hex8": 6}[p.cell_type]
-    n_bf = len(p.bfaces)
+    mi = {"tri3": 2, "quad4": 2, "tet4": 3, "hex8": 3}[p.cell_type]   # most upwind faces of one cell
     dist = N * B * D * es
-    inflow = n_bf * (D // 2) * B * 8          # incoming half of the directions
-    cells = N * (F * (24 + 4) + 8 + 8 + 8)    # S, nbr, 1/V, theta, Q
-    sched = N * D * 4                          # level-ordered cell lists
-    return dist + inflow + cells + sched, dist / (N * B * D)
+    streams = D * N * (4 + 4 + 4 * mi + es * (mi + 3))
+    inflow = len(p.bfaces) * (D // 2) * B * es             # incoming half of the directions
+    total = dist + streams + inflow
+    return total, total / (N * B * D)
 
 
 def kernel_source_hash():
@@ -156,6 +160,57 @@ def counter_traffic(workload_name, precision):
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return d.get("traffic_bytes_per_launch")
+
+
+def _counter_rows(d):
+    """rows of a rocprofv3 --pmc CSV output directory"""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _median_counter(rows, name_part, counter, pick_largest_grid=False):
+    vals = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
+            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        return None
+    if pick_largest_grid:
+        g = max(v[0] for v in vals)
+        vals = [v for v in vals if v[0] == g]
+    xs = sorted(v[1] for v in vals)
+    return xs[len(xs) // 2]
+
+
+def summarize_counters(args):
+    """Write the sweep's HBM traffic per launch from four rocprofv3 --pmc runs
+    (FETCH_SIZE and WRITE_SIZE of the bench, then of the copy probe) into
+    profiles/sweep_<workload>_<precision>_counters.json.  The counters (KiB per
+    dispatch) are scaled by what they read for a device copy of known size."""
+    fd, wd, cfd, cwd = args.summarize
+    probe = args.copy_probe_bytes
+    fetch = _median_counter(_counter_rows(fd), "k_sweep", "FETCH_SIZE")
+    write = _median_counter(_counter_rows(wd), "k_sweep", "WRITE_SIZE")
+    cf = _median_counter(_counter_rows(cfd), "copyBuffer", "FETCH_SIZE", pick_largest_grid=True)
+    cw = _median_counter(_counter_rows(cwd), "copyBuffer", "WRITE_SIZE", pick_largest_grid=True)
+    ffac, wfac = probe / (cf * 1024.0), probe / (cw * 1024.0)
+    traffic = fetch * 1024.0 * ffac + write * 1024.0 * wfac
+    out = {"kernel": "k_sweep", "workload": args.workload, "precision": args.precision,
+           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+           "copy_probe_bytes": probe, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": ffac, "write_scale": wfac, "traffic_bytes_per_launch": traffic,
+           "kernel_source_sha256_16": kernel_source_hash(),
+           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
+                        "--steps 3 --warmup 1 --no-cpu --no-converge",
+                        "rocprofv3 --pmc WRITE_SIZE (same)",
+                        f"rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE -- python bench.py --copy-probe {probe >> 20}"]}
+    path = os.path.join(ROOT, "profiles", f"sweep_{args.workload}_{args.precision}_counters.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(p, iters):
@@ -196,7 +251,13 @@ def main():
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--summarize", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the sweep's counter traffic summary from rocprofv3 --pmc outputs and exit")
+    ap.add_argument("--copy-probe-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
+    if args.summarize:
+        summarize_counters(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the per-GPU path is what is measured, sharding is described in DESIGN.md", file=sys.stderr)
@@ -311,7 +372,7 @@ def main():
                    "cell_type": p.cell_type, "scheme": p.scheme, "precision": args.precision,
                    "updates_per_step": ups},
         "roofline": roofline, "cpu_baseline": cpu, "converge": converge,
-        "phases_ms_per_step": phases, "bytes_per_update_stored": per_update,
+        "phases_ms_per_step": phases, "algorithmic_bytes_per_update": per_update,
         "sweep_shape": {k: st[k] for k in ("bands_per_block", "bands_per_lane", "block_size", "lds_slots",
                                            "spilled_values", "max_levels")},
     }

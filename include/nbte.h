@@ -148,6 +148,9 @@ typedef struct {
     const double *T_init;    /* nullable host array (n_cells): initial T_L; NULL = Fourier guess */
     int32_t outputs_on_device; /* 1: result arrays are device pointers */
     int32_t time_phases;     /* 1: record per-phase HIP-event times (see nbte_get_stats) */
+    int32_t refine;          /* mixed precision only (default 1): when the FP32 iteration stops
+                                improving (no 2% residual gain in 64 iterations) before reaching
+                                tol, the solve continues with FP64 sweeps from where it stands */
 } nbte_solve_opts;
 
 /* Fill opts with the defaults listed above. */
@@ -213,6 +216,7 @@ typedef struct {
     int32_t block_size;
     int32_t lds_slots;         /* staged slots per direction (0: staging off) */
     int64_t spilled_values;    /* consumed values per sweep that did not fit the LDS budget */
+    int32_t refined_at;        /* iteration at which a mixed solve switched to FP64 sweeps, -1 if not */
 } nbte_stats;
 nbte_status nbte_get_stats(nbte_problem *p, nbte_stats *st);
 

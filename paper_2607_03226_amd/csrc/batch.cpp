@@ -117,6 +117,20 @@ nbte_status nbte_batch_poll(nbte_batch *b, nbte_problem **done, int32_t cap, int
     return guarded([&] {
         if (!b || cap < 0 || (cap > 0 && !done)) throw Error(NBTE_ERR_INVALID_ARG, "bad arguments");
         b->runner->collect();
+        // mixed members whose FP32 iteration stalled continue in FP64
+        bool changed = false;
+        for (size_t k = 0; k < b->members.size(); ++k) {
+            nbte_problem *p = b->members[k];
+            if (p->hs.done != NBTE_DONE_STALLED) continue;
+            p->promote();
+            int64_t need = 0;   // charge the FP64 footprint from now on
+            if (nbte_problem_footprint(p, NBTE_PREC_FP64, &need) == NBTE_OK) {
+                b->in_use += need - b->charged[k];
+                b->charged[k] = need;
+            }
+            changed = true;
+        }
+        if (changed) b->runner->set_members(b->members);
         int32_t nd = 0, nr = 0;
         for (nbte_problem *p : b->members) {
             if (p->hs.done) {

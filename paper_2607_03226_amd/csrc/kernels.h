@@ -32,12 +32,15 @@ struct SolveState {
     int32_t done;         // 0 running; NBTE_DONE_* once stopped (kernels then skip the solve)
     int32_t stop;         // host: 1 = stop at tol / max_iter, 0 = run every launched iteration
     int32_t max_iter;
-    int32_t pad;
+    int32_t patience;     // stop as STALLED after this many iterations without a 2% residual gain (0: off)
     double tol;           // residual tolerance
     double residual;      // max|theta_new - theta| / max|theta_new| of the last iteration
+    double best;          // smallest residual so far (since the last controls were set)
+    int32_t since;        // iterations since best improved by 2%
+    int32_t pad;
     unsigned long long maxbuf[2];   // running maxima of the update (ordered bit patterns)
 };
-enum { NBTE_DONE_CONVERGED = 1, NBTE_DONE_MAX_ITER = 2, NBTE_DONE_DIVERGED = 3 };
+enum { NBTE_DONE_CONVERGED = 1, NBTE_DONE_MAX_ITER = 2, NBTE_DONE_DIVERGED = 3, NBTE_DONE_STALLED = 4 };
 
 // Jacobi-preconditioned conjugate gradients on a symmetric positive definite
 // CSR matrix (the synthetic correction); per-solve work arrays.
@@ -160,8 +163,11 @@ constexpr int64_t kPcgBlockMaxRows = 8192;   // larger systems use the multi-wor
 
 // Iteration state: clear the stop flag and set the stop rule of a solve;
 // copy the states of a list of solves into out[0..n).
-void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, hipStream_t st);
+void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, int patience, hipStream_t st);
 void launch_collect_states(const DeviceView *vs, int n, SolveState *out, hipStream_t st);
+
+// out[k] = in[k] widened to FP64
+void launch_widen(int64_t n, const float *in, double *out, hipStream_t st);
 
 // Single-solve helpers (outside the iteration).
 // out[k] = offset + scale * in[k]

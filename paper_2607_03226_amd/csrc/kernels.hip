@@ -710,18 +710,34 @@ __global__ void k_finish(const DeviceView *__restrict__ vs, const WorkItem *__re
     s->maxbuf[1] = 0ull;
     s->iterations += 1;
     s->rot = (s->rot + 1) % 3;
+    if (res < 0.98 * s->best) {
+        s->best = res;
+        s->since = 0;
+    } else {
+        s->since += 1;
+    }
     if (!(res <= 1e300)) s->done = NBTE_DONE_DIVERGED;
     else if (s->stop && res <= s->tol) s->done = NBTE_DONE_CONVERGED;
     else if (s->stop && s->iterations >= s->max_iter) s->done = NBTE_DONE_MAX_ITER;
+    else if (s->stop && s->patience > 0 && s->since >= s->patience) s->done = NBTE_DONE_STALLED;
 }
 
-__global__ void k_set_controls(SolveState *s, int stop, double tol, int max_iter) {
+__global__ void k_set_controls(SolveState *s, int stop, double tol, int max_iter, int patience) {
     if (threadIdx.x == 0) {
         s->done = 0;
         s->stop = stop;
         s->tol = tol;
         s->max_iter = max_iter;
+        s->patience = patience;
+        s->best = INFINITY;
+        s->since = 0;
     }
+}
+
+// FP32 distribution -> FP64 (switch of a solve to FP64 sweeps)
+__global__ void k_widen(int64_t n, const float *in, double *out) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = static_cast<double>(in[k]);
 }
 
 __global__ void k_collect_states(const DeviceView *__restrict__ vs, int n, SolveState *out) {
@@ -1061,8 +1077,14 @@ void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, int mode,
         hipLaunchKernelGGL(k_cg1_iter, dim3(n), dim3(256), 0, st, vs, wk, mode, k, rtol2_o, max_o);
 }
 
-void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, hipStream_t st) {
-    hipLaunchKernelGGL(k_set_controls, dim3(1), dim3(64), 0, st, s, stop, tol, max_iter);
+void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, int patience, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_controls, dim3(1), dim3(64), 0, st, s, stop, tol, max_iter, patience);
+}
+
+void launch_widen(int64_t n, const float *in, double *out, hipStream_t st) {
+    if (n <= 0) return;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_widen, dim3(grid), dim3(256), 0, st, n, in, out);
 }
 
 void launch_collect_states(const DeviceView *vs, int n, SolveState *out, hipStream_t st) {

@@ -182,6 +182,11 @@ struct nbte_problem {
     void prepare(const double *Q_cell, const nbte_solve_opts &o);
     // device state: stop rule for the following iterations (clears the stop flag)
     void set_controls(int stop, double tol, int max_iter);
+    // continue a mixed solve that stopped improving with FP64 sweeps (keeps theta,
+    // the distribution and the iteration count)
+    void promote();
+    bool refine = true;      // mixed: switch to FP64 when the FP32 iteration stalls
+    int refined_at = -1;
     int stop_mode = 0;
     double stop_tol = 0.0;
     int stop_max_iter = 0;

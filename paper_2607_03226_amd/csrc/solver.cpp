@@ -408,6 +408,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     SolveState s0{};
     s0.max_iter = o.max_iter;
     s0.tol = o.tol;
+    s0.best = INFINITY;
     NBTE_HIP(hipMemcpyAsync(d_state.ptr, &s0, sizeof(s0), hipMemcpyHostToDevice, stream));
     NBTE_HIP(hipMemcpyAsync(d_Q.ptr, Q.data(), m.N * 8, hipMemcpyHostToDevice, stream));
     launch_gather((int64_t)quad.D * m.N, d_pcell.as<int32_t>(), d_Q.as<double>(), d_tq.ptr, fp32(), stream);
@@ -437,6 +438,8 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     stop_mode = 0;
     stop_tol = o.tol;
     stop_max_iter = o.max_iter;
+    refine = o.refine != 0;
+    refined_at = -1;
     if (!solo) solo = std::make_unique<Runner>(stream);
     solo->set_members({this});
     solo->set_timing(time_phases != 0);
@@ -447,13 +450,35 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
 }
 
 void nbte_problem::set_controls(int stop, double tol, int max_iter) {
-    launch_set_controls(d_state.as<SolveState>(), stop, tol, max_iter, stream);
+    const int patience = (stop && fp32() && refine) ? 64 : 0;
+    launch_set_controls(d_state.as<SolveState>(), stop, tol, max_iter, patience, stream);
     NBTE_HIP(hipGetLastError());
     NBTE_HIP(hipStreamSynchronize(stream));
     stop_mode = stop;
     stop_tol = tol;
     stop_max_iter = max_iter;
     hs.done = 0;
+}
+
+void nbte_problem::promote() {
+    if (!fp32()) return;
+    NBTE_HIP(hipStreamSynchronize(stream));
+    const int64_t n = mesh->N * (int64_t)bands.B * quad.D;
+    DevBuf old_g;   // the FP32 distribution, widened into the new FP64 one below
+    std::swap(old_g.ptr, d_g.ptr);
+    std::swap(old_g.bytes, d_g.bytes);
+    precision = NBTE_PREC_FP64;
+    ensure_setup();   // launch shape and slot table for FP64 staged values
+    allocate_state(precision);
+    launch_widen(n, old_g.as<float>(), d_g.as<double>(), stream);
+    launch_gather((int64_t)quad.D * mesh->N, d_pcell.as<int32_t>(), d_Q.as<double>(), d_tq.ptr, false, stream);
+    make_view();
+    NBTE_HIP(hipMemcpyAsync(d_view.ptr, &hv, sizeof(DeviceView), hipMemcpyHostToDevice, stream));
+    NBTE_HIP(hipGetLastError());
+    NBTE_HIP(hipStreamSynchronize(stream));
+    refined_at = hs.iterations;
+    set_controls(stop_mode, stop_tol, stop_max_iter);
+    if (solo) solo->set_members({this});
 }
 
 void nbte_problem::sync_state() {
@@ -537,6 +562,7 @@ void nbte_problem::collect_stats() {
     stats.block_size = shape.block;
     stats.lds_slots = shape.slots > 0 ? sched.max_slots : 0;
     stats.spilled_values = sched.spilled;
+    stats.refined_at = refined_at;
 }
 
 // ============================================================================ ABI
@@ -673,6 +699,7 @@ void nbte_solve_opts_default(nbte_solve_opts *o) {
     o->T_init = nullptr;
     o->outputs_on_device = 0;
     o->time_phases = 0;
+    o->refine = 1;
 }
 
 nbte_status nbte_prepare(nbte_problem *p, const double *Q_cell, const nbte_solve_opts *o) {
@@ -711,9 +738,13 @@ nbte_status nbte_solve_steady(nbte_problem *p, const double *Q_cell, const nbte_
         // only polls, so the result does not depend on check_every
         const int every = std::max(1, o->check_every);
         auto t0 = std::chrono::steady_clock::now();
-        for (int64_t polls = 0; polls <= (int64_t)o->max_iter / every + 2; ++polls) {
+        for (int64_t polls = 0; polls <= (int64_t)o->max_iter / every + 4; ++polls) {
             p->solo->run(every);
             p->solo->collect();
+            if (p->hs.done == NBTE_DONE_STALLED) {
+                p->promote();   // FP32 floor reached: continue in FP64
+                continue;
+            }
             if (p->hs.done) break;
         }
         p->stats.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

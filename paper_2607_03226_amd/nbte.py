@@ -36,7 +36,7 @@ class Boundary(ct.Structure):
 class SolveOpts(ct.Structure):
     _fields_ = [("scheme", ct.c_int32), ("precision", ct.c_int32), ("T_ref", ct.c_double), ("tol", ct.c_double),
                 ("max_iter", ct.c_int32), ("check_every", ct.c_int32), ("T_init", _d),
-                ("outputs_on_device", ct.c_int32), ("time_phases", ct.c_int32)]
+                ("outputs_on_device", ct.c_int32), ("time_phases", ct.c_int32), ("refine", ct.c_int32)]
 
 
 class Result(ct.Structure):
@@ -55,7 +55,7 @@ class Stats(ct.Structure):
                 ("ms_update", ct.c_double), ("sweep_launches", ct.c_int32), ("updates_per_sweep", ct.c_int64),
                 ("max_levels", ct.c_int32), ("device_bytes", ct.c_int64), ("bands_per_block", ct.c_int32),
                 ("bands_per_lane", ct.c_int32), ("block_size", ct.c_int32), ("lds_slots", ct.c_int32),
-                ("spilled_values", ct.c_int64)]
+                ("spilled_values", ct.c_int64), ("refined_at", ct.c_int32)]
 
 
 class BatchInfo(ct.Structure):
@@ -241,13 +241,14 @@ def nbte_solve_opts_default():
 
 
 def make_opts(scheme="synthetic", precision="fp64", T_ref=300.0, tol=1e-8, max_iter=10000, check_every=8,
-              T_init=None, outputs_on_device=False, time_phases=False):
+              T_init=None, outputs_on_device=False, time_phases=False, refine=True):
     o = nbte_solve_opts_default()
     o.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.T_ref, o.tol, o.max_iter, o.check_every = float(T_ref), float(tol), int(max_iter), int(check_every)
     o.outputs_on_device = int(bool(outputs_on_device))
     o.time_phases = int(bool(time_phases))
+    o.refine = int(bool(refine))
     o._keep = None
     if T_init is not None:
         t = _f64(T_init)

@@ -148,3 +148,26 @@ def test_batch_stops_at_max_iter_and_reports_it():
     assert [d.handle.value for d in done] == [h.handle.value] and running == 0
     out = N.nbte_read_result(h)
     assert out["iterations"] == 7
+
+
+def test_stalled_mixed_member_continues_in_fp64():
+    N = _N()
+    specs = [(C.config1(), 1e-11), (C.config2_small(), 1e-8)]
+    alone = []
+    for p, tol in specs:
+        mesh, h = N.build_problem(p)
+        out = N.nbte_solve_steady(h, p.Q, N.make_opts(scheme=p.scheme, precision="mixed", T_ref=p.T_ref, tol=tol,
+                                                       max_iter=20000))
+        alone.append((out, N.nbte_get_stats(h)["refined_at"]))
+    assert alone[0][1] > 0
+    batch = N.nbte_batch_create()
+    handles, keep = [], []
+    for p, tol in specs:
+        mesh, h = N.build_problem(p)
+        keep.append(mesh)
+        N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision="mixed", T_ref=p.T_ref, tol=tol,
+                                                       max_iter=20000))
+        handles.append(h)
+    res = _drain(N, batch, handles, step=16, limit=40000)
+    for h, (a, refined_at) in zip(handles, alone):
+        _same(res[h.handle.value], a)

@@ -254,3 +254,24 @@ def test_graph_replays_match_eager_iterations():
         outs[mode] = snaps
     for a, b in zip(outs["eager"], outs["graph"]):
         assert np.array_equal(a, b)
+
+
+def test_mixed_solve_that_stalls_continues_in_fp64():
+    """The FP32 iteration of the gray square levels off near 5e-8; with
+    refinement on, the solve switches to FP64 sweeps and reaches 1e-11."""
+    N = _N()
+    p = C.config1()
+    ref = _oracle("config1", p)
+    mesh, h = N.build_problem(p)
+    out = N.nbte_solve_steady(h, p.Q, N.make_opts(scheme="sequential", precision="mixed", T_ref=p.T_ref, tol=1e-11,
+                                                   max_iter=20000))
+    st = N.nbte_get_stats(h)
+    rec = _errors(out, ref, p.T_ref)
+    rec.update(iterations=out["iterations"], refined_at=st["refined_at"])
+    _log("config1/mixed_refined", rec)
+    assert st["refined_at"] > 0
+    assert max(rec["err_TL"], rec["err_T"], rec["err_q"]) < 1e-9, rec
+    with pytest.raises(N.NbteError) as e:   # without refinement the FP32 floor stops it
+        N.nbte_solve_steady(h, p.Q, N.make_opts(scheme="sequential", precision="mixed", T_ref=p.T_ref, tol=1e-11,
+                                                max_iter=3000, refine=False))
+    assert e.value.status == N.ERR_NOT_CONVERGED
