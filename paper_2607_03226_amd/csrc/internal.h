@@ -143,14 +143,15 @@ struct SweepProgram {
     std::vector<int32_t> in_row;            // NBF*D: ghost row of incoming (bf, i), -1 otherwise
     int max_ghosts = 0;                     // most ghosts of one level
 };
-// record reference ranges (shared with the sweep kernel): >= 0 LDS slot;
-// [-kSpillBase, -1] ghost of the level kept in LDS, -1 - rank;
-// [-2 kSpillBase, -kSpillBase - 1] ghost read from HBM, -kSpillBase - 1 - row;
-// below: stored value of the upwind cell at stream position k of the same
-// direction, -(2 kSpillBase + 2) - k (its cell index and theta are read from
-// the streams, so a program does not depend on where theta lives)
+// record reference encoding (shared with the sweep kernel): >= 0 an element
+// offset in the workgroup's LDS (a staged value: ring_off + slot ls; a ghost
+// of the level kept in LDS: gbuf0 + (level & 1) gstride + rank ls; see
+// sweep_lds_layout); [-kSpillBase, -1] ghost read from HBM, -1 - row; below:
+// the stored value of the upwind cell at stream position k of the same
+// direction, -(kSpillBase + 1) - k.  The own slot ("mine") is the element
+// offset of the staged value, or -1.
 constexpr int32_t kSpillBase = 1 << 24;
-SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap);
+SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap, int ls, int es);
 
 // Boundary plan: per boundary face kind/wall data, s.S per direction and the
 // specular mirror table.

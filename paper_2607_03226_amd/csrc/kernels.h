@@ -145,6 +145,22 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
                   int block, size_t lds_bytes, hipStream_t st);
 size_t sweep_lds_bytes(int max_levels, int gcap, int lstride, int slots, int elem_bytes);
+
+// Dynamic LDS of a sweep workgroup, in elements of the storage type (es
+// bytes): [level tables: 2 (max_levels + 1) ints][ghost buffers of the two
+// level parities: 2 x gcap x ls][staged values: slots x ls].  Shared by the
+// host (which encodes upwind references as final LDS offsets) and the kernel.
+struct SweepLdsLayout {
+    int ls, gbuf0, gstride, ring_off;
+};
+__host__ __device__ inline SweepLdsLayout sweep_lds_layout(int max_levels, int gcap, int ls, int es) {
+    SweepLdsLayout L;
+    L.ls = ls;
+    L.gbuf0 = (2 * (max_levels + 1) * 4) / es;
+    L.gstride = gcap * ls;
+    L.ring_off = L.gbuf0 + 2 * L.gstride;
+    return L;
+}
 // LDS stride (doubles) of a staged value's bands: they are contiguous, so
 // two-band blocks are read with 16-byte LDS loads (padding the stride to an
 // odd count, to spread random slots over the banks, measured slower)
@@ -158,7 +174,9 @@ inline int sweep_lds_stride(int bpb) { return bpb; }
 // one launch per iteration): items (solve, -, local block, nblk); max_iter
 // is the largest iteration count of the listed solves, each stops at its own.
 void launch_pcg_block(const DeviceView *vs, const WorkItem *wk, int n, int mode, hipStream_t st);
-void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, int mode, int max_iter, hipStream_t st);
+// (k0, init: continue an earlier call from iteration k0 without the initial step)
+void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, int mode, int max_iter, hipStream_t st,
+                      int k0 = 0, bool init = true);
 constexpr int64_t kPcgBlockMaxRows = 8192;   // larger systems use the multi-workgroup form
 
 // Iteration state: clear the stop flag and set the stop rule of a solve;

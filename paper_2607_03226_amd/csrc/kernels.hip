@@ -225,8 +225,9 @@ extern __shared__ float sweep_ldsf[];  // ... and as floats (FP32 staged values)
 
 constexpr int kGhostPerThread = 2;    // ghost values a thread prefetches per level
 constexpr int kPrefetch = 4;          // passes whose records are in flight ahead of the computed one
-// record references: >= 0 LDS slot; [-kSpill, -1] ghost of the level in LDS (rank);
-// [-2 kSpill, -kSpill - 1] ghost read from HBM (row); below: spilled cell
+// record references: >= 0 LDS element offset (staged value or ghost kept in
+// LDS); [-kSpill, -1] ghost read from HBM (row -1 - ref); below: the stored
+// copy of a spilled value at stream position -(kSpill + 1) - ref
 constexpr int32_t kSpill = 1 << 24;
 
 // The sweep works in the deviation from local equilibrium,
@@ -238,6 +239,18 @@ constexpr int32_t kSpill = 1 << 24;
 // uses sum_{a<0} |a| = sum_{a>0} a of a closed cell).  g is small wherever
 // theta is smooth, so the FP32 form of the mixed path rounds relative to the
 // deviation, not to e; the FP64 path runs the same form in FP64.
+
+// element k of a global array through a 32-bit byte offset from a uniform
+// base (one VGPR offset shared by every stream; the address is formed by the
+// load itself)
+template <class T>
+__device__ __forceinline__ T gload(const T NBTE_G *base, uint32_t k) {
+    return *reinterpret_cast<const T NBTE_G *>(reinterpret_cast<const char NBTE_G *>(base) + k * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void gstore(T NBTE_G *base, uint32_t k, T x) {
+    *reinterpret_cast<T NBTE_G *>(reinterpret_cast<char NBTE_G *>(base) + k * (uint32_t)sizeof(T)) = x;
+}
 
 // One cell's sweep record (a position of a direction's level-ordered streams).
 template <class T, int MI>
@@ -255,19 +268,20 @@ __device__ __forceinline__ void load_rec(SweepRec<T, MI> &r, const DeviceView &v
     // the loads are issued on every path (a past-the-end record reads stream
     // position 0 of the direction), so the number of loads in flight is the
     // same on every path and a later wait on an older record can leave the
-    // younger prefetches outstanding
+    // younger prefetches outstanding.  Stream positions fit 32 bits.
     r.ok = k < kend;
-    const int64_t at = base + (r.ok ? k : 0);
+    const uint32_t at = (uint32_t)(base + (r.ok ? k : 0));
+    const uint32_t dn = (uint32_t)DN;
     const T NBTE_G *coef = static_cast<const T NBTE_G *>(v.t_coef);
-    r.c = v.p_cell[at];
-    r.mine = v.p_slot[at];
-    r.sout = static_cast<const T NBTE_G *>(v.t_sout)[at];
-    r.dc = static_cast<const T NBTE_G *>(v.t_dc)[at];
-    r.q = static_cast<const T NBTE_G *>(v.t_q)[at];
+    r.c = gload(v.p_cell, at);
+    r.mine = gload(v.p_slot, at);
+    r.sout = gload(static_cast<const T NBTE_G *>(v.t_sout), at);
+    r.dc = gload(static_cast<const T NBTE_G *>(v.t_dc), at);
+    r.q = gload(static_cast<const T NBTE_G *>(v.t_q), at);
 #pragma unroll
     for (int j = 0; j < MI; ++j) {
-        r.ref[j] = v.p_ref[j * DN + at];
-        r.cf[j] = coef[j * DN + at];
+        r.ref[j] = gload(v.p_ref + j * dn, at);
+        r.cf[j] = gload(coef + j * dn, at);
     }
 }
 
@@ -300,8 +314,7 @@ __device__ __forceinline__ float quot(float a, float b) { return a * __builtin_a
 
 template <class T, int MI, int BPL>
 __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const DeviceView &v, const BandConst<T, BPL> &bc,
-                                           T *gi, int64_t base, int ring_off, int gbuf_off, int ls,
-                                           int b0, int lane, int nb_here) {
+                                           T NBTE_G *gi, int64_t base, int b0, int lane, int nb_here) {
     const int B = v.B;
     const T NBTE_G *gval = static_cast<const T NBTE_G *>(v.gval);
 #pragma unroll
@@ -316,15 +329,13 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
             const int rf = r.ref[j];
             T up;
             if (rf >= 0) {
-                up = lds_get<T>(ring_off + rf * ls + lb);
+                up = lds_get<T>(rf + lb);   // staged value or ghost kept in LDS
             } else if (rf >= -kSpill) {
-                up = lds_get<T>(gbuf_off + (-1 - rf) * ls + lb);
-            } else if (rf >= -2 * kSpill) {
-                up = gval[(int64_t)(-kSpill - 1 - rf) * B + lam];   // ghost beyond the LDS capacity
+                up = gval[(int64_t)(-1 - rf) * B + lam];   // ghost beyond the LDS capacity
             } else {
                 // value without an LDS slot: its stored copy, located through
                 // the neighbour's position in this direction's streams
-                const int n = v.p_cell[base + (-(2 * kSpill + 2) - rf)];
+                const int n = v.p_cell[base + (-(kSpill + 1) - rf)];
                 up = gi[(int64_t)n * B + lam];
             }
             gain += r.cf[j] * up;
@@ -332,7 +343,7 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
         const T vel = bc.vel[jb];
         const T g = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
         gi[(int64_t)r.c * B + lam] = g;
-        if (r.mine >= 0) lds_put<T>(ring_off + r.mine * ls + lb, g);
+        if (r.mine >= 0) lds_put<T>(r.mine + lb, g);
     }
 }
 
@@ -342,17 +353,9 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
 // (coefficient 0) masked by a select, past-the-end records computed but not
 // stored, so the items of a thread interleave.
 template <class T, int MI, int BPL>
-__device__ __forceinline__ void sweep_cell_lds(const SweepRec<T, MI> &r, const BandConst<T, BPL> &bc, T *gi, int B,
-                                               int ring_off, int gbuf_off, int ls, int b0, int lane,
-                                               int nb_here) {
-    int off[MI];
-#pragma unroll
-    for (int j = 0; j < MI; ++j) {
-        const int rf = r.ref[j];
-        off[j] = rf >= 0 ? ring_off + rf * ls : gbuf_off + (-1 - rf) * ls;
-    }
-    T *gc = gi + (int64_t)r.c * B + b0;
-    const int mine = ring_off + r.mine * ls;
+__device__ __forceinline__ void sweep_cell_lds(const SweepRec<T, MI> &r, const BandConst<T, BPL> &bc, T NBTE_G *gi,
+                                               int B, int ls, int b0, int lane, int nb_here) {
+    const uint32_t gc = (uint32_t)r.c * (uint32_t)B + (uint32_t)b0;   // within one direction's slice
 #pragma unroll
     for (int jb = 0; jb < BPL; ++jb) {
         const int lb = lane * BPL + jb;
@@ -361,14 +364,14 @@ __device__ __forceinline__ void sweep_cell_lds(const SweepRec<T, MI> &r, const B
         T gain = 0;
 #pragma unroll
         for (int j = 0; j < MI; ++j) {
-            const T up = lds_get<T>(off[j] + lr);
+            const T up = lds_get<T>(r.ref[j] + lr);
             gain += r.cf[j] != T(0) ? r.cf[j] * up : T(0);
         }
         const T vel = bc.vel[jb];
         const T g = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
         if (on) {
-            gc[lb] = g;
-            if (r.mine >= 0) lds_put<T>(mine + lb, g);
+            gstore(gi, gc + lb, g);
+            if (r.mine >= 0) lds_put<T>(r.mine + lb, g);
         }
     }
 }
@@ -429,17 +432,17 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     const int64_t N = v.N;
     const int B = v.B;
     const int64_t DN = (int64_t)v.D * N;
-    T *gi = static_cast<T *>(v.g) + (int64_t)i * N * B;
+    T NBTE_G *gi = static_cast<T NBTE_G *>(v.g) + (int64_t)i * N * B;
     const int64_t base = (int64_t)i * N;
     const int nlev = v.lvl_off[i + 1] - v.lvl_off[i] - 1;
     const int nb_here = min(B, b0 + bands_per_block) - b0;
     const int ML = v.max_levels + 1;
 #define lp(t) sweep_ldsi[(t)]
 #define gp(t) sweep_ldsi[ML + (t)]
-    const int gbuf0 = (2 * ML * (int)sizeof(int)) / (int)sizeof(T);   // first element after the tables
-    const int ls = v.lstride;
-    const int gstride = gcap * ls;                      // ghosts of a level kept in LDS (rank < gcap)
-    const int ring_off = gbuf0 + 2 * gstride;
+    const SweepLdsLayout lay = sweep_lds_layout(v.max_levels, gcap, v.lstride, (int)sizeof(T));
+    const int ls = lay.ls;
+    const int gbuf0 = lay.gbuf0;       // first element after the level tables
+    const int gstride = lay.gstride;   // ghosts of a level kept in LDS (rank < gcap)
     {
         const int32_t *glp = v.lvl_ptr + v.lvl_off[i];
         const int32_t *ggp = v.gptr + v.lvl_off[i];
@@ -484,7 +487,7 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
             const int e = threadIdx.x + m * blockDim.x;
             const int q = e / bands_per_block, lb = e - q * bands_per_block;
             const bool ok = e < ne && lb < nb_here;
-            const T x = gval[ok ? (int64_t)(g0 + q) * B + b0 + lb : 0];
+            const T x = gload(gval, ok ? (uint32_t)((g0 + q) * B + b0 + lb) : 0u);
             h.v[m] = ok ? x : T(0);
         }
     };
@@ -524,11 +527,10 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     // computed last, now free); returns false when the sweep is done
     auto step = [&](Set &cur, Set &nxt, const Set &after) -> bool {
         fetch(nxt);
-        const int gcur = gbuf0 + (lc & 1) * gstride;
         if constexpr (MODE == kModeLds)
-            sweep_cell_lds<T, MI, BPL>(cur.r, bc, gi, B, ring_off, gcur, ls, b0, lane, nb_here);
+            sweep_cell_lds<T, MI, BPL>(cur.r, bc, gi, B, ls, b0, lane, nb_here);
         else if (cur.r.ok)
-            sweep_cell<T, MI, BPL>(cur.r, v, bc, gi, base, ring_off, gcur, ls, b0, lane, nb_here);
+            sweep_cell<T, MI, BPL>(cur.r, v, bc, gi, base, b0, lane, nb_here);
         kc += nslots;
         if (kc >= lp(lc + 1)) {   // level done
             ++lc;
@@ -573,6 +575,10 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
     if (!after && v.state->done) return;
     const int64_t bf = (int64_t)it.b * 4 + (threadIdx.x >> 6);
     if (bf >= v.NBF) return;
+    // inside the iteration only reflective walls' flows are used (the
+    // correction's right-hand side); thermalizing ones matter for the energy
+    // balance read at the end
+    if (!after && v.bf_kind[bf] == NBTE_BC_THERMALIZING) return;
     const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
@@ -599,7 +605,8 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
 
 // --------------------------------------------------------------------------
 // band x direction reductions (Methods, Eqs. (5), (7); T = energy temperature)
-// mom_lpc lanes per cell, FP64 accumulation, shuffle reduction over the lanes.
+// mom_lpc lanes per cell (bands x direction groups), FP64 accumulation,
+// shuffle reduction over the lanes in a fixed order.
 // Synthetic schemes also get the V-weighted right-hand side of the correction:
 //   V (Qdot - D_h' q) = V beta (theta_seq - theta) + sum_{reflective f} J_f
 // (collision-divergence identity; reflective walls carry zero net flux at the
@@ -610,19 +617,23 @@ __global__ void __launch_bounds__(256) k_moments(const DeviceView *__restrict__ 
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (v.state->done) return;
+    // lanes of a cell: lb band lanes x (lpc / lb) direction groups
     const int lpc = v.mom_lpc;
-    const int64_t c = ((int64_t)it.b * blockDim.x + threadIdx.x) / lpc;
-    const int lane = threadIdx.x % lpc;
     const int64_t N = v.N;
     const int B = v.B, D = v.D;
+    int lb = 1;
+    while (lb < B && lb < 64) lb <<= 1;
+    const int64_t c = ((int64_t)it.b * blockDim.x + threadIdx.x) / lpc;
+    const int lane = threadIdx.x % lpc;
+    const int bl = lane % lb, dg = lane / lb, ng = lpc / lb;
     const T *g = static_cast<const T *>(v.g);
     double a_tau = 0, a_w = 0, qx = 0, qy = 0, qz = 0;
     if (c < N) {
-        for (int lam = lane; lam < B; lam += lpc) {
+        for (int lam = bl; lam < B; lam += lb) {
             double sw = 0, s_x = 0, s_y = 0, s_z = 0;
-            // independent loads, eight directions in flight (summation order unchanged)
+            // independent loads, eight directions of the group in flight
 #pragma unroll 8
-            for (int i = 0; i < D; ++i) {
+            for (int i = dg; i < D; i += ng) {
                 const double ww = v.w[i] * ld(g, ((int64_t)i * N + c) * B + lam);
                 sw += ww;
                 s_x += ww * v.dirs[3 * i];
@@ -1068,12 +1079,13 @@ void launch_pcg_block(const DeviceView *vs, const WorkItem *wk, int n, int mode,
     hipLaunchKernelGGL(k_pcg_block, dim3(n), dim3(1024), 0, st, vs, wk, mode, rtol2_o, max_o);
 }
 
-void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, int mode, int max_iter, hipStream_t st) {
+void launch_pcg_multi(const DeviceView *vs, const WorkItem *wk, int n, int mode, int max_iter, hipStream_t st,
+                      int k0, bool init) {
     if (n <= 0) return;
     const double rtol2_o = mode == 1 ? 1e-24 : -1.0;
-    const int max_o = mode == 1 ? max_iter : -1;
-    hipLaunchKernelGGL(k_cg1_init, dim3(n), dim3(256), 0, st, vs, wk, mode);
-    for (int k = 0; k < max_iter; ++k)
+    const int max_o = mode == 1 ? (1 << 30) : -1;
+    if (init) hipLaunchKernelGGL(k_cg1_init, dim3(n), dim3(256), 0, st, vs, wk, mode);
+    for (int k = k0; k < k0 + max_iter; ++k)
         hipLaunchKernelGGL(k_cg1_iter, dim3(n), dim3(256), 0, st, vs, wk, mode, k, rtol2_o, max_o);
 }
 

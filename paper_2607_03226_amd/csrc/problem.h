@@ -142,7 +142,7 @@ struct nbte_problem {
         int bpb = 1, bpl = 1, block = 256, slots = 0, gcap = 0;
     } shape;
     int slots_for_cap = -2;   // slot budget the current slot table was built for
-    int prog_B = -1, prog_gcap = -1;
+    int prog_B = -1, prog_gcap = -1, prog_ls = -1, prog_es = -1;
     nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0};
 
     // iteration state

@@ -16,6 +16,7 @@
 #include <numeric>
 
 #include "internal.h"
+#include "kernels.h"
 
 namespace nbte {
 
@@ -132,7 +133,8 @@ void assign_slots(const Mesh &m, const Quadrature &q, Schedule &sc, int cap) {
     }
 }
 
-SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap) {
+SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap, int ls, int es) {
+    const SweepLdsLayout lay = sweep_lds_layout(sc.max_levels, gcap, ls, es);
     const int64_t N = m.N;
     const int F = m.F;
     const int D = q.D;
@@ -177,7 +179,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                 const int32_t c = sc.perm[at];
                 pg.cell[at] = c;
                 for (int j = 0; j < pg.maxin; ++j) pg.upc[(size_t)j * DN + at] = c;
-                pg.slot[at] = slot_i ? slot_i[c] : -1;
+                pg.slot[at] = (slot_i && slot_i[c] >= 0) ? lay.ring_off + slot_i[c] * ls : -1;
                 const double iv = 1.0 / m.V[c];
                 double sout = 0.0;
                 int j = 0;
@@ -194,12 +196,12 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                             const int64_t row = (int64_t)pg.ghost_src.size();
                             pg.ghost_src.push_back((bf * D + i) * (int64_t)B);
                             pg.in_row[bf * D + i] = (int32_t)row;
-                            r = rank < gcap ? -1 - rank : -kSpillBase - 1 - (int32_t)row;
+                            r = rank < gcap ? lay.gbuf0 + (l & 1) * lay.gstride + rank * ls : -1 - (int32_t)row;
                             ++rank;
                         } else if (slot_i && slot_i[n] >= 0) {
-                            r = slot_i[n];                             // staged in LDS
+                            r = lay.ring_off + slot_i[n] * ls;         // staged in LDS
                         } else {
-                            r = -(2 * kSpillBase + 2) - pos[n];        // stored copy in HBM
+                            r = -(kSpillBase + 1) - pos[n];            // stored copy in HBM
                         }
                         pg.ref[(size_t)j * DN + at] = r;
                         if (n >= 0) pg.upc[(size_t)j * DN + at] = n;
@@ -214,7 +216,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
         gp[L] = (int32_t)pg.ghost_src.size();
     }
     if ((int64_t)pg.ghost_src.size() >= kSpillBase) throw Error(NBTE_ERR_MESH, "too many boundary inflow rows");
-    if (N >= INT32_MAX - 2 * (int64_t)kSpillBase - 2) throw Error(NBTE_ERR_MESH, "too many cells");
+    if (N >= INT32_MAX - (int64_t)kSpillBase - 1) throw Error(NBTE_ERR_MESH, "too many cells");
     return pg;
 }
 

@@ -132,13 +132,20 @@ void nbte_problem::build_host() {
         slots_for_cap = -2;
     }
     shape = resolve_shape();
-    if (slots_for_cap != shape.slots || prog_B != bands.B || prog_gcap != shape.gcap) {
-        if (shape.slots > 0) assign_slots(m, quad, sched, shape.slots);
-        else sched.slot.clear(), sched.max_slots = 0, sched.spilled = 0;
-        slots_for_cap = shape.slots;
-        prog = build_program(m, quad, sched, bands.B, shape.gcap);
+    const int ls = sweep_lds_stride(shape.bpb), es = fp32() ? 4 : 8;
+    if (slots_for_cap != shape.slots || prog_B != bands.B || prog_gcap != shape.gcap || prog_ls != ls ||
+        prog_es != es) {
+        if (slots_for_cap != shape.slots) {
+            if (shape.slots > 0) assign_slots(m, quad, sched, shape.slots);
+            else sched.slot.clear(), sched.max_slots = 0, sched.spilled = 0;
+            slots_for_cap = shape.slots;
+        }
+        // references are encoded as LDS offsets of this launch shape and precision
+        prog = build_program(m, quad, sched, bands.B, shape.gcap, ls, es);
         prog_B = bands.B;
         prog_gcap = shape.gcap;
+        prog_ls = ls;
+        prog_es = es;
         sched_up = false;
     }
     if (!plan_ok) {
@@ -424,9 +431,20 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
         const WorkItem *wk = d_self_work.as<WorkItem>();
         if (m.N <= kPcgBlockMaxRows)
             launch_pcg_block(vp, wk + self_one, 1, 1, stream);
-        else
-            launch_pcg_multi(vp, wk + self_pcg, n_self_pcg, 1, std::max(1000, (int)std::sqrt((double)m.N) * 20),
-                             stream);
+        else {
+            // in chunks, stopping once the sticky converged flag is set (the
+            // launches after convergence would return at once but still cost
+            // their launch time)
+            const int limit = std::max(1000, (int)std::sqrt((double)m.N) * 20), chunk = 64;
+            for (int k0 = 0; k0 < limit; k0 += chunk) {
+                launch_pcg_multi(vp, wk + self_pcg, n_self_pcg, 1, std::min(chunk, limit - k0), stream, k0, k0 == 0);
+                double flag = 0.0;
+                NBTE_HIP(hipMemcpyAsync(&flag, d_pcg_scal.as<double>() + 4, sizeof(double), hipMemcpyDeviceToHost,
+                                        stream));
+                NBTE_HIP(hipStreamSynchronize(stream));
+                if (flag != 0.0) break;
+            }
+        }
     }
     // g = 0 is equilibrium at theta^0; the stored g is relative to theta[prev]
     NBTE_HIP(hipMemcpyAsync(d_theta[1].ptr, th0, m.N * 8, hipMemcpyDeviceToDevice, stream));
