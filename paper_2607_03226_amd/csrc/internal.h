@@ -116,6 +116,7 @@ struct Schedule {
     int max_slots = 0;               // slots actually used (max over directions)
     int64_t spilled = 0;             // consumed values that did not fit
     int max_ghosts = 0;              // most boundary inflow faces feeding one level
+    int max_ghost_pair = 0;          // most inflow faces feeding two consecutive levels
 };
 
 Schedule build_schedule(const Mesh &m, const Quadrature &q);
@@ -127,7 +128,9 @@ void assign_slots(const Mesh &m, const Quadrature &q, Schedule &sc, int cap);
 // everything it needs for a cell with independent, coalesced loads:
 //   cell, LDS slot of the cell's own value, up to maxin upwind references
 //   (ranges below), their coefficients |s.S|/V, and the outflow sum
-//   sum_{a>0} a.  Unused reference entries have coefficient 0.
+//   sum_{a>0} a.  Unused reference entries have coefficient 0 and point at
+//   the LDS zero block; maxin is the fan-in class (2, 3 or 5) of the widest
+//   cell.
 struct SweepProgram {
     int maxin = 0;
     std::vector<int32_t> cell, slot, ref;   // ref: maxin * D*N
@@ -145,13 +148,15 @@ struct SweepProgram {
 };
 // record reference encoding (shared with the sweep kernel): >= 0 an element
 // offset in the workgroup's LDS (a staged value: ring_off + slot ls; a ghost
-// of the level kept in LDS: gbuf0 + (level & 1) gstride + rank ls; see
-// sweep_lds_layout); [-kSpillBase, -1] ghost read from HBM, -1 - row; below:
+// kept in LDS: gbuf0 + ((pos_l + rank) mod gring) ls, pos_l = the kept ghosts
+// of the direction's earlier levels; see sweep_lds_layout); [-kSpillBase, -1] ghost read from HBM, -1 - row; below:
 // the stored value of the upwind cell at stream position k of the same
 // direction, -(kSpillBase + 1) - k.  The own slot ("mine") is the element
-// offset of the staged value, or -1.
+// offset of the staged value, or the LDS scratch block when no later cell
+// reads the value from LDS.
 constexpr int32_t kSpillBase = 1 << 24;
-SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap, int ls, int es);
+SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap, int gring, int ls,
+                           int es);
 
 // Boundary plan: per boundary face kind/wall data, s.S per direction and the
 // specular mirror table.

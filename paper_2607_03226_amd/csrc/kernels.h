@@ -51,6 +51,13 @@ struct PcgWork {
     double rtol2;         // stop when r.z <= rtol2 * r0.z0
     const int32_t NBTE_G *row_ptr, *col;
     const double NBTE_G *val, *dinv;
+    // the same matrix as ELL columns for the multi-workgroup form: slot s of
+    // row r at s n + r, ell_w = 8 slots (every slot is read: no per-slot
+    // branch splits the loads), values pre-scaled by the column's Jacobi
+    // factor (A D^-1); unused slots hold the row itself with value 0
+    int32_t ell_w;
+    const int32_t NBTE_G *ecol;
+    const double NBTE_G *eval;
     double NBTE_G *vec;          // 7 n: block form r, z, p, Ap; multi form r[2], w[2], s[2], p
     double NBTE_G *partial;      // 4 * nblk: per parity the r.u and w.u partial sums
     double NBTE_G *scal;         // [-, r0.u0, -, -, converged flag, iterations, alpha/gamma per parity (6..9)]
@@ -74,11 +81,14 @@ struct DeviceView {
     int32_t max_levels;     // deepest level count over the directions
     int32_t lpc;            // sweep lanes per cell
     int32_t bpb;            // sweep bands per workgroup
-    int32_t gcap;           // ghosts per level kept in LDS
-    int32_t lstride;        // LDS stride (doubles) of one staged value's bands
+    int32_t gcap;           // ghosts per level kept in LDS (the rest is read from HBM)
+    int32_t gring;          // LDS ghost ring capacity (power of two)
+    int32_t lstride;        // LDS stride (elements) of one staged value's bands: lpc x bands per lane
     const int32_t NBTE_G *lvl_ptr; // per direction L_i + 1 level offsets, concatenated
     const int32_t NBTE_G *lvl_off; // D+1: start of direction i's entries in lvl_ptr
     const int32_t NBTE_G *gptr;    // ghost offsets per level (layout of lvl_ptr)
+    // p_slot = p_cell + D N and p_ref = p_cell + 2 D N (rows of one array);
+    // likewise t_dc = t_sout + D N, t_q = t_sout + 2 D N, t_coef = t_sout + 3 D N
     const int32_t NBTE_G *p_cell, *p_slot, *p_ref;
     const int32_t NBTE_G *p_upc;   // maxin*D*N: upwind cell of each reference (the cell itself for inflow)
     // in the storage type T of g (FP64, or FP32 for the mixed path):
@@ -144,27 +154,33 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
 // (bpl = bands per block, up to 8); otherwise bpl is 1, 2 or 4.
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
                   int block, size_t lds_bytes, hipStream_t st);
-size_t sweep_lds_bytes(int max_levels, int gcap, int lstride, int slots, int elem_bytes);
+size_t sweep_lds_bytes(int max_levels, int gring, int lstride, int slots, int elem_bytes);
 
 // Dynamic LDS of a sweep workgroup, in elements of the storage type (es
-// bytes): [level tables: 2 (max_levels + 1) ints][ghost buffers of the two
-// level parities: 2 x gcap x ls][staged values: slots x ls].  Shared by the
-// host (which encodes upwind references as final LDS offsets) and the kernel.
+// bytes): [level tables: 2 (max_levels + 1) ints, padded to 16 bytes]
+// [zero block: ls][scratch block: ls][ghost ring: gring x ls][staged values:
+// slots x ls].  The ghosts (boundary inflow) kept in LDS of consecutive
+// levels follow each other around the ring (gring is a power of two), so the
+// ring needs room for the two largest consecutive levels, not twice the
+// largest.  ls is the stride of
+// one cell's bands (lanes per cell x bands per lane), so every lane's bands
+// start on a boundary of their own width and are read and written with one
+// LDS access of up to 16 bytes per chunk.  Unused upwind references point at
+// the zero block; values nobody reads again are written to the scratch
+// block.  Shared by the host (which encodes references as final LDS offsets)
+// and the kernel.
 struct SweepLdsLayout {
-    int ls, gbuf0, gstride, ring_off;
+    int ls, zero_off, trash_off, gbuf0, ring_off;
 };
-__host__ __device__ inline SweepLdsLayout sweep_lds_layout(int max_levels, int gcap, int ls, int es) {
+__host__ __device__ inline SweepLdsLayout sweep_lds_layout(int max_levels, int gring, int ls, int es) {
     SweepLdsLayout L;
     L.ls = ls;
-    L.gbuf0 = (2 * (max_levels + 1) * 4) / es;
-    L.gstride = gcap * ls;
-    L.ring_off = L.gbuf0 + 2 * L.gstride;
+    L.zero_off = ((2 * (max_levels + 1) * 4 + 15) / 16) * 16 / es;
+    L.trash_off = L.zero_off + ls;
+    L.gbuf0 = L.trash_off + ls;
+    L.ring_off = L.gbuf0 + gring * ls;
     return L;
 }
-// LDS stride (doubles) of a staged value's bands: they are contiguous, so
-// two-band blocks are read with 16-byte LDS loads (padding the stride to an
-// odd count, to spread random slots over the banks, measured slower)
-inline int sweep_lds_stride(int bpb) { return bpb; }
 
 // PCG of the synthetic correction for a list of solves.
 //   mode 0: solve L delta = rhs (every iteration);

@@ -164,6 +164,33 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
     }
 }
 
+// The imbalance term D of stream entries t0, t0 + stride, ...: every load of
+// an entry (its cell, upwind cells and coefficients) is issued before the
+// theta gathers they feed, the fan-in is a compile-time bound (rows past a
+// cell's fan-in have coefficient 0 and point at the cell itself).
+template <class T, int MI>
+__device__ __forceinline__ void stage_dc(const DeviceView &v, int64_t t0, int64_t stride) {
+    const int64_t n = (int64_t)v.D * v.N;
+    const double *th = theta_cur(v);
+    const T *cf = static_cast<const T *>(v.t_coef);
+    T *dc = static_cast<T *>(v.t_dc);
+    for (int64_t t = t0; t < n; t += stride) {
+        int up[MI];
+        T c[MI];
+        const int cell = v.p_cell[t];
+#pragma unroll
+        for (int j = 0; j < MI; ++j) {
+            up[j] = v.p_upc[j * n + t];
+            c[j] = cf[j * n + t];
+        }
+        const double thc = th[cell];
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < MI; ++j) acc += static_cast<double>(c[j]) * (th[up[j]] - thc);
+        dc[t] = static_cast<T>(acc);
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
     __shared__ double red[256];
@@ -183,17 +210,9 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
         // rounding of the face vectors), so D needs no outflow term and is
         // exactly zero for a uniform theta.  The differences are taken in
         // FP64, then weighted by the sweep's coefficients.
-        const int64_t n = (int64_t)v.D * v.N;
-        const int MI = v.maxin;
-        const double *th = theta_cur(v);
-        const T *cf = static_cast<const T *>(v.t_coef);
-        T *dc = static_cast<T *>(v.t_dc);
-        for (int64_t t = t0; t < n; t += stride) {
-            const double thc = th[v.p_cell[t]];
-            double acc = 0.0;
-            for (int j = 0; j < MI; ++j) acc += static_cast<double>(cf[j * n + t]) * (th[v.p_upc[j * n + t]] - thc);
-            dc[t] = static_cast<T>(acc);
-        }
+        if (v.maxin == 2) stage_dc<T, 2>(v, t0, stride);
+        else if (v.maxin == 3) stage_dc<T, 3>(v, t0, stride);
+        else stage_dc<T, 5>(v, t0, stride);
     }
 }
 
@@ -223,7 +242,7 @@ extern __shared__ double sweep_lds[];
 extern __shared__ int sweep_ldsi[];   // the same memory viewed as ints (level tables)
 extern __shared__ float sweep_ldsf[];  // ... and as floats (FP32 staged values)
 
-constexpr int kGhostPerThread = 2;    // ghost values a thread prefetches per level
+constexpr int kGhostPerThread = 1;    // ghost values a thread prefetches per level
 constexpr int kPrefetch = 4;          // passes whose records are in flight ahead of the computed one
 // record references: >= 0 LDS element offset (staged value or ghost kept in
 // LDS); [-kSpill, -1] ghost read from HBM (row -1 - ref); below: the stored
@@ -252,6 +271,33 @@ __device__ __forceinline__ void gstore(T NBTE_G *base, uint32_t k, T x) {
     *reinterpret_cast<T NBTE_G *>(reinterpret_cast<char NBTE_G *>(base) + k * (uint32_t)sizeof(T)) = x;
 }
 
+// Raw buffer resources (CDNA buffer descriptors) over the sweep's streams.  A
+// buffer load adds a per-lane 32-bit byte offset and a uniform (SGPR) byte
+// offset to the descriptor's base, so the reference rows j of a stream are
+// one descriptor with the row offset j D N in an SGPR: no per-lane 64-bit
+// address is ever formed, and no address temporary can reuse a register
+// whose load is still in flight.  Reads whose lane offset is at or past the
+// descriptor's size return 0.
+constexpr int kBufferWord3 = 0x00020000;   // gfx9 raw buffer, 32-bit elements
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void NBTE_G *p, uint64_t bytes) {
+    const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)n, kBufferWord3);
+}
+template <class T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff);
+template <>
+__device__ __forceinline__ int bload<int>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0);
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
+
 // One cell's sweep record (a position of a direction's level-ordered streams).
 template <class T, int MI>
 struct SweepRec {
@@ -262,26 +308,45 @@ struct SweepRec {
     bool ok;
 };
 
+// The streams of one direction as two buffer descriptors (base at the
+// direction's first position).  The rows of each kind are contiguous, D N
+// elements apart: ints = cell | slot | MI reference rows, reals = outflow
+// sum | imbalance term D | heat source | MI coefficient rows.
+struct SweepStreams {
+    __amdgpu_buffer_rsrc_t ints, reals;
+    uint32_t row4, rowT;   // byte distance of two rows (int32 / storage type)
+};
+
+template <class T>
+__device__ __forceinline__ SweepStreams sweep_streams(const DeviceView &v, int64_t base, int MI) {
+    const int64_t DN = (int64_t)v.D * v.N;
+    const uint64_t es = sizeof(T);
+    SweepStreams S;
+    S.ints = make_rsrc(v.p_cell + base, (uint64_t)((2 + MI) * DN - base) * 4);
+    S.reals = make_rsrc(static_cast<const T NBTE_G *>(v.t_sout) + base, (uint64_t)((3 + MI) * DN - base) * es);
+    S.row4 = (uint32_t)(DN * 4);
+    S.rowT = (uint32_t)(DN * (int64_t)es);
+    return S;
+}
+
 template <class T, int MI>
-__device__ __forceinline__ void load_rec(SweepRec<T, MI> &r, const DeviceView &v, int64_t base, int64_t DN, int k,
-                                         int kend) {
+__device__ __forceinline__ void load_rec(SweepRec<T, MI> &r, const SweepStreams &S, int k, int kend) {
     // the loads are issued on every path (a past-the-end record reads stream
     // position 0 of the direction), so the number of loads in flight is the
     // same on every path and a later wait on an older record can leave the
     // younger prefetches outstanding.  Stream positions fit 32 bits.
     r.ok = k < kend;
-    const uint32_t at = (uint32_t)(base + (r.ok ? k : 0));
-    const uint32_t dn = (uint32_t)DN;
-    const T NBTE_G *coef = static_cast<const T NBTE_G *>(v.t_coef);
-    r.c = gload(v.p_cell, at);
-    r.mine = gload(v.p_slot, at);
-    r.sout = gload(static_cast<const T NBTE_G *>(v.t_sout), at);
-    r.dc = gload(static_cast<const T NBTE_G *>(v.t_dc), at);
-    r.q = gload(static_cast<const T NBTE_G *>(v.t_q), at);
+    const uint32_t at = (uint32_t)(r.ok ? k : 0);
+    const uint32_t o4 = at * 4u, oT = at * (uint32_t)sizeof(T);
+    r.c = bload<int>(S.ints, o4, 0);
+    r.mine = bload<int>(S.ints, o4, S.row4);
+    r.sout = bload<T>(S.reals, oT, 0);
+    r.dc = bload<T>(S.reals, oT, S.rowT);
+    r.q = bload<T>(S.reals, oT, 2 * S.rowT);
 #pragma unroll
     for (int j = 0; j < MI; ++j) {
-        r.ref[j] = gload(v.p_ref + j * dn, at);
-        r.cf[j] = gload(coef + j * dn, at);
+        r.ref[j] = bload<int>(S.ints, o4, (2 + j) * S.row4);
+        r.cf[j] = bload<T>(S.reals, oT, (3 + j) * S.rowT);
     }
 }
 
@@ -296,17 +361,74 @@ struct BandConst {
 
 // LDS views of the staged values: element k of the sweep's type
 template <class T>
-__device__ __forceinline__ T lds_get(int k);
+__device__ __forceinline__ T *lds_elems();
 template <>
-__device__ __forceinline__ double lds_get<double>(int k) { return sweep_lds[k]; }
+__device__ __forceinline__ double *lds_elems<double>() { return sweep_lds; }
 template <>
-__device__ __forceinline__ float lds_get<float>(int k) { return sweep_ldsf[k]; }
+__device__ __forceinline__ float *lds_elems<float>() { return sweep_ldsf; }
 template <class T>
-__device__ __forceinline__ void lds_put(int k, T x);
-template <>
-__device__ __forceinline__ void lds_put<double>(int k, double x) { sweep_lds[k] = x; }
-template <>
-__device__ __forceinline__ void lds_put<float>(int k, float x) { sweep_ldsf[k] = x; }
+__device__ __forceinline__ T lds_get(int k) { return lds_elems<T>()[k]; }
+template <class T>
+__device__ __forceinline__ void lds_put(int k, T x) { lds_elems<T>()[k] = x; }
+
+// n consecutive elements as one access of up to 16 bytes per chunk (k is a
+// multiple of the chunk's element count: the LDS layout keeps every lane's
+// bands on a boundary of their own width)
+template <class T, int C>
+struct VecOf {
+    typedef T type __attribute__((ext_vector_type(C)));
+};
+template <class T, int BPL>
+constexpr int chunk_elems() { return BPL * (int)sizeof(T) >= 16 ? 16 / (int)sizeof(T) : BPL; }
+
+template <class T, int BPL>
+__device__ __forceinline__ void lds_read_bands(int k, T (&o)[BPL]) {
+    constexpr int C = chunk_elems<T, BPL>();
+#pragma unroll
+    for (int c0 = 0; c0 < BPL; c0 += C) {
+        if constexpr (C == 1) {
+            o[c0] = lds_get<T>(k + c0);
+        } else {
+            using V = typename VecOf<T, C>::type;
+            const V x = *reinterpret_cast<const V *>(lds_elems<T>() + k + c0);
+#pragma unroll
+            for (int e = 0; e < C; ++e) o[c0 + e] = x[e];
+        }
+    }
+}
+template <class T, int BPL>
+__device__ __forceinline__ void lds_write_bands(int k, const T (&x)[BPL]) {
+    constexpr int C = chunk_elems<T, BPL>();
+#pragma unroll
+    for (int c0 = 0; c0 < BPL; c0 += C) {
+        if constexpr (C == 1) {
+            lds_put<T>(k + c0, x[c0]);
+        } else {
+            using V = typename VecOf<T, C>::type;
+            V y;
+#pragma unroll
+            for (int e = 0; e < C; ++e) y[e] = x[c0 + e];
+            *reinterpret_cast<V *>(lds_elems<T>() + k + c0) = y;
+        }
+    }
+}
+// the same for global memory (element offset k of a uniform base)
+template <class T, int BPL>
+__device__ __forceinline__ void gstore_bands(T NBTE_G *base, uint32_t k, const T (&x)[BPL]) {
+    constexpr int C = chunk_elems<T, BPL>();
+#pragma unroll
+    for (int c0 = 0; c0 < BPL; c0 += C) {
+        if constexpr (C == 1) {
+            gstore(base, k + c0, x[c0]);
+        } else {
+            using V = typename VecOf<T, C>::type;
+            V y;
+#pragma unroll
+            for (int e = 0; e < C; ++e) y[e] = x[c0 + e];
+            *reinterpret_cast<V NBTE_G *>(reinterpret_cast<char NBTE_G *>(base) + (k + c0) * (uint32_t)sizeof(T)) = y;
+        }
+    }
+}
 
 // the update's quotient: IEEE division in FP64, reciprocal (1 ulp) in FP32
 __device__ __forceinline__ double quot(double a, double b) { return a / b; }
@@ -343,35 +465,40 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
         const T vel = bc.vel[jb];
         const T g = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
         gi[(int64_t)r.c * B + lam] = g;
-        if (r.mine >= 0) lds_put<T>(r.mine + lb, g);
+        lds_put<T>(r.mine + lb, g);   // own slot, or the scratch block
     }
 }
 
 // The common case: every upwind reference is an LDS slot or a ghost kept in
 // LDS (no spilled values, no ghost beyond the LDS capacity).  Branch-free:
-// one LDS offset per reference shared by the bands, unused references
-// (coefficient 0) masked by a select, past-the-end records computed but not
-// stored, so the items of a thread interleave.
+// a lane reads its BPL bands of each reference with one LDS access per 16
+// bytes (unused references read the zero block with coefficient 0), writes
+// its own slot (the scratch block when the value has no slot or the record
+// is past the end), and stores to HBM only for live records.
 template <class T, int MI, int BPL>
 __device__ __forceinline__ void sweep_cell_lds(const SweepRec<T, MI> &r, const BandConst<T, BPL> &bc, T NBTE_G *gi,
-                                               int B, int ls, int b0, int lane, int nb_here) {
-    const uint32_t gc = (uint32_t)r.c * (uint32_t)B + (uint32_t)b0;   // within one direction's slice
+                                               int B, int b0, int lofs, int nv, bool vst, int trash) {
+    T up[MI][BPL];
+#pragma unroll
+    for (int j = 0; j < MI; ++j) lds_read_bands<T, BPL>(r.ref[j] + lofs, up[j]);
+    T out[BPL];
 #pragma unroll
     for (int jb = 0; jb < BPL; ++jb) {
-        const int lb = lane * BPL + jb;
-        const bool on = r.ok && lb < nb_here;
-        const int lr = lb < ls ? lb : ls - 1;   // lanes past the block read in range
-        T gain = 0;
+        T gain = r.cf[0] * up[0][jb];
 #pragma unroll
-        for (int j = 0; j < MI; ++j) {
-            const T up = lds_get<T>(r.ref[j] + lr);
-            gain += r.cf[j] != T(0) ? r.cf[j] * up : T(0);
-        }
+        for (int j = 1; j < MI; ++j) gain += r.cf[j] * up[j][jb];
         const T vel = bc.vel[jb];
-        const T g = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
-        if (on) {
-            gstore(gi, gc + lb, g);
-            if (r.mine >= 0) lds_put<T>(r.mine + lb, g);
+        out[jb] = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
+    }
+    lds_write_bands<T, BPL>((r.ok ? r.mine : trash) + lofs, out);
+    if (r.ok) {
+        const uint32_t gc = (uint32_t)r.c * (uint32_t)B + (uint32_t)(b0 + lofs);   // within one direction's slice
+        if (vst) {
+            gstore_bands<T, BPL>(gi, gc, out);
+        } else {
+#pragma unroll
+            for (int jb = 0; jb < BPL; ++jb)
+                if (jb < nv) gstore(gi, gc + jb, out[jb]);
         }
     }
 }
@@ -396,6 +523,14 @@ __device__ __forceinline__ void level_barrier() {
     }
 }
 
+// A wave's window on a direction's level tables: lane t holds entries
+// base + t of the level and ghost offsets, read back as uniform values with
+// readlane (no LDS round trip on the pass cursor's path).  Refilled from LDS
+// once per 63 levels.
+struct LevelWindow {
+    int base, lp, gp;
+};
+
 // --------------------------------------------------------------------------
 // Pipeline: the cells of a direction are processed in passes (up to one
 // cell per slot, all of one level).  While pass q is computed from registers
@@ -413,10 +548,6 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     // ONE: one lane per cell (it sweeps all BPL bands of the block), so the
     // band of a register is the same on every lane and the band constants are
     // workgroup-uniform (scalar loads, scalar registers)
-    // dynamic LDS: [lvl_ptr | gptr of this direction: 2 (max_levels + 1) ints]
-    //              [ghost buffers: 2 x gcap x ls doubles]
-    //              [ring: slot x ls doubles]
-    // ls = LDS stride of one staged value's bands
     const WorkItem tk = wk[blockIdx.x];
     if (tk.solve < 0) return;   // padding of the XCD-ordered work list
     const DeviceView v = vs[tk.solve];   // a copy: fields stay in registers across the stores
@@ -431,18 +562,18 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     const int nslots = ONE ? (int)blockDim.x : (int)blockDim.x / lpc;
     const int64_t N = v.N;
     const int B = v.B;
-    const int64_t DN = (int64_t)v.D * N;
     T NBTE_G *gi = static_cast<T NBTE_G *>(v.g) + (int64_t)i * N * B;
     const int64_t base = (int64_t)i * N;
     const int nlev = v.lvl_off[i + 1] - v.lvl_off[i] - 1;
+    if (nlev <= 0) return;
     const int nb_here = min(B, b0 + bands_per_block) - b0;
     const int ML = v.max_levels + 1;
 #define lp(t) sweep_ldsi[(t)]
 #define gp(t) sweep_ldsi[ML + (t)]
-    const SweepLdsLayout lay = sweep_lds_layout(v.max_levels, gcap, v.lstride, (int)sizeof(T));
+    const SweepLdsLayout lay = sweep_lds_layout(v.max_levels, v.gring, v.lstride, (int)sizeof(T));
     const int ls = lay.ls;
-    const int gbuf0 = lay.gbuf0;       // first element after the level tables
-    const int gstride = lay.gstride;   // ghosts of a level kept in LDS (rank < gcap)
+    const int gbuf0 = lay.gbuf0;        // the ghost ring
+    const int gmask = v.gring - 1;      // ring positions wrap (power of two)
     {
         const int32_t *glp = v.lvl_ptr + v.lvl_off[i];
         const int32_t *ggp = v.gptr + v.lvl_off[i];
@@ -451,18 +582,43 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
             lp(t) = glp[t];
             gp(t) = ggp[t];
         }
+        for (int t = threadIdx.x; t < ls; t += blockDim.x) lds_put<T>(lay.zero_off + t, T(0));
     }
+    // this lane's bands: [lofs, lofs + BPL) of the block, nv of them real
+    const int lofs = lane * BPL;
+    const int nv = max(0, min(BPL, nb_here - lofs));
+    const bool vst = (B % BPL) == 0 && (b0 % BPL) == 0 && nv == BPL;   // whole-lane stores are aligned
     BandConst<T, BPL> bc;
 #pragma unroll
     for (int jb = 0; jb < BPL; ++jb) {
-        const int lam = min(b0 + lane * BPL + jb, B - 1);
+        const int lam = min(b0 + lofs + jb, B - 1);
         bc.cw[jb] = static_cast<T>(v.Cw[lam]);
         bc.itau[jb] = static_cast<T>(v.inv_tau[lam]);
         bc.vel[jb] = static_cast<T>(v.vel[lam]);
         bc.src[jb] = static_cast<T>(v.src[lam]);
     }
-    const T NBTE_G *gval = static_cast<const T NBTE_G *>(v.gval);
+    const SweepStreams S = sweep_streams<T>(v, base, MI);
+    const __amdgpu_buffer_rsrc_t rg = make_rsrc(v.gval, (uint64_t)max<int64_t>(v.NBF, 1) * v.D * B * sizeof(T));
+    // the ghost entries this thread moves: entry e = threadIdx.x + m blockDim.x
+    // of a level is band gl[m] of the level's ghost gq[m]
+    int gq[kGhostPerThread], gl[kGhostPerThread];
+#pragma unroll
+    for (int m = 0; m < kGhostPerThread; ++m) {
+        const int e = threadIdx.x + m * blockDim.x;
+        gq[m] = e / bands_per_block;
+        gl[m] = e - gq[m] * bands_per_block;
+    }
     __syncthreads();
+
+    const int lane64 = (int)(threadIdx.x & 63);
+    auto fill = [&](LevelWindow &w, int l) {
+        w.base = l;
+        const int t = min(l + lane64, nlev);
+        w.lp = lp(t);
+        w.gp = gp(t);
+    };
+    auto win_lp = [](const LevelWindow &w, int l) { return __builtin_amdgcn_readlane(w.lp, l - w.base); };
+    auto win_gp = [](const LevelWindow &w, int l) { return __builtin_amdgcn_readlane(w.gp, l - w.base); };
 
     // The sweep of a direction as a sequence of passes: pass = up to nslots
     // cells of one level, one cell per slot.  Records are requested
@@ -478,69 +634,92 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
         SweepRec<T, MI> r;
         Ghosts h;
     };
-    auto ghost_load = [&](Ghosts &h, int l, bool first) {
-        // branch-free like load_rec: entries past the level read element 0
-        const int ll = l < nlev ? l : nlev - 1;
-        const int g0 = gp(ll), ne = (first && l < nlev) ? min(gp(ll + 1) - g0, gcap) * bands_per_block : 0;
+    auto ghost_load = [&](Ghosts &h, int g0, int ne) {
+        // branch-free like load_rec: entries past the level read element 0.
+        // The loaded value is used as it is (no select on it here: an
+        // operation on a loaded register waits for the load, and the
+        // compiler may place it where that wait drains every prefetch);
+        // entries past a block's real bands only feed padding bands, which
+        // are never stored.
 #pragma unroll
         for (int m = 0; m < kGhostPerThread; ++m) {
             const int e = threadIdx.x + m * blockDim.x;
-            const int q = e / bands_per_block, lb = e - q * bands_per_block;
-            const bool ok = e < ne && lb < nb_here;
-            const T x = gload(gval, ok ? (uint32_t)((g0 + q) * B + b0 + lb) : 0u);
-            h.v[m] = ok ? x : T(0);
+            const bool ok = e < ne && gl[m] < nb_here;
+            const uint32_t off = ok ? (uint32_t)((g0 + gq[m]) * B + b0 + gl[m]) * (uint32_t)sizeof(T) : 0u;
+            h.v[m] = bload<T>(rg, off, 0);
         }
     };
-    auto ghost_store = [&](const Ghosts &h, int l) {
-        const int dst = gbuf0 + (l & 1) * gstride;
-        const int g0 = gp(l), ne = min(gp(l + 1) - g0, gcap) * bands_per_block;
+    // a level's kept ghosts occupy ring positions pos, pos + 1, ...
+    auto ghost_store = [&](const Ghosts &h, int pos, int g0, int ne) {
 #pragma unroll
         for (int m = 0; m < kGhostPerThread; ++m) {
             const int e = threadIdx.x + m * blockDim.x;
-            const int q = e / bands_per_block, lb = e - q * bands_per_block;
-            if (e < ne) lds_put<T>(dst + q * ls + lb, h.v[m]);
+            if (e < ne) lds_put<T>(gbuf0 + ((pos + gq[m]) & gmask) * ls + gl[m], h.v[m]);
         }
         // levels with more ghosts than the registers hold: direct copy
+        const T NBTE_G *gval = static_cast<const T NBTE_G *>(v.gval);
 #pragma nounroll
         for (int e = threadIdx.x + kGhostPerThread * blockDim.x; e < ne; e += blockDim.x) {
             const int q = e / bands_per_block, lb = e - q * bands_per_block;
-            lds_put<T>(dst + q * ls + lb, lb < nb_here ? gval[(int64_t)(g0 + q) * B + b0 + lb] : T(0));
+            lds_put<T>(gbuf0 + ((pos + q) & gmask) * ls + lb,
+                       lb < nb_here ? gval[(int64_t)(g0 + q) * B + b0 + lb] : T(0));
         }
     };
-    // pass cursors (uniform): level and first position of the pass
-    int lf = 0, kf = lp(0);   // next pass to request
-    int lc = 0, kc = lp(0);   // next pass to compute
+    // pass cursors (uniform): level, first position of the pass, end of the
+    // level, the level's ghosts (first offset and count)
+    LevelWindow wf, wc;
+    fill(wf, 0);
+    wc = wf;
+    int lf = 0, kf = win_lp(wf, 0), kendf = win_lp(wf, 1), g0f = win_gp(wf, 0), gnf = win_gp(wf, 1) - g0f;
+    bool firstf = true;
+    int lc = 0, kc = kf, kendc = kendf, g0c = g0f, gnc = gnf, gposc = 0;
     auto fetch = [&](Set &st) {
         const bool live = lf < nlev;
-        const int kend = live ? lp(lf + 1) : 0;
-        load_rec(st.r, v, base, DN, kf + slot, kend);
-        ghost_load(st.h, lf, live && kf == lp(lf));
+        load_rec(st.r, S, kf + slot, live ? kendf : 0);
+        ghost_load(st.h, g0f, (live && firstf) ? min(gnf, gcap) * bands_per_block : 0);
         if (live) {
             kf += nslots;
-            if (kf >= kend) {
+            firstf = false;
+            if (kf >= kendf) {
                 ++lf;
-                kf = lp(lf);
+                kf = kendf;
+                firstf = true;
+                if (lf < nlev) {
+                    if (lf + 1 - wf.base > 63) fill(wf, lf);
+                    kendf = win_lp(wf, lf + 1);
+                    g0f += gnf;
+                    gnf = win_gp(wf, lf + 1) - g0f;
+                }
             }
         }
     };
     // compute the pass in `cur`, request a new pass into `nxt` (the set
-    // computed last, now free); returns false when the sweep is done
-    auto step = [&](Set &cur, Set &nxt, const Set &after) -> bool {
+    // computed last, now free).  Passes after the last one compute
+    // past-the-end records (no stores to HBM, LDS writes to the scratch
+    // block), so the ring below runs whole turns and has one exit test: an
+    // exit after each step would join the loop's back edge, and the wait
+    // analysis would then assume the youngest records of every step might
+    // be the ones computed next, draining the prefetches once per turn.
+    auto step = [&](Set &cur, Set &nxt, const Set &after) {
         fetch(nxt);
         if constexpr (MODE == kModeLds)
-            sweep_cell_lds<T, MI, BPL>(cur.r, bc, gi, B, ls, b0, lane, nb_here);
+            sweep_cell_lds<T, MI, BPL>(cur.r, bc, gi, B, b0, lofs, nv, vst, lay.trash_off);
         else if (cur.r.ok)
             sweep_cell<T, MI, BPL>(cur.r, v, bc, gi, base, b0, lane, nb_here);
         kc += nslots;
-        if (kc >= lp(lc + 1)) {   // level done
+        if (lc < nlev && kc >= kendc) {   // level done
             ++lc;
             if (lc < nlev) {
-                kc = lp(lc);
-                ghost_store(after.h, lc);   // the next pass opens level lc
+                kc = kendc;
+                if (lc + 1 - wc.base > 63) fill(wc, lc);
+                kendc = win_lp(wc, lc + 1);
+                gposc += min(gnc, gcap);   // past the previous level's kept ghosts
+                g0c += gnc;
+                gnc = win_gp(wc, lc + 1) - g0c;
+                ghost_store(after.h, gposc, g0c, min(gnc, gcap) * bands_per_block);   // the next pass opens level lc
             }
             level_barrier<MODE == kModeSpill>();
         }
-        return lc < nlev;
     };
     Set s0, s1, s2, s3, s4;
     static_assert(kPrefetch == 4, "the step ring below is written for four passes in flight");
@@ -548,16 +727,16 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     fetch(s1);
     fetch(s2);
     fetch(s3);
-    ghost_store(s0.h, 0);
+    ghost_store(s0.h, gposc, g0c, min(gnc, gcap) * bands_per_block);
     __syncthreads();
 #pragma nounroll
-    while (true) {
-        if (!step(s0, s4, s1)) break;
-        if (!step(s1, s0, s2)) break;
-        if (!step(s2, s1, s3)) break;
-        if (!step(s3, s2, s4)) break;
-        if (!step(s4, s3, s0)) break;
-    }
+    do {
+        step(s0, s4, s1);
+        step(s1, s0, s2);
+        step(s2, s1, s3);
+        step(s3, s2, s4);
+        step(s4, s3, s0);
+    } while (lc < nlev);
 }
 #undef lp
 #undef gp
@@ -605,8 +784,7 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
 
 // --------------------------------------------------------------------------
 // band x direction reductions (Methods, Eqs. (5), (7); T = energy temperature)
-// mom_lpc lanes per cell (bands x direction groups), FP64 accumulation,
-// shuffle reduction over the lanes in a fixed order.
+// mom_lpc lanes per cell, FP64 accumulation, shuffle reduction over the lanes.
 // Synthetic schemes also get the V-weighted right-hand side of the correction:
 //   V (Qdot - D_h' q) = V beta (theta_seq - theta) + sum_{reflective f} J_f
 // (collision-divergence identity; reflective walls carry zero net flux at the
@@ -617,23 +795,19 @@ __global__ void __launch_bounds__(256) k_moments(const DeviceView *__restrict__ 
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (v.state->done) return;
-    // lanes of a cell: lb band lanes x (lpc / lb) direction groups
     const int lpc = v.mom_lpc;
-    const int64_t N = v.N;
-    const int B = v.B, D = v.D;
-    int lb = 1;
-    while (lb < B && lb < 64) lb <<= 1;
     const int64_t c = ((int64_t)it.b * blockDim.x + threadIdx.x) / lpc;
     const int lane = threadIdx.x % lpc;
-    const int bl = lane % lb, dg = lane / lb, ng = lpc / lb;
+    const int64_t N = v.N;
+    const int B = v.B, D = v.D;
     const T *g = static_cast<const T *>(v.g);
     double a_tau = 0, a_w = 0, qx = 0, qy = 0, qz = 0;
     if (c < N) {
-        for (int lam = bl; lam < B; lam += lb) {
+        for (int lam = lane; lam < B; lam += lpc) {
             double sw = 0, s_x = 0, s_y = 0, s_z = 0;
-            // independent loads, eight directions of the group in flight
+            // independent loads, eight directions in flight (summation order unchanged)
 #pragma unroll 8
-            for (int i = dg; i < D; i += ng) {
+            for (int i = 0; i < D; ++i) {
                 const double ww = v.w[i] * ld(g, ((int64_t)i * N + c) * B + lam);
                 sw += ww;
                 s_x += ww * v.dirs[3 * i];
@@ -865,14 +1039,73 @@ __global__ void __launch_bounds__(1024) k_pcg_block(const DeviceView *__restrict
 // all see identical scalars and the result is bitwise reproducible.  The
 // iteration stops (for every later launch too, through a sticky flag) once
 // gamma_k <= rtol2 gamma_0.
-__device__ double sum_partials(const double *p, int n, double *lds) {
-    double x = (threadIdx.x < (unsigned)n) ? p[threadIdx.x] : 0.0;
-    return block_sum(x, lds);
+// Two sums over a workgroup in one LDS exchange (fixed order: lanes, then
+// waves; every thread adds the wave sums itself).  The barrier orders LDS
+// only, so global loads issued before it stay in flight.  lds holds 2 x 16.
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *lds) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+        lds[2 * wv] = a;
+        lds[2 * wv + 1] = b;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    double sa = 0.0, sb = 0.0;
+    for (int k = 0; k < nw; ++k) {
+        sa += lds[2 * k];
+        sb += lds[2 * k + 1];
+    }
+    a = sa;
+    b = sb;
+}
+
+// three sums (the flag and the two partial sums of a CG launch) the same way
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *lds) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+        lds[3 * wv] = a;
+        lds[3 * wv + 1] = b;
+        lds[3 * wv + 2] = c;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    double sa = 0.0, sb = 0.0, sc = 0.0;
+    for (int k = 0; k < nw; ++k) {
+        sa += lds[3 * k];
+        sb += lds[3 * k + 1];
+        sc += lds[3 * k + 2];
+    }
+    a = sa;
+    b = sb;
+    c = sc;
+}
+
+constexpr int kEllMax = 8;   // ELL slots per row of the multi-workgroup CG (faces + 1 <= 8)
+
+// r = A D^-1 x at one row, ELL form (values already scaled by D^-1)
+__device__ __forceinline__ double ell_row(const PcgWork &w, int64_t n, int64_t r, const double *x) {
+    int c[kEllMax];
+    double e[kEllMax];
+#pragma unroll
+    for (int s = 0; s < kEllMax; ++s)
+        c[s] = w.ecol[s * n + r], e[s] = w.eval[s * n + r];
+    double au = 0.0;
+#pragma unroll
+    for (int s = 0; s < kEllMax; ++s)
+        au += e[s] * x[c[s]];
+    return au;
 }
 
 __global__ void __launch_bounds__(256) k_cg1_init(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
                                                   int mode) {
-    __shared__ double lds[16];
+    __shared__ double lds[32];
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (pcg_skip(v, mode)) return;
@@ -885,11 +1118,7 @@ __global__ void __launch_bounds__(256) k_cg1_init(const DeviceView *__restrict__
     for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < n; r += (int64_t)w.nblk * blockDim.x) {
         const double bi = b[r];
         const double u = w.dinv[r] * bi;
-        double au = 0.0;
-        for (int32_t k = w.row_ptr[r]; k < w.row_ptr[r + 1]; ++k) {
-            const int32_t j = w.col[k];
-            au += w.val[k] * (w.dinv[j] * b[j]);
-        }
+        const double au = ell_row(w, n, r, b);
         x[r] = 0.0;
         r0[r] = bi;
         w0[r] = au;
@@ -898,8 +1127,7 @@ __global__ void __launch_bounds__(256) k_cg1_init(const DeviceView *__restrict__
         ga += bi * u;
         de += au * u;
     }
-    ga = block_sum(ga, lds);
-    de = block_sum(de, lds);
+    block_sum2(ga, de, lds);
     if (threadIdx.x == 0) {
         w.partial[it.b] = ga;
         w.partial[w.nblk + it.b] = de;
@@ -910,30 +1138,53 @@ __global__ void __launch_bounds__(256) k_cg1_init(const DeviceView *__restrict__
     }
 }
 
+// One iteration of the single-reduction (Chronopoulos-Gear) Jacobi-PCG per
+// launch: the launch boundary is the only grid-wide synchronisation.  Every
+// load a row needs (its vectors, its ELL row and the gathered neighbour
+// values) is issued before the reduction of the previous launch's partial
+// sums, so the launch costs about two memory round trips.
 __global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
                                                   int mode, int k, double rtol2_o, int max_o) {
-    __shared__ double lds[16];
+    __shared__ double lds[80];
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (pcg_skip(v, mode)) return;
     const PcgWork &w = v.pcg;
     const int max_iter = max_o >= 0 ? max_o : w.max_iter;
     if (k >= max_iter) return;
-    // the flag is read once per workgroup and broadcast through LDS, so every
-    // thread takes the same (uniform) exit
-    __syncthreads();
-    if (threadIdx.x == 0) lds[15] = w.scal[4];
-    __syncthreads();
-    if (lds[15] != 0.0) return;
-    __syncthreads();
     const double rtol2 = rtol2_o >= 0 ? rtol2_o : w.rtol2;
     const int64_t n = w.n;
     const int cur = k & 1, nxt = cur ^ 1;
     const double *pin = w.partial + cur * 2 * w.nblk;
     double *pout = w.partial + nxt * 2 * w.nblk;
-    const double gamma = sum_partials(pin, w.nblk, lds);
-    const double delta = sum_partials(pin + w.nblk, w.nblk, lds);
-    const double gamma0 = k == 0 ? gamma : w.scal[1];
+    const double *rk = w.vec + cur * n, *wk_ = w.vec + (2 + cur) * n, *sk1 = w.vec + (4 + nxt) * n;
+    double *rn = w.vec + nxt * n, *wn = w.vec + (2 + nxt) * n, *sk = w.vec + (4 + cur) * n, *pp = w.vec + 6 * n;
+    double *x = pcg_x(v, mode);
+    const int64_t stride = (int64_t)w.nblk * blockDim.x;
+    const int64_t r0 = (int64_t)it.b * blockDim.x + threadIdx.x;
+
+    // loads: the stop flag, partial sums, scalars, and the first row with its
+    // neighbours.  The flag may be set by workgroup 0 of this very launch
+    // (when it converges), so waves can read different values: the decision
+    // is taken from the workgroup's sum of the flags, after the exchange.
+    double flag = w.scal[4] != 0.0 ? 1.0 : 0.0;
+    double gamma = threadIdx.x < (unsigned)w.nblk ? pin[threadIdx.x] : 0.0;
+    double delta = threadIdx.x < (unsigned)w.nblk ? pin[w.nblk + threadIdx.x] : 0.0;
+    const double gamma0_s = w.scal[1], alpha_old = w.scal[6 + 2 * nxt], gamma_old = w.scal[7 + 2 * nxt];
+    const bool have = r0 < n;
+    const int64_t ra = have ? r0 : 0;
+    double d_rk = rk[ra], d_wk = wk_[ra], d_sk1 = sk1[ra], d_pp = pp[ra], d_di = w.dinv[ra], d_x = x[ra];
+    int c[kEllMax];
+    double e[kEllMax], gr[kEllMax], gw[kEllMax], gs[kEllMax];
+#pragma unroll
+    for (int s = 0; s < kEllMax; ++s)
+        c[s] = w.ecol[s * n + ra], e[s] = w.eval[s * n + ra];
+#pragma unroll
+    for (int s = 0; s < kEllMax; ++s)
+        gr[s] = rk[c[s]], gw[s] = wk_[c[s]], gs[s] = sk1[c[s]];
+    block_sum3(flag, gamma, delta, lds);
+    if (flag != 0.0) return;
+    const double gamma0 = k == 0 ? gamma : gamma0_s;
     if (!(gamma > rtol2 * gamma0)) {   // converged (or zero right-hand side)
         if (it.b == 0 && threadIdx.x == 0) w.scal[4] = 1.0;
         return;
@@ -943,36 +1194,38 @@ __global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__
         beta = 0.0;
         alpha = gamma / delta;
     } else {
-        const double alpha_old = w.scal[6 + 2 * nxt], gamma_old = w.scal[7 + 2 * nxt];
         beta = gamma / gamma_old;
         alpha = gamma / (delta - beta * gamma / alpha_old);
     }
-    const double *rk = w.vec + cur * n, *wk_ = w.vec + (2 + cur) * n, *sk1 = w.vec + (4 + nxt) * n;
-    double *rn = w.vec + nxt * n, *wn = w.vec + (2 + nxt) * n, *sk = w.vec + (4 + cur) * n, *pp = w.vec + 6 * n;
-    double *x = pcg_x(v, mode);
     double ga = 0.0, de = 0.0;
-    for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < n; r += (int64_t)w.nblk * blockDim.x) {
-        const double ui = w.dinv[r] * rk[r];
-        const double pi = ui + beta * pp[r];
-        const double si = wk_[r] + beta * sk1[r];
+    for (int64_t r = r0; r < n; r += stride) {
+        if (r != r0) {   // further rows (meshes above nblk x blockDim cells)
+            d_rk = rk[r], d_wk = wk_[r], d_sk1 = sk1[r], d_pp = pp[r], d_di = w.dinv[r], d_x = x[r];
+#pragma unroll
+            for (int s = 0; s < kEllMax; ++s)
+                c[s] = w.ecol[s * n + r], e[s] = w.eval[s * n + r];
+#pragma unroll
+            for (int s = 0; s < kEllMax; ++s)
+                gr[s] = rk[c[s]], gw[s] = wk_[c[s]], gs[s] = sk1[c[s]];
+        }
+        const double ui = d_di * d_rk;
+        const double pi = ui + beta * d_pp;
+        const double si = d_wk + beta * d_sk1;
         pp[r] = pi;
         sk[r] = si;
-        x[r] += alpha * pi;
-        const double ri = rk[r] - alpha * si;
+        x[r] = d_x + alpha * pi;
+        const double ri = d_rk - alpha * si;
         rn[r] = ri;
-        const double un = w.dinv[r] * ri;
+        const double un = d_di * ri;
         double au = 0.0;
-        for (int32_t q = w.row_ptr[r]; q < w.row_ptr[r + 1]; ++q) {
-            const int32_t j = w.col[q];
-            const double sj = wk_[j] + beta * sk1[j];
-            au += w.val[q] * (w.dinv[j] * (rk[j] - alpha * sj));
-        }
+#pragma unroll
+        for (int s = 0; s < kEllMax; ++s)
+            au += e[s] * (gr[s] - alpha * (gw[s] + beta * gs[s]));
         wn[r] = au;
         ga += ri * un;
         de += au * un;
     }
-    ga = block_sum(ga, lds);
-    de = block_sum(de, lds);
+    block_sum2(ga, de, lds + 48);
     if (threadIdx.x == 0) {
         pout[it.b] = ga;
         pout[w.nblk + it.b] = de;
@@ -1058,10 +1311,9 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
     hipLaunchKernelGGL(k_finish, dim3((n + 63) / 64), dim3(64), 0, st, vs, wk, n);
 }
 
-size_t sweep_lds_bytes(int max_levels, int gcap, int ls, int slots, int es) {
-    return (size_t)(max_levels + 1) * 2 * sizeof(int)    // two int level tables
-           + (size_t)2 * gcap * ls * es                  // ghost buffers
-           + (size_t)std::max(slots, 1) * ls * es;       // staged values
+size_t sweep_lds_bytes(int max_levels, int gring, int ls, int slots, int es) {
+    const SweepLdsLayout L = sweep_lds_layout(max_levels, gring, ls, es);
+    return ((size_t)L.ring_off + (size_t)std::max(slots, 1) * ls) * es;
 }
 
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,

@@ -124,25 +124,34 @@ struct nbte_problem {
 
     // device buffers
     nbte::DevBuf d_nbr, d_V;
-    nbte::DevBuf d_lvl_ptr, d_lvl_off, d_gptr, d_pcell, d_pslot, d_pref, d_pupc, d_inrow;
-    nbte::DevBuf d_tcoef, d_tsout;   // coefficients and outflow sums in the storage type
-    nbte::DevBuf d_tq, d_tdc;        // heat source and imbalance term in sweep order (storage type)
-    int coef_prec = -1;              // precision d_tcoef / d_tsout were uploaded in
+    nbte::DevBuf d_lvl_ptr, d_lvl_off, d_gptr, d_pupc, d_inrow;
+    // the sweep's streams, D*N entries per row, rows contiguous so the sweep
+    // reads them through one buffer descriptor each:
+    //   d_pint (int32):           cell | slot | maxin reference rows
+    //   d_tstream (storage type): outflow sum | imbalance term D | heat source | maxin coefficient rows
+    nbte::DevBuf d_pint, d_tstream;
+    int coef_prec = -1;              // precision the outflow sums and coefficients were uploaded in
+    int64_t stream_DN() const;
+    const int32_t *p_cell() const { return d_pint.as<int32_t>(); }
+    void *t_row(int r) const;        // row r of d_tstream
     nbte::DevBuf d_Cw, d_src, d_vel, d_itau, d_dirs, d_w, d_qbias;
     nbte::DevBuf d_bf_owner, d_bf_kind, d_mirror, d_bf_thw, d_bf_p, d_sdotS, d_win;
     nbte::DevBuf d_Lrow, d_Lcol, d_Lval, d_Ldinv;
+    nbte::DevBuf d_Ecol, d_Eval;     // ELL copy (A D^-1) for the multi-workgroup CG
     nbte::DevBuf d_g, d_gval, d_Jw, d_Q;
     nbte::DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta;
     nbte::DevBuf d_pcg_vec, d_pcg_part, d_pcg_scal;
     nbte::DevBuf d_view, d_state, d_self_work;
     int pcg_nblk = 1;
+    int ell_w = 0;                   // ELL width of the correction's matrix
 
     // launch shape of the sweep
     struct Shape {
-        int bpb = 1, bpl = 1, block = 256, slots = 0, gcap = 0;
+        int bpb = 1, bpl = 1, block = 256, slots = 0, gcap = 0, gring = 1;
+        int lpc = 1, ls = 1;   // sweep lanes per cell; LDS stride of a cell's bands (lpc x bpl)
     } shape;
     int slots_for_cap = -2;   // slot budget the current slot table was built for
-    int prog_B = -1, prog_gcap = -1, prog_ls = -1, prog_es = -1;
+    int prog_B = -1, prog_gcap = -1, prog_gring = -1, prog_ls = -1, prog_es = -1;
     nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0};
 
     // iteration state

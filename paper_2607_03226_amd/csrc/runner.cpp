@@ -104,7 +104,7 @@ void Runner::build() {
         L.off = (int)work.size();
         each(f, [&](int s, nbte_problem &p) {
             const int64_t nb0 = std::min<int64_t>(cdiv(p.mesh->NBF, 4), 2048);   // a wave per face
-            const int64_t nb1 = std::min<int64_t>(cdiv((int64_t)p.quad.D * p.mesh->N, 256), 2048);
+            const int64_t nb1 = std::min<int64_t>(cdiv((int64_t)p.quad.D * p.mesh->N, 256), 16384);
             for (int64_t b = 0; b < nb0; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb0});
             for (int64_t b = 0; b < nb1; ++b) work.push_back({s, 1, (int32_t)b, (int32_t)nb1});
         });
@@ -135,7 +135,7 @@ void Runner::build() {
                 const int nbb = (int)cdiv(p.bands.B, p.shape.bpb);
                 const int lpc = p.hv.lpc;
                 const int nslots = std::max(1, p.shape.block / lpc);
-                lds = std::max(lds, sweep_lds_bytes(p.sched.max_levels, p.shape.gcap, p.hv.lstride,
+                lds = std::max(lds, sweep_lds_bytes(p.sched.max_levels, p.shape.gring, p.hv.lstride,
                                                     std::max(p.sched.max_slots, 1), p.fp32() ? 4 : 8));
                 for (int i = 0; i < p.quad.D; ++i) {
                     // passes over the cells of direction i: one per level and slot row

@@ -46,6 +46,7 @@ Schedule build_schedule(const Mesh &m, const Quadrature &q) {
         int32_t *perm = &sc.perm[(size_t)i * N];
         int64_t done = 0;
         int levels = 0;
+        int prev_ghosts = 0;
         sc.lvl_ptr.push_back(0);
         while (!frontier.empty()) {
             std::sort(frontier.begin(), frontier.end());
@@ -54,6 +55,8 @@ Schedule build_schedule(const Mesh &m, const Quadrature &q) {
                 for (int f = 0; f < F; ++f)
                     if (m.nbr[(int64_t)u * F + f] < 0 && sdot(u, f) < 0.0) ++ghosts;
             sc.max_ghosts = std::max(sc.max_ghosts, ghosts);
+            sc.max_ghost_pair = std::max(sc.max_ghost_pair, prev_ghosts + ghosts);
+            prev_ghosts = ghosts;
             std::copy(frontier.begin(), frontier.end(), perm + done);
             done += (int64_t)frontier.size();
             sc.lvl_ptr.push_back((int32_t)done);
@@ -133,8 +136,9 @@ void assign_slots(const Mesh &m, const Quadrature &q, Schedule &sc, int cap) {
     }
 }
 
-SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap, int ls, int es) {
-    const SweepLdsLayout lay = sweep_lds_layout(sc.max_levels, gcap, ls, es);
+SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &sc, int B, int gcap, int gring, int ls,
+                           int es) {
+    const SweepLdsLayout lay = sweep_lds_layout(sc.max_levels, gring, ls, es);
     const int64_t N = m.N;
     const int F = m.F;
     const int D = q.D;
@@ -152,12 +156,14 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
             pg.maxin = std::max(pg.maxin, nin);
         }
     }
-    pg.maxin = std::max(pg.maxin, 1);
     if (pg.maxin > 5) throw Error(NBTE_ERR_MESH, "a cell has more than 5 upwind faces in some direction");
+    // the streams hold as many reference rows as the kernel variant reads
+    // (fan-in classes 2, 3 and 5); rows past a cell's fan-in are unused
+    pg.maxin = pg.maxin <= 2 ? 2 : (pg.maxin == 3 ? 3 : 5);
     pg.cell.resize(DN);
     pg.slot.resize(DN);
     pg.sout.resize(DN);
-    pg.ref.assign((size_t)pg.maxin * DN, 0);
+    pg.ref.assign((size_t)pg.maxin * DN, lay.zero_off);   // unused: the zero block
     pg.upc.assign((size_t)pg.maxin * DN, 0);
     pg.coef.assign((size_t)pg.maxin * DN, 0.0);
     pg.gptr.resize(sc.lvl_ptr.size());
@@ -171,6 +177,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
         const int32_t *lp = &sc.lvl_ptr[sc.lvl_off[i]];
         int32_t *gp = &pg.gptr[sc.lvl_off[i]];
         const int L = sc.lvl_off[i + 1] - sc.lvl_off[i] - 1;
+        int gpos = 0;   // ring position of the level's first kept ghost
         for (int l = 0; l < L; ++l) {
             gp[l] = (int32_t)pg.ghost_src.size();
             int rank = 0;
@@ -179,7 +186,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                 const int32_t c = sc.perm[at];
                 pg.cell[at] = c;
                 for (int j = 0; j < pg.maxin; ++j) pg.upc[(size_t)j * DN + at] = c;
-                pg.slot[at] = (slot_i && slot_i[c] >= 0) ? lay.ring_off + slot_i[c] * ls : -1;
+                pg.slot[at] = (slot_i && slot_i[c] >= 0) ? lay.ring_off + slot_i[c] * ls : lay.trash_off;
                 const double iv = 1.0 / m.V[c];
                 double sout = 0.0;
                 int j = 0;
@@ -196,7 +203,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                             const int64_t row = (int64_t)pg.ghost_src.size();
                             pg.ghost_src.push_back((bf * D + i) * (int64_t)B);
                             pg.in_row[bf * D + i] = (int32_t)row;
-                            r = rank < gcap ? lay.gbuf0 + (l & 1) * lay.gstride + rank * ls : -1 - (int32_t)row;
+                            r = rank < gcap ? lay.gbuf0 + ((gpos + rank) & (gring - 1)) * ls : -1 - (int32_t)row;
                             ++rank;
                         } else if (slot_i && slot_i[n] >= 0) {
                             r = lay.ring_off + slot_i[n] * ls;         // staged in LDS
@@ -212,6 +219,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                 pg.sout[at] = sout;
             }
             pg.max_ghosts = std::max(pg.max_ghosts, rank);
+            gpos += std::min(rank, gcap);
         }
         gp[L] = (int32_t)pg.ghost_src.size();
     }

@@ -67,6 +67,29 @@ nbte_problem::~nbte_problem() {
     if (own_stream) (void)hipStreamDestroy(own_stream);
 }
 
+// LDS bytes one workgroup may use on the current device (64 KiB if unknown)
+static int lds_limit() {
+    static int cached = 0;
+    if (cached > 0) return cached;
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+        (void)hipGetLastError();
+        return 65536;
+    }
+    cached = v;
+    return v;
+}
+
+int64_t nbte_problem::stream_DN() const { return (int64_t)quad.D * mesh->N; }
+
+void *nbte_problem::t_row(int r) const {
+    return static_cast<char *>(d_tstream.ptr) + (size_t)r * stream_DN() * (fp32() ? 4 : 8);
+}
+
+// lanes per cell of the reductions: a power of two >= B, at most 64 (one
+// band per lane; measured: splitting the directions of a cell over more
+// lanes breaks the coalesced band rows and is slower)
 int nbte_problem::mom_lpc() const {
     int lpc = 1;
     while (lpc < bands.B && lpc < 64) lpc <<= 1;
@@ -103,18 +126,37 @@ nbte_problem::Shape nbte_problem::resolve_shape() const {
     sh.bpb = bpb;
     sh.bpl = bpl;
     sh.block = block;
-    // the level tables and the two ghost buffers of a direction share the
-    // workgroup's LDS with the staged values; at most a quarter of the budget
-    // goes to ghosts, larger boundary levels read the rest from HBM
-    const int table = ((sched_ok ? sched.max_levels : 0) + 1) * 8;
-    const int ls = sweep_lds_stride(bpb);
+    sh.lpc = lpc;
+    sh.ls = lpc * bpl;   // a cell's bands in LDS, padded to whole lanes
+    // the level tables and the ghost ring of a direction share the
+    // workgroup's LDS with the staged values.  The ring keeps every ghost in
+    // LDS when room for the two largest consecutive levels fits in half the
+    // budget; otherwise it takes a quarter of the budget and each level keeps
+    // half of it, larger boundary levels read the rest from HBM.  The default
+    // budget is half of a CU's LDS (two workgroups per CU; only what the
+    // schedule needs is allocated).
+    const int ls = sh.ls;
     const int es = fp32() ? 4 : 8;   // staged values are held in the storage type
-    const int total = tuning.lds_bytes == 0 ? 65536 : std::min(std::abs(tuning.lds_bytes), 65536);
-    sh.gcap = std::min(sched_ok ? sched.max_ghosts : 0, std::max(1, total / 4 / (2 * ls * es)));
-    const int ghosts = 2 * sh.gcap * ls * es;
-    if (table + ghosts > 65536 - es * ls)
+    const int levels = sched_ok ? sched.max_levels : 0;
+    const int limit = lds_limit();
+    const int dflt = std::min(limit, 81920);
+    const int total = tuning.lds_bytes == 0 ? dflt : std::min(std::abs(tuning.lds_bytes), limit);
+    const int pair = sched_ok ? sched.max_ghost_pair : 0;
+    int ring = 1;
+    while (ring < pair) ring <<= 1;
+    if ((int64_t)ring * ls * es <= total / 2) {
+        sh.gring = ring;
+        sh.gcap = sched_ok ? sched.max_ghosts : 0;
+    } else {
+        ring = 2;
+        while ((int64_t)ring * 2 * ls * es <= total / 4) ring <<= 1;
+        sh.gring = ring;
+        sh.gcap = ring / 2;
+    }
+    const SweepLdsLayout lay = sweep_lds_layout(levels, sh.gring, ls, es);
+    if ((int64_t)(lay.ring_off + ls) * es > limit)
         throw Error(NBTE_ERR_INVALID_ARG, "sweep level tables do not fit in LDS; use fewer bands per block");
-    const int budget = (tuning.lds_bytes == 0 ? 65536 : std::min(tuning.lds_bytes, 65536)) - table - ghosts;
+    const int budget = (tuning.lds_bytes == 0 ? dflt : std::min(tuning.lds_bytes, limit)) - lay.ring_off * es;
     sh.slots = tuning.lds_bytes < 0 ? 0 : std::max(budget, 0) / (ls * es);
     return sh;
 }
@@ -132,18 +174,19 @@ void nbte_problem::build_host() {
         slots_for_cap = -2;
     }
     shape = resolve_shape();
-    const int ls = sweep_lds_stride(shape.bpb), es = fp32() ? 4 : 8;
-    if (slots_for_cap != shape.slots || prog_B != bands.B || prog_gcap != shape.gcap || prog_ls != ls ||
-        prog_es != es) {
+    const int ls = shape.ls, es = fp32() ? 4 : 8;
+    if (slots_for_cap != shape.slots || prog_B != bands.B || prog_gcap != shape.gcap || prog_gring != shape.gring ||
+        prog_ls != ls || prog_es != es) {
         if (slots_for_cap != shape.slots) {
             if (shape.slots > 0) assign_slots(m, quad, sched, shape.slots);
             else sched.slot.clear(), sched.max_slots = 0, sched.spilled = 0;
             slots_for_cap = shape.slots;
         }
         // references are encoded as LDS offsets of this launch shape and precision
-        prog = build_program(m, quad, sched, bands.B, shape.gcap, ls, es);
+        prog = build_program(m, quad, sched, bands.B, shape.gcap, shape.gring, ls, es);
         prog_B = bands.B;
         prog_gcap = shape.gcap;
+        prog_gring = shape.gring;
         prog_ls = ls;
         prog_es = es;
         sched_up = false;
@@ -181,9 +224,12 @@ void nbte_problem::upload_device() {
     if (!sched_up) {
         upload(d_lvl_ptr, sched.lvl_ptr, stream);
         upload(d_lvl_off, sched.lvl_off, stream);
-        upload(d_pcell, prog.cell, stream);
-        upload(d_pslot, prog.slot, stream);
-        upload(d_pref, prog.ref, stream);
+        const int64_t DN = stream_DN();
+        d_pint.alloc((size_t)(2 + prog.maxin) * DN * 4);
+        NBTE_HIP(hipMemcpyAsync(d_pint.as<int32_t>(), prog.cell.data(), DN * 4, hipMemcpyHostToDevice, stream));
+        NBTE_HIP(hipMemcpyAsync(d_pint.as<int32_t>() + DN, prog.slot.data(), DN * 4, hipMemcpyHostToDevice, stream));
+        NBTE_HIP(hipMemcpyAsync(d_pint.as<int32_t>() + 2 * DN, prog.ref.data(), prog.maxin * DN * 4,
+                                hipMemcpyHostToDevice, stream));
         upload(d_pupc, prog.upc, stream);
         coef_prec = -1;
         upload(d_gptr, prog.gptr, stream);
@@ -230,6 +276,27 @@ void nbte_problem::upload_device() {
         upload(d_Lcol, diff.col, stream);
         upload(d_Lval, diff.val, stream);
         upload(d_Ldinv, dinv, stream);
+        {
+            // ELL copy of the matrix for the multi-workgroup CG, scaled A D^-1
+            const int64_t N = m.N;
+            int W = 1;
+            for (int64_t c = 0; c < N; ++c) W = std::max<int>(W, diff.row_ptr[c + 1] - diff.row_ptr[c]);
+            if (W > 8) throw Error(NBTE_ERR_MESH, "cells with more than 7 faces are not supported");
+            W = 8;   // the kernel reads every slot
+            std::vector<int32_t> ecol((size_t)W * N);
+            std::vector<double> eval((size_t)W * N, 0.0);
+            for (int64_t c = 0; c < N; ++c)
+                for (int s = 0; s < W; ++s) {
+                    const int64_t q = diff.row_ptr[c] + s;
+                    const bool used = q < diff.row_ptr[c + 1];
+                    ecol[(size_t)s * N + c] = used ? diff.col[q] : (int32_t)c;
+                    eval[(size_t)s * N + c] = used ? diff.val[q] * dinv[diff.col[q]] : 0.0;
+                }
+            upload(d_Ecol, ecol, stream);
+            upload(d_Eval, eval, stream);
+            NBTE_HIP(hipStreamSynchronize(stream));   // the host copies go out of scope
+            ell_w = W;
+        }
         pcg_nblk = (int)std::min<int64_t>(256, cdiv(m.N, 256));
         d_pcg_vec.alloc(7 * m.N * sizeof(double));
         d_pcg_part.alloc(4 * 256 * sizeof(double));
@@ -251,18 +318,22 @@ void nbte_problem::allocate_state(int prec) {
     const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
     d_g.alloc(D * N * B * es);
     d_gval.alloc(std::max<int64_t>((int64_t)prog.ghost_src.size() * B, 1) * es);
-    d_tq.alloc(D * N * es);
-    d_tdc.alloc(D * N * es);
-    if (coef_prec != prec) {
-        if (prec == NBTE_PREC_MIXED) {
-            std::vector<float> fc(prog.coef.begin(), prog.coef.end()), fs(prog.sout.begin(), prog.sout.end());
-            upload(d_tcoef, fc, stream);
-            upload(d_tsout, fs, stream);
-            NBTE_HIP(hipStreamSynchronize(stream));   // the host copies go out of scope
-        } else {
-            upload(d_tcoef, prog.coef, stream);
-            upload(d_tsout, prog.sout, stream);
-        }
+    const int64_t DN = D * N;
+    void *before = d_tstream.ptr;
+    d_tstream.alloc((size_t)(3 + prog.maxin) * DN * es);
+    if (coef_prec != prec || d_tstream.ptr != before) {
+        // outflow sums (row 0) and coefficients (rows 3..) in the storage type
+        auto put = [&](int row, const std::vector<double> &h) {
+            if (prec == NBTE_PREC_MIXED) {
+                std::vector<float> f(h.begin(), h.end());
+                NBTE_HIP(hipMemcpyAsync(t_row(row), f.data(), f.size() * 4, hipMemcpyHostToDevice, stream));
+                NBTE_HIP(hipStreamSynchronize(stream));   // the host copy goes out of scope
+            } else {
+                NBTE_HIP(hipMemcpyAsync(t_row(row), h.data(), h.size() * 8, hipMemcpyHostToDevice, stream));
+            }
+        };
+        put(0, prog.sout);
+        put(3, prog.coef);
         coef_prec = prec;
     }
     d_Jw.alloc(std::max<int64_t>(NBF, 1) * 8);
@@ -280,9 +351,8 @@ void nbte_problem::allocate_state(int prec) {
 int64_t nbte_problem::device_bytes() const {
     int64_t s = 0;
     for (const DevBuf *b :
-         {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pcell, &d_pslot, &d_pref, &d_pupc, &d_tcoef,
-          &d_tsout, &d_tq, &d_tdc, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
-          &d_mirror, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_g, &d_gval,
+         {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pint, &d_pupc, &d_tstream, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
+          &d_mirror, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_Ecol, &d_Eval, &d_g, &d_gval,
           &d_Jw, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work})
         s += (int64_t)b->bytes;
@@ -303,25 +373,22 @@ void nbte_problem::make_view() {
     v.V = d_V.as<double>();
     v.maxin = prog.maxin;
     v.max_levels = sched.max_levels;
-    {
-        int lanes = (shape.bpb + shape.bpl - 1) / shape.bpl, lpc = 1;
-        while (lpc < lanes) lpc <<= 1;
-        v.lpc = lpc;
-    }
+    v.lpc = shape.lpc;
     v.bpb = shape.bpb;
     v.gcap = shape.gcap;
-    v.lstride = sweep_lds_stride(shape.bpb);
+    v.gring = shape.gring;
+    v.lstride = shape.ls;
     v.lvl_ptr = d_lvl_ptr.as<int32_t>();
     v.lvl_off = d_lvl_off.as<int32_t>();
     v.gptr = d_gptr.as<int32_t>();
-    v.p_cell = d_pcell.as<int32_t>();
-    v.p_slot = d_pslot.as<int32_t>();
-    v.p_ref = d_pref.as<int32_t>();
+    v.p_cell = d_pint.as<int32_t>();
+    v.p_slot = d_pint.as<int32_t>() + stream_DN();
+    v.p_ref = d_pint.as<int32_t>() + 2 * stream_DN();
     v.p_upc = d_pupc.as<int32_t>();
-    v.t_coef = d_tcoef.ptr;
-    v.t_sout = d_tsout.ptr;
-    v.t_q = d_tq.ptr;
-    v.t_dc = d_tdc.ptr;
+    v.t_sout = t_row(0);
+    v.t_dc = t_row(1);
+    v.t_q = t_row(2);
+    v.t_coef = t_row(3);
     v.Cw = d_Cw.as<double>();
     v.src = d_src.as<double>();
     v.vel = d_vel.as<double>();
@@ -358,6 +425,9 @@ void nbte_problem::make_view() {
     w.col = d_Lcol.as<int32_t>();
     w.val = d_Lval.as<double>();
     w.dinv = d_Ldinv.as<double>();
+    w.ell_w = ell_w;
+    w.ecol = d_Ecol.as<int32_t>();
+    w.eval = d_Eval.as<double>();
     w.vec = d_pcg_vec.as<double>();
     w.partial = d_pcg_part.as<double>();
     w.scal = d_pcg_scal.as<double>();
@@ -418,7 +488,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     s0.best = INFINITY;
     NBTE_HIP(hipMemcpyAsync(d_state.ptr, &s0, sizeof(s0), hipMemcpyHostToDevice, stream));
     NBTE_HIP(hipMemcpyAsync(d_Q.ptr, Q.data(), m.N * 8, hipMemcpyHostToDevice, stream));
-    launch_gather((int64_t)quad.D * m.N, d_pcell.as<int32_t>(), d_Q.as<double>(), d_tq.ptr, fp32(), stream);
+    launch_gather((int64_t)quad.D * m.N, p_cell(), d_Q.as<double>(), t_row(2), fp32(), stream);
     double *th0 = d_theta[0].as<double>();   // theta[cur] at rotation 0
     if (o.T_init) {
         NBTE_HIP(hipMemcpyAsync(th0, t0.data(), m.N * 8, hipMemcpyHostToDevice, stream));
@@ -489,7 +559,7 @@ void nbte_problem::promote() {
     ensure_setup();   // launch shape and slot table for FP64 staged values
     allocate_state(precision);
     launch_widen(n, old_g.as<float>(), d_g.as<double>(), stream);
-    launch_gather((int64_t)quad.D * mesh->N, d_pcell.as<int32_t>(), d_Q.as<double>(), d_tq.ptr, false, stream);
+    launch_gather((int64_t)quad.D * mesh->N, p_cell(), d_Q.as<double>(), t_row(2), false, stream);
     make_view();
     NBTE_HIP(hipMemcpyAsync(d_view.ptr, &hv, sizeof(DeviceView), hipMemcpyHostToDevice, stream));
     NBTE_HIP(hipGetLastError());
@@ -855,14 +925,14 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
         if (!p->have_bands || !p->have_quad) throw Error(NBTE_ERR_STATE, "bands and quadrature must be set");
         const Mesh &m = *p->mesh;
         const int64_t N = m.N, F = m.F, D = p->quad.D, NBF = m.NBF;
-        const int64_t mi = std::max<int64_t>(F - 1, 1);
+        const int64_t mi = F - 1 <= 2 ? 2 : (F - 1 == 3 ? 3 : 5);   // reference rows (fan-in class)
         const int64_t geo = N * F * 4 + N * 8 + NBF * 4;
         // level tables (at most one level per cell); streams cell, slot, refs, upwind cells, coefficients
         // and outflow sums (storage type); inflow rows
         const int64_t es = precision == NBTE_PREC_MIXED ? 4 : 8;
         const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * (8 + es) + es) + NBF * D * 4;
         const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * D * (8 + 4);
-        const int64_t lh = N * (F + 1) * 12 + N * 8 * 8 + 256 * 4 * 8;
+        const int64_t lh = 2 * N * (F + 1) * 12 + N * 8 * 8 + 256 * 4 * 8;   // CSR and ELL copies, vectors
         *bytes = geo + sched + plan + lh + p->state_bytes(precision);
         return NBTE_OK;
     });
