@@ -129,10 +129,12 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
         if (p < 1.0) {
             double acc = 0.0;
             if (on) {
-#pragma unroll 4
+                // incoming directions (s.S <= 0) read one shared element
+                // instead of their own, so only outgoing values are fetched
+#pragma unroll 8
                 for (int j = jg; j < D; j += JG) {
                     const double a = sd[j];
-                    const double e = ld(g, ((int64_t)j * N + c) * B + lam_c) + eq;
+                    const double e = ld(g, a > 0.0 ? ((int64_t)j * N + c) * B + lam_c : 0) + eq;
                     acc += a > 0.0 ? v.w[j] * a * e : 0.0;
                 }
             }
@@ -765,18 +767,29 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
     const double th = (after ? theta_prev(v) : theta_cur(v))[c];
     const T *g = static_cast<const T *>(v.g);
     const T *gv = static_cast<const T *>(v.gval);
+    // lanes: BL bands x JG direction groups; a direction's s.S and inflow row
+    // are the same for the lanes of its group, and each element is one load
+    // (the inflow row of an incoming direction, the owner's value otherwise;
+    // directions with s.S = 0 contribute exactly zero)
+    const int BL = B < 64 ? B : 64, JG = 64 / BL;
+    const int jg = lane / BL, ml = lane - jg * BL;
     double acc = 0.0;
-    // both candidate values are loaded on every path (independent loads, four
-    // pairs in flight); directions with s.S = 0 contribute exactly zero
-#pragma unroll 4
-    for (int t = lane; t < D * B; t += 64) {
-        const int i = t / B, lam = t - i * B;
-        const double sd = v.sdotS[bf * D + i];
-        const int32_t row = v.in_row[bf * D + i];
-        const double ein = ld(gv, row >= 0 ? (int64_t)row * B + lam : 0) + v.Cw[lam] * th;
-        const double eout = ld(g, ((int64_t)i * N + c) * B + lam) + v.Cw[lam] * th;
-        const double e = row >= 0 ? ein : (sd > 0.0 ? eout : 0.0);
-        acc += v.vel[lam] * v.w[i] * sd * e;
+    if (jg < JG) {
+        for (int l0 = 0; l0 < B; l0 += BL) {
+            const int lam = l0 + ml;
+            if (lam >= B) break;
+            const double cwt = v.Cw[lam] * th;
+            double sum = 0.0;
+#pragma unroll 8
+            for (int i = jg; i < D; i += JG) {
+                const double sd = v.sdotS[bf * D + i];
+                const int32_t row = v.in_row[bf * D + i];
+                const T *src = row >= 0 ? gv + (int64_t)row * B : g + ((int64_t)i * N + c) * B;
+                const double e = ld(src, lam) + cwt;
+                sum += (row >= 0 || sd > 0.0) ? v.w[i] * sd * e : 0.0;
+            }
+            acc += v.vel[lam] * sum;
+        }
     }
     acc = wave_sum(acc);
     if (lane == 0) v.Jw[bf] = acc;
