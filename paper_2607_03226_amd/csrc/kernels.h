@@ -112,6 +112,8 @@ struct DeviceView {
     void NBTE_G *gval;             // n_ghost*B boundary inflow in sweep (ghost) order, type T, as the
                                    // deviation from equilibrium at the sweep's theta of the owner cell
     double NBTE_G *Jw;             // NBF: net flux through each boundary face
+    double NBTE_G *Jin;            // NBF: its incoming part, from the inflow the stage wrote
+    double NBTE_G *bsum;           // NBF*B: per band sum_out w (s.S) e of the last sweep
     double NBTE_G *theta[3];       // deviational lattice temperature, rotated by state->rot
     double NBTE_G *theta_seq, *thetaE, *q, *rhs, *delta;
     SolveState NBTE_G *state;
@@ -138,9 +140,12 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 //   update:  theta update and residual maxima (grid-stride over the cells)
 //   finish:  one thread per solve (a = solve); residual, stop test, rotation
 void launch_stage(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
-// after = 0: inside the iteration (theta[cur] is the sweep's temperature);
-// after = 1: once the iteration has rotated theta (theta[prev] is)
-void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int after, hipStream_t st);
+// mode 0: inside the iteration (theta[cur] is the sweep's temperature): the
+//         per-band outgoing sums of every reflective face and its net flow;
+// mode 1: once the iteration has rotated theta (theta[prev] is): the net flow
+//         of every face from the stored values;
+// mode 2: at prepare: the outgoing sums of the initial distribution
+void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int mode, hipStream_t st);
 void launch_moments(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
 void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);

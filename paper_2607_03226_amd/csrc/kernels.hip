@@ -84,10 +84,12 @@ __global__ void k_fill_zero(uint32_t *p, size_t n) {
 // theta of the coming sweep (the form the sweep works in).
 // --------------------------------------------------------------------------
 // One wave per boundary face.  Lanes are (direction group, band) pairs:
-// BL = min(B, 64) bands per pass, JG = 64 / BL directions in flight per band,
-// so the loads of a pass are independent and the bands of one (direction,
-// cell) are read as one contiguous run.  The diffuse sums are reduced across
-// the direction groups through LDS in a fixed order.
+// BL = min(B, 64) bands per pass, JG = 64 / BL directions in flight per band.
+// The diffuse part comes from the per-band outgoing sums the flux kernel
+// stored after the previous sweep (bsum = sum_out w (s.S) e, e of that
+// sweep), so only specular parts read the distribution.  The face's incoming
+// flow sum_l v_l sum_in w (s.S) e_in, with the values just written, is kept
+// for the flux kernel of this iteration (Jin).
 template <class T>
 __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
     const int lane = threadIdx.x & 63;
@@ -117,53 +119,43 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
     }
     const double thp = theta_prev(v)[c];
     const double p = v.bf_p[bf];
+    const double iw = 1.0 / v.win[bf];
     const int32_t *mir = v.mirror + bf * D;
+    double jin = 0.0;
     for (int l0 = 0; l0 < B; l0 += BL) {
         const int lam = l0 + ml;
-        const bool on = jg < JG && lam < B;
-        const int lam_c = on ? lam : 0;
-        const double cw = v.Cw[lam_c];
+        if (jg >= JG || lam >= B) continue;
+        const double cw = v.Cw[lam];
         const double eq = cw * thp;
         const double eqc = cw * thc;
-        double diff = 0.0;
-        if (p < 1.0) {
-            double acc = 0.0;
-            if (on) {
-                // incoming directions (s.S <= 0) read one shared element
-                // instead of their own, so only outgoing values are fetched
-#pragma unroll 8
-                for (int j = jg; j < D; j += JG) {
-                    const double a = sd[j];
-                    const double e = ld(g, a > 0.0 ? ((int64_t)j * N + c) * B + lam_c : 0) + eq;
-                    acc += a > 0.0 ? v.w[j] * a * e : 0.0;
-                }
-            }
-            red[lane] = acc;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-            for (int k = 0; k < JG; ++k) diff += red[k * BL + ml];
-            diff /= v.win[bf];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-        }
-        if (!on) continue;
+        const double diff = p < 1.0 ? v.bsum[bf * B + lam] * iw : 0.0;
+        double acc = 0.0;
         if (p > 0.0) {
 #pragma unroll 4
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
                 const int mi = mir[i] >= 0 ? mir[i] : 0;   // outgoing directions have no mirror entry
                 const double em = ld(g, ((int64_t)mi * N + c) * B + lam) + eq;
-                if (r >= 0) gv[(int64_t)r * B + lam] = static_cast<T>((1.0 - p) * diff + p * em - eqc);
+                const double e = (1.0 - p) * diff + p * em;
+                if (r >= 0) {
+                    gv[(int64_t)r * B + lam] = static_cast<T>(e - eqc);
+                    acc += v.w[i] * sd[i] * e;
+                }
             }
         } else {
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
-                if (r >= 0) gv[(int64_t)r * B + lam] = static_cast<T>(diff - eqc);
+                if (r >= 0) {
+                    gv[(int64_t)r * B + lam] = static_cast<T>(diff - eqc);
+                    acc += v.w[i] * sd[i] * diff;
+                }
             }
         }
+        jin += v.vel[lam] * acc;
     }
+    jin = wave_sum(jin);
+    if (lane == 0) v.Jin[bf] = jin;
+    (void)red;
 }
 
 // The imbalance term D of stream entries t0, t0 + stride, ...: every load of
@@ -750,49 +742,93 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
 // --------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
-                                              int after) {
+                                              int mode) {
+    // mode 0: inside the iteration (after the sweep, theta[cur] is its
+    //         temperature): the outgoing sums per band (bsum, for the next
+    //         boundary stage) and J_f = Jin + sum_l v_l bsum_l of every
+    //         reflective face (the correction's right-hand side);
+    // mode 1: once the iteration has rotated theta (theta[prev] is the
+    //         sweep's): J_f of every face from the stored values (the
+    //         energy balance);
+    // mode 2: at prepare: bsum of the initial distribution at theta[prev]
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
-    if (!after && v.state->done) return;
+    if (mode == 0 && v.state->done) return;
     const int64_t bf = (int64_t)it.b * 4 + (threadIdx.x >> 6);
     if (bf >= v.NBF) return;
-    // inside the iteration only reflective walls' flows are used (the
-    // correction's right-hand side); thermalizing ones matter for the energy
-    // balance read at the end
-    if (!after && v.bf_kind[bf] == NBTE_BC_THERMALIZING) return;
+    if (mode != 1 && v.bf_kind[bf] == NBTE_BC_THERMALIZING) return;
     const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
-    const double th = (after ? theta_prev(v) : theta_cur(v))[c];
+    const double th = (mode == 0 ? theta_cur(v) : theta_prev(v))[c];
     const T *g = static_cast<const T *>(v.g);
     const T *gv = static_cast<const T *>(v.gval);
-    // lanes: BL bands x JG direction groups; a direction's s.S and inflow row
-    // are the same for the lanes of its group, and each element is one load
-    // (the inflow row of an incoming direction, the owner's value otherwise;
-    // directions with s.S = 0 contribute exactly zero)
     const int BL = B < 64 ? B : 64, JG = 64 / BL;
     const int jg = lane / BL, ml = lane - jg * BL;
-    double acc = 0.0;
-    if (jg < JG) {
-        for (int l0 = 0; l0 < B; l0 += BL) {
-            const int lam = l0 + ml;
-            if (lam >= B) break;
-            const double cwt = v.Cw[lam] * th;
-            double sum = 0.0;
+    if (mode == 1) {
+        // every direction: the inflow row of an incoming one, the owner's
+        // value otherwise (directions with s.S = 0 contribute exactly zero)
+        double acc = 0.0;
+        if (jg < JG) {
+            for (int l0 = 0; l0 < B; l0 += BL) {
+                const int lam = l0 + ml;
+                if (lam >= B) break;
+                const double cwt = v.Cw[lam] * th;
+                double sum = 0.0;
+                for (int i = jg; i < D; i += JG) {
+                    const double sd = v.sdotS[bf * D + i];
+                    const int32_t row = v.in_row[bf * D + i];
+                    const T *src = row >= 0 ? gv + (int64_t)row * B : g + ((int64_t)i * N + c) * B;
+                    const double e = ld(src, lam) + cwt;
+                    sum += (row >= 0 || sd > 0.0) ? v.w[i] * sd * e : 0.0;
+                }
+                acc += v.vel[lam] * sum;
+            }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) v.Jw[bf] = acc;
+        return;
+    }
+    // outgoing directions only: every load is independent of the others
+    // (the owner's value is read for every direction and weighted by
+    // s.S > 0), the direction groups' partial sums are combined in LDS in a
+    // fixed order
+    __shared__ double part[4][64];
+    double* red = part[threadIdx.x >> 6];
+    double jout = 0.0;
+    for (int l0 = 0; l0 < B; l0 += BL) {
+        const int lam = l0 + ml;
+        const bool on = jg < JG && lam < B;
+        const int lc = on ? lam : 0;
+        const double cwt = v.Cw[lc] * th;
+        double sum = 0.0;
+        if (on) {
 #pragma unroll 8
             for (int i = jg; i < D; i += JG) {
                 const double sd = v.sdotS[bf * D + i];
-                const int32_t row = v.in_row[bf * D + i];
-                const T *src = row >= 0 ? gv + (int64_t)row * B : g + ((int64_t)i * N + c) * B;
-                const double e = ld(src, lam) + cwt;
-                sum += (row >= 0 || sd > 0.0) ? v.w[i] * sd * e : 0.0;
+                const double e = ld(g, ((int64_t)i * N + c) * B + lc) + cwt;
+                sum += sd > 0.0 ? v.w[i] * sd * e : 0.0;
             }
-            acc += v.vel[lam] * sum;
         }
+        red[lane] = sum;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        if (on && jg == 0) {
+            double s = 0.0;
+            for (int k = 0; k < JG; ++k) s += red[k * BL + ml];
+            v.bsum[bf * B + lam] = s;
+            jout += v.vel[lam] * s;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     }
-    acc = wave_sum(acc);
-    if (lane == 0) v.Jw[bf] = acc;
+    if (mode == 0) {
+        jout = wave_sum(jout);
+        if (lane == 0) v.Jw[bf] = v.Jin[bf] + jout;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -1302,10 +1338,10 @@ void launch_stage(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hi
     else hipLaunchKernelGGL(k_stage<double>, dim3(n), dim3(256), 0, st, vs, wk);
 }
 
-void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int after, hipStream_t st) {
+void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int mode, hipStream_t st) {
     if (n <= 0) return;
-    if (fp32) hipLaunchKernelGGL(k_flux<float>, dim3(n), dim3(256), 0, st, vs, wk, after);
-    else hipLaunchKernelGGL(k_flux<double>, dim3(n), dim3(256), 0, st, vs, wk, after);
+    if (fp32) hipLaunchKernelGGL(k_flux<float>, dim3(n), dim3(256), 0, st, vs, wk, mode);
+    else hipLaunchKernelGGL(k_flux<double>, dim3(n), dim3(256), 0, st, vs, wk, mode);
 }
 
 void launch_moments(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {

@@ -138,6 +138,7 @@ struct nbte_problem {
     nbte::DevBuf d_bf_owner, d_bf_kind, d_mirror, d_bf_thw, d_bf_p, d_sdotS, d_win;
     nbte::DevBuf d_Lrow, d_Lcol, d_Lval, d_Ldinv;
     nbte::DevBuf d_Ecol, d_Eval;     // ELL copy (A D^-1) for the multi-workgroup CG
+    nbte::DevBuf d_Jin, d_bsum;      // boundary faces: incoming flow, per-band outgoing sums
     nbte::DevBuf d_g, d_gval, d_Jw, d_Q;
     nbte::DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta;
     nbte::DevBuf d_pcg_vec, d_pcg_part, d_pcg_scal;

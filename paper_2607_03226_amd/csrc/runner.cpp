@@ -185,7 +185,8 @@ void Runner::build() {
         L.fp32 = f;
         L.off = (int)work.size();
         each(f, [&](int s, nbte_problem &p) {
-            if (!p.synthetic()) return;
+            // every scheme: the outgoing sums feed the next diffuse inflow
+            // (the net flows are used by the synthetic correction only)
             const int64_t nb = cdiv(p.mesh->NBF, 4);
             for (int64_t b = 0; b < nb; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb});
         });

@@ -310,7 +310,8 @@ int64_t nbte_problem::state_bytes(int prec) const {
     const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
     const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
     const int64_t ghosts = prog_B > 0 ? (int64_t)prog.ghost_src.size() : NBF * D;   // incoming pairs
-    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + NBF * 8 + N * 8 * 10 + 1024;
+    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + NBF * (B + 2) * 8 + N * 8 * 10 +
+           1024;
 }
 
 void nbte_problem::allocate_state(int prec) {
@@ -337,6 +338,8 @@ void nbte_problem::allocate_state(int prec) {
         coef_prec = prec;
     }
     d_Jw.alloc(std::max<int64_t>(NBF, 1) * 8);
+    d_Jin.alloc(std::max<int64_t>(NBF, 1) * 8);
+    d_bsum.alloc(std::max<int64_t>(NBF, 1) * B * 8);
     d_Q.alloc(N * 8);
     for (auto &t : d_theta) t.alloc(N * 8);
     d_theta_seq.alloc(N * 8);
@@ -353,7 +356,7 @@ int64_t nbte_problem::device_bytes() const {
     for (const DevBuf *b :
          {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pint, &d_pupc, &d_tstream, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
           &d_mirror, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_Ecol, &d_Eval, &d_g, &d_gval,
-          &d_Jw, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
+          &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work})
         s += (int64_t)b->bytes;
     return s;
@@ -409,6 +412,8 @@ void nbte_problem::make_view() {
     v.g = d_g.ptr;
     v.gval = d_gval.ptr;
     v.Jw = d_Jw.as<double>();
+    v.Jin = d_Jin.as<double>();
+    v.bsum = d_bsum.as<double>();
     for (int k = 0; k < 3; ++k) v.theta[k] = d_theta[k].as<double>();
     v.theta_seq = d_theta_seq.as<double>();
     v.thetaE = d_thetaE.as<double>();
@@ -520,6 +525,8 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     NBTE_HIP(hipMemcpyAsync(d_theta[1].ptr, th0, m.N * 8, hipMemcpyDeviceToDevice, stream));
     launch_fill_zero(d_g.ptr, d_g.bytes, stream);
     launch_fill_zero(d_gval.ptr, d_gval.bytes, stream);
+    // the first boundary stage's diffuse sums, from the initial distribution
+    launch_flux(d_view.as<DeviceView>(), d_self_work.as<WorkItem>() + self_flux, n_self_flux, fp32(), 2, stream);
     NBTE_HIP(hipGetLastError());
     NBTE_HIP(hipStreamSynchronize(stream));
     hs = s0;
