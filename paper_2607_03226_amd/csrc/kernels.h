@@ -135,7 +135,7 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 // blocks of this (solve, kind)), 256 threads each.
 //   stage:   kind 0 = boundary inflow, one wave per boundary face;
 //            kind 1 = equilibrium-imbalance term D of every stream entry
-//   flux:    net flow through each boundary face, four faces per workgroup
+//   flux:    per-band outgoing sums and net flow, one workgroup per boundary face
 //   moments: band x direction reductions, mom_lpc lanes per cell
 //   update:  theta update and residual maxima (grid-stride over the cells)
 //   finish:  one thread per solve (a = solve); residual, stop test, rotation

@@ -110,6 +110,7 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
             const int lam = l0 + ml;
             if (jg >= JG || lam >= B) continue;
             const T val = static_cast<T>(v.Cw[lam] * thw - v.Cw[lam] * thc);
+#pragma unroll 8
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
                 if (r >= 0) gv[(int64_t)r * B + lam] = val;
@@ -131,7 +132,7 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
         const double diff = p < 1.0 ? v.bsum[bf * B + lam] * iw : 0.0;
         double acc = 0.0;
         if (p > 0.0) {
-#pragma unroll 4
+#pragma unroll 8
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
                 const int mi = mir[i] >= 0 ? mir[i] : 0;   // outgoing directions have no mirror entry
@@ -143,6 +144,7 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
                 }
             }
         } else {
+#pragma unroll 8
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
                 if (r >= 0) {
@@ -751,13 +753,17 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
     //         sweep's): J_f of every face from the stored values (the
     //         energy balance);
     // mode 2: at prepare: bsum of the initial distribution at theta[prev]
+    // One workgroup per face: the four waves take every fourth direction
+    // group, lanes are (direction group, band) pairs; the partial sums are
+    // combined through LDS in a fixed order.
+    __shared__ double part[4][64];
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (mode == 0 && v.state->done) return;
-    const int64_t bf = (int64_t)it.b * 4 + (threadIdx.x >> 6);
+    const int64_t bf = it.b;
     if (bf >= v.NBF) return;
     if (mode != 1 && v.bf_kind[bf] == NBTE_BC_THERMALIZING) return;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
@@ -766,37 +772,8 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
     const T *gv = static_cast<const T *>(v.gval);
     const int BL = B < 64 ? B : 64, JG = 64 / BL;
     const int jg = lane / BL, ml = lane - jg * BL;
-    if (mode == 1) {
-        // every direction: the inflow row of an incoming one, the owner's
-        // value otherwise (directions with s.S = 0 contribute exactly zero)
-        double acc = 0.0;
-        if (jg < JG) {
-            for (int l0 = 0; l0 < B; l0 += BL) {
-                const int lam = l0 + ml;
-                if (lam >= B) break;
-                const double cwt = v.Cw[lam] * th;
-                double sum = 0.0;
-                for (int i = jg; i < D; i += JG) {
-                    const double sd = v.sdotS[bf * D + i];
-                    const int32_t row = v.in_row[bf * D + i];
-                    const T *src = row >= 0 ? gv + (int64_t)row * B : g + ((int64_t)i * N + c) * B;
-                    const double e = ld(src, lam) + cwt;
-                    sum += (row >= 0 || sd > 0.0) ? v.w[i] * sd * e : 0.0;
-                }
-                acc += v.vel[lam] * sum;
-            }
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) v.Jw[bf] = acc;
-        return;
-    }
-    // outgoing directions only: every load is independent of the others
-    // (the owner's value is read for every direction and weighted by
-    // s.S > 0), the direction groups' partial sums are combined in LDS in a
-    // fixed order
-    __shared__ double part[4][64];
-    double* red = part[threadIdx.x >> 6];
-    double jout = 0.0;
+    const int i0 = wv * JG + jg, di = nw * JG;   // this lane's directions: i0, i0 + di, ...
+    double jsum = 0.0;
     for (int l0 = 0; l0 < B; l0 += BL) {
         const int lam = l0 + ml;
         const bool on = jg < JG && lam < B;
@@ -804,30 +781,41 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
         const double cwt = v.Cw[lc] * th;
         double sum = 0.0;
         if (on) {
+            if (mode == 1) {
+                // every direction: the inflow row of an incoming one, the
+                // owner's value otherwise (s.S = 0 contributes exactly zero)
+                for (int i = i0; i < D; i += di) {
+                    const double sd = v.sdotS[bf * D + i];
+                    const int32_t row = v.in_row[bf * D + i];
+                    const T *src = row >= 0 ? gv + (int64_t)row * B : g + ((int64_t)i * N + c) * B;
+                    const double e = ld(src, lc) + cwt;
+                    sum += (row >= 0 || sd > 0.0) ? v.w[i] * sd * e : 0.0;
+                }
+            } else {
+                // outgoing directions: the owner's value is read for every
+                // direction (independent loads) and weighted by s.S > 0
 #pragma unroll 8
-            for (int i = jg; i < D; i += JG) {
-                const double sd = v.sdotS[bf * D + i];
-                const double e = ld(g, ((int64_t)i * N + c) * B + lc) + cwt;
-                sum += sd > 0.0 ? v.w[i] * sd * e : 0.0;
+                for (int i = i0; i < D; i += di) {
+                    const double sd = v.sdotS[bf * D + i];
+                    const double e = ld(g, ((int64_t)i * N + c) * B + lc) + cwt;
+                    sum += sd > 0.0 ? v.w[i] * sd * e : 0.0;
+                }
             }
         }
-        red[lane] = sum;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-        if (on && jg == 0) {
-            double s = 0.0;
-            for (int k = 0; k < JG; ++k) s += red[k * BL + ml];
-            v.bsum[bf * B + lam] = s;
-            jout += v.vel[lam] * s;
+        part[wv][lane] = sum;
+        __syncthreads();
+        if (wv == 0 && on && jg == 0) {
+            double t = 0.0;
+            for (int w = 0; w < nw; ++w)
+                for (int k = 0; k < JG; ++k) t += part[w][k * BL + ml];
+            if (mode != 1) v.bsum[bf * B + lam] = t;
+            jsum += v.vel[lam] * t;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        __syncthreads();
     }
-    if (mode == 0) {
-        jout = wave_sum(jout);
-        if (lane == 0) v.Jw[bf] = v.Jin[bf] + jout;
+    if (wv == 0) {
+        jsum = wave_sum(jsum);
+        if (lane == 0 && mode != 2) v.Jw[bf] = (mode == 0 ? v.Jin[bf] : 0.0) + jsum;
     }
 }
 

@@ -187,7 +187,7 @@ void Runner::build() {
         each(f, [&](int s, nbte_problem &p) {
             // every scheme: the outgoing sums feed the next diffuse inflow
             // (the net flows are used by the synthetic correction only)
-            const int64_t nb = cdiv(p.mesh->NBF, 4);
+            const int64_t nb = p.mesh->NBF;   // a workgroup per face
             for (int64_t b = 0; b < nb; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb});
         });
         close(L);

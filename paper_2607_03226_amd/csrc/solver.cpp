@@ -475,7 +475,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     NBTE_HIP(hipMemcpyAsync(d_view.ptr, &hv, sizeof(DeviceView), hipMemcpyHostToDevice, stream));
     // work items of the single-solve launches: [one][PCG workgroups][flux workgroups]
     {
-        const int nf = (int)cdiv(m.NBF, 4);
+        const int nf = (int)m.NBF;   // flux: a workgroup per boundary face
         std::vector<WorkItem> wk;
         wk.push_back({0, 0, 0, 1});
         self_pcg = (int)wk.size();

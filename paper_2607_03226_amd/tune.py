@@ -1,8 +1,9 @@
-"""Autotuner of the sweep launch shape.
+"""Autotuner of the sweep launch shape and the correction's CG cap.
 
 For a problem it times candidate shapes (bands per workgroup, bands per lane,
 workgroup size, LDS budget) through the C ABI's HIP-event phase timers and
-keeps the fastest.  Results are cached in tune_cache.json next to this file,
+keeps the fastest; for the synthetic schemes it then picks the CG iteration
+cap of the diffusion correction by time-to-converge.  Results are cached in tune_cache.json next to this file,
 keyed by (cell type, cell-count bucket, bands, directions, precision), and
 looked up by nbte.solve(..., tuning="auto").
 """
@@ -70,7 +71,25 @@ def time_shape(h, problem, precision, shape, iters=4):
     return (st["ms_sweep"] - st0["ms_sweep"]) / max(n, 1)
 
 
-def tune(problem, precision="mixed", shapes=None, iters=4, verbose=True, write=True):
+def time_to_converge(h, problem, precision, shape, tol=1e-8, max_iter=20000, reps=2):
+    """Wall time of a whole steady solve (setup cached) with a launch shape."""
+    N.nbte_set_tuning(h, **shape)
+    opts = N.make_opts(scheme=problem.scheme, precision=precision, T_ref=problem.T_ref, tol=tol, max_iter=max_iter)
+    N.nbte_solve_steady(h, problem.Q, opts)        # setup for this shape and precision
+    best, iters = float("inf"), 0
+    for _ in range(reps):
+        t = time.perf_counter()
+        out = N.nbte_solve_steady(h, problem.Q, opts)
+        best = min(best, time.perf_counter() - t)
+        iters = out["iterations"]
+    return best, iters
+
+
+def tune(problem, precision="mixed", shapes=None, iters=4, verbose=True, write=True,
+         cg_choices=(4, 6, 8, 12, 16, 24, 32)):
+    """Fastest sweep shape by sweep time; then, for the synthetic schemes, the
+    correction's CG iteration cap by time-to-converge (fewer CG launches per
+    iteration against more outer iterations)."""
     mesh, h = N.build_problem(problem)
     table = []
     t0 = time.time()
@@ -87,6 +106,16 @@ def tune(problem, precision="mixed", shapes=None, iters=4, verbose=True, write=T
             print(f"tune: {problem.name} {precision} {shape} sweep {ms:.4f} ms ({ups:.3e} updates/s)", flush=True)
     table.sort(key=lambda t: t[0])
     best_ms, best = table[0]
+    best = dict(best)
+    if problem.scheme != "sequential" and cg_choices:
+        conv = []
+        for cg in cg_choices:
+            sec, it = time_to_converge(h, problem, precision, dict(best, cg_max_iter=cg))
+            conv.append((sec, cg))
+            if verbose:
+                print(f"tune: {problem.name} {precision} cg_max_iter {cg}: converged in {it} iterations, {sec:.4f} s",
+                      flush=True)
+        best["cg_max_iter"] = min(conv)[1]
     if write:
         cache = load_cache()
         cache[key(problem, precision)] = {"shape": best, "sweep_ms": best_ms, "workload": problem.name,
@@ -102,6 +131,18 @@ if __name__ == "__main__":
     from workloads import configs as C
     names = sys.argv[1:] or ["config2"]
     for name in names:
+        if name == "config4":
+            # one representative film per cache key (size bucket) of the batch
+            seen = set()
+            for p in C.config4():
+                k = key(p, "mixed")
+                if k in seen:
+                    continue
+                seen.add(k)
+                for prec in ("mixed", "fp64"):
+                    best, ms, _ = tune(p, prec, verbose=False)
+                    print(f"tune: BEST config4/{p.name} {prec} {best} {ms:.4f} ms", flush=True)
+            continue
         p = {"config1": C.config1, "config2": C.config2, "config3": C.config3}[name]()
         for prec in ("mixed", "fp64"):
             best, ms, _ = tune(p, prec)
