@@ -225,8 +225,10 @@ typedef struct {
     int32_t bands_per_block;  /* bands of one direction per sweep workgroup (0 = auto) */
     int32_t bands_per_lane;   /* bands one lane sweeps (1,2,4,8; 0 = auto) */
     int32_t block_size;       /* threads per sweep workgroup (64..1024, multiple of 64; 0 = auto) */
-    int32_t lds_bytes;        /* LDS budget per sweep workgroup for staged neighbour values
-                                 (0 = auto, -1 = no staging: neighbours read from HBM) */
+    int32_t lds_bytes;        /* LDS budget per sweep workgroup (level tables, inflow ring and
+                                 staged neighbour values), at most 163840 and capped at the
+                                 device's per-workgroup LDS (0 = auto: half of a CU's LDS,
+                                 -1 = no staging: neighbours read from HBM) */
     int32_t cg_max_iter;      /* diffusion-correction CG iterations per outer iteration (0 = auto) */
     double cg_rtol;           /* diffusion-correction CG relative tolerance (0 = auto) */
     int32_t no_graphs;        /* 1: launch every kernel eagerly instead of replaying HIP graphs

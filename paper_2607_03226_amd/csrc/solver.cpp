@@ -904,7 +904,8 @@ nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t) {
     return guarded([&] {
         if (!p || !t) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
         if (t->bands_per_block < 0) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block must be >= 0");
-        if (t->lds_bytes < -1 || t->lds_bytes > 65536) throw Error(NBTE_ERR_INVALID_ARG, "lds_bytes must be -1, 0 or <= 65536");
+        if (t->lds_bytes < -1 || t->lds_bytes > 163840)
+            throw Error(NBTE_ERR_INVALID_ARG, "lds_bytes must be -1, 0 or <= 163840 (capped at the device's per-workgroup LDS)");
         const int bpl = t->bands_per_lane;
         if (bpl != 0 && bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8)
             throw Error(NBTE_ERR_INVALID_ARG, "bands_per_lane must be 0, 1, 2, 4 or 8");

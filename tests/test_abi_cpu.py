@@ -176,3 +176,33 @@ def test_footprint_scales_with_precision():
     ndn = p.n_cells * p.n_dirs
     halved = p.n_cells * p.n_bands * p.n_dirs * 4
     assert halved < f64 - f32 <= halved + ndn * (6 + 3) * 4 + p.n_bands * len(p.bfaces) * p.n_dirs * 4
+
+
+def test_tuning_validation():
+    p = C.config1()
+    mesh, h = _handles(p)
+    N.nbte_set_tuning(h, lds_bytes=163840, cg_max_iter=12)   # a whole CU's LDS may be asked for
+    t = N.nbte_get_tuning(h)
+    assert t["lds_bytes"] == 163840 and t["cg_max_iter"] == 12
+    for bad in (163841, -2):
+        with pytest.raises(N.NbteError) as e:
+            N.nbte_set_tuning(h, lds_bytes=bad)
+        assert e.value.status == N.ERR_INVALID_ARG
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_tuning(h, cg_max_iter=-1)
+    assert e.value.status == N.ERR_INVALID_ARG
+
+
+def test_tuner_keys_and_candidates():
+    from paper_2607_03226_amd import tune
+    p2 = C.config2_small()
+    k = tune.key(p2, "mixed")
+    assert k.startswith(f"{p2.cell_type}|") and k.endswith(f"|B{p2.n_bands}|D{p2.n_dirs}|mixed")
+    shapes = tune.candidates(16)
+    assert all(s["bands_per_lane"] <= s["bands_per_block"] for s in shapes)
+    # one lane per cell (bands per lane = bands per workgroup) is among the candidates up to 8 bands
+    assert any(s["bands_per_block"] == s["bands_per_lane"] == 8 for s in shapes)
+    # the committed cache holds a CG cap for the synthetic workloads it covers
+    cache = tune.load_cache()
+    for entry in cache.values():
+        assert entry["shape"].get("cg_max_iter", 8) in (4, 6, 8, 12, 16, 24, 32)
