@@ -74,6 +74,12 @@ def bench_batch(args, N, tune):
             keep.append((mesh, h))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        # the iteration-independent setup of every film, 16 at a time on the
+        # host threads (the library call releases the interpreter lock), then
+        # admission (initial guess) in order
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=16) as ex:
+            list(ex.map(lambda ph: N.nbte_problem_setup(ph[1], prec), keep))
         for p, (mesh, h) in zip(probs, keep):
             N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision=prec, T_ref=p.T_ref, tol=tol,
                                                           max_iter=max_iter))

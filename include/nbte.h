@@ -242,6 +242,19 @@ nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t);
  * (set_bands/set_quadrature must have been called). */
 nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int64_t *bytes);
 
+/* Build and upload the iteration-independent setup of a problem for a
+ * precision -- sweep schedules and streams, LDS slot table, boundary plan,
+ * band tables, diffusion operator, device state -- without starting a solve
+ * (the setup step the method precomputes once; Methods, iteration scheme).
+ * The next nbte_prepare / nbte_solve_steady / nbte_batch_admit at that
+ * precision and tuning reuses it, so a caller admitting many problems can run
+ * their setups concurrently, one thread per problem (different problems share
+ * no state).  Errors: those of nbte_prepare's setup (NBTE_ERR_STATE when
+ * bands, quadrature or boundaries are missing or the problem is a batch
+ * member, NBTE_ERR_MESH, NBTE_ERR_BOUNDARY, NBTE_ERR_ILL_POSED,
+ * NBTE_ERR_DEVICE). */
+nbte_status nbte_problem_setup(nbte_problem *p, int32_t precision);
+
 /* -------------------------------------------------------------- batches -- */
 
 /* A batch iterates many independent solves together: every kernel of an

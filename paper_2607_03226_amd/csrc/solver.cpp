@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -69,15 +70,16 @@ nbte_problem::~nbte_problem() {
 
 // LDS bytes one workgroup may use on the current device (64 KiB if unknown)
 static int lds_limit() {
-    static int cached = 0;
-    if (cached > 0) return cached;
+    static std::atomic<int> cached{0};   // problems may be set up from several threads
+    const int c = cached.load(std::memory_order_relaxed);
+    if (c > 0) return c;
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
         (void)hipGetLastError();
         return 65536;
     }
-    cached = v;
+    cached.store(v, std::memory_order_relaxed);
     return v;
 }
 
@@ -923,6 +925,21 @@ nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t) {
     return guarded([&] {
         if (!p || !t) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
         *t = p->tuning;
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_problem_setup(nbte_problem *p, int32_t precision) {
+    return guarded([&] {
+        if (!p) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        if (precision != NBTE_PREC_FP64 && precision != NBTE_PREC_MIXED) throw Error(NBTE_ERR_INVALID_ARG, "bad precision");
+        if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member; remove it from the batch first");
+        require_gfx950();
+        p->prepared = false;
+        p->precision = precision;   // the launch shape's LDS budget depends on it
+        p->ensure_setup();
+        p->allocate_state(precision);
+        NBTE_HIP(hipStreamSynchronize(p->stream));
         return NBTE_OK;
     });
 }

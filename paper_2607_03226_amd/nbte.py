@@ -91,6 +91,7 @@ SIGNATURES = [
     ("nbte_set_tuning", ct.c_int32, [ct.c_void_p, ct.POINTER(Tuning)]),
     ("nbte_get_tuning", ct.c_int32, [ct.c_void_p, ct.POINTER(Tuning)]),
     ("nbte_problem_footprint", ct.c_int32, [ct.c_void_p, ct.c_int32, _i64]),
+    ("nbte_problem_setup", ct.c_int32, [ct.c_void_p, ct.c_int32]),
     ("nbte_batch_create", ct.c_int32, [ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_void_p)]),
     ("nbte_batch_destroy", None, [ct.c_void_p]),
     ("nbte_batch_admit", ct.c_int32, [ct.c_void_p, ct.c_void_p, _d, ct.POINTER(SolveOpts)]),
@@ -348,6 +349,10 @@ def nbte_problem_footprint(p, precision="mixed"):
     _check(_lib.nbte_problem_footprint(p.handle, PRECISION[precision] if isinstance(precision, str) else int(precision),
                                        ct.byref(b)))
     return b.value
+
+
+def nbte_problem_setup(p, precision="mixed"):
+    _check(_lib.nbte_problem_setup(p.handle, PRECISION[precision] if isinstance(precision, str) else int(precision)))
 
 
 class Batch:

@@ -49,13 +49,15 @@ def percentile(x, q):
 
 
 def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_iter=20000, step=8,
-          keep_results=False, tuning=None, clock=time.perf_counter, log=None):
+          keep_results=False, tuning=None, clock=time.perf_counter, log=None, lookahead=4):
     """Run the request stream.
 
     requests  list of problem descriptions (see nbte.build_problem)
     arrivals  arrival times in seconds from the start (non-decreasing)
     budget    device bytes the running solves may hold together
     tuning    None, "auto" (autotuner cache) or a dict of launch-shape settings
+    lookahead waiting requests whose setup runs ahead on host threads (their
+              setup holds device memory outside the admission budget)
     Returns (list of Served, summary dict).
     """
     n = len(requests)
@@ -70,23 +72,40 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
     def now():
         return clock() - t0
 
-    built = {}                  # host setup of waiting requests, kept across admission attempts
+    # setup of waiting requests (mesh, tables, schedules, streams: the
+    # iteration-independent part), run on host threads for the first
+    # `lookahead` requests in the queue while the GPU steps the batch; a
+    # request's setup is kept across admission attempts
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=max(1, lookahead))
+    built = {}
+
+    def setup(j):
+        p = requests[j]
+        mesh, h = N.build_problem(p)
+        if tuning == "auto":
+            from . import tune
+            shape = tune.lookup(p, precision)
+            if shape:
+                N.nbte_set_tuning(h, **shape)
+        elif tuning:
+            N.nbte_set_tuning(h, **tuning)
+        N.nbte_problem_setup(h, precision)
+        return mesh, h
+
+    def start_setups():
+        for j in list(queue)[:max(1, lookahead)]:
+            if j not in built:
+                built[j] = pool.submit(setup, j)
 
     def admit_waiting():
+        start_setups()
         while queue:
             j = queue[0]
             p = requests[j]
             if j not in built:
-                mesh, h = N.build_problem(p)
-                if tuning == "auto":
-                    from . import tune
-                    shape = tune.lookup(p, precision)
-                    if shape:
-                        N.nbte_set_tuning(h, **shape)
-                elif tuning:
-                    N.nbte_set_tuning(h, **tuning)
-                built[j] = (mesh, h)
-            mesh, h = built[j]
+                built[j] = pool.submit(setup, j)
+            mesh, h = built[j].result()
             opts = N.make_opts(scheme=p.scheme, precision=precision, T_ref=p.T_ref, tol=tol, max_iter=max_iter)
             try:
                 N.nbte_batch_admit(batch, h, p.Q, opts)
@@ -98,6 +117,7 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
                 return              # wait for running solves to leave
             queue.popleft()
             del built[j]
+            start_setups()
             handles[h.handle.value] = (j, mesh, h)
             served[j].admitted = now()
             if log:
@@ -133,6 +153,7 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
                 log(f"serve: t={s.finished:.3f} s finished {j} {s.name} in {s.iterations} iterations, "
                     f"latency {s.latency:.3f} s")
             del mesh, hh
+    pool.shutdown(wait=True)
     lat = [s.latency for s in served]
     span = max(s.finished for s in served) - min(s.arrival for s in served)
     summary = {"requests": n, "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),

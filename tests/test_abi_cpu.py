@@ -206,3 +206,11 @@ def test_tuner_keys_and_candidates():
     cache = tune.load_cache()
     for entry in cache.values():
         assert entry["shape"].get("cg_max_iter", 8) in (4, 6, 8, 12, 16, 24, 32)
+
+
+def test_setup_call_validates_before_touching_the_device():
+    p = C.config1()
+    mesh, h = _handles(p)
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_problem_setup(h, 7)
+    assert e.value.status == N.ERR_INVALID_ARG

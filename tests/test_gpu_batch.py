@@ -171,3 +171,23 @@ def test_stalled_mixed_member_continues_in_fp64():
     res = _drain(N, batch, handles, step=16, limit=40000)
     for h, (a, refined_at) in zip(handles, alone):
         _same(res[h.handle.value], a)
+
+
+def test_setup_on_several_threads_then_admission_equals_alone():
+    """The iteration-independent setup of several problems run concurrently on
+    host threads (nbte_problem_setup), then batch admission: each member's
+    result is bitwise its stand-alone solve's."""
+    from concurrent.futures import ThreadPoolExecutor
+    N = _N()
+    probs = C.config4_small()
+    alone = [_alone(N, p, "mixed", 1e-8) for p in probs]
+    built = [N.build_problem(p) for p in probs]
+    with ThreadPoolExecutor(max_workers=len(built)) as ex:
+        list(ex.map(lambda mh: N.nbte_problem_setup(mh[1], "mixed"), built))
+    batch = N.nbte_batch_create()
+    for p, (mesh, h) in zip(probs, built):
+        N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision="mixed", T_ref=p.T_ref, tol=1e-8,
+                                                       max_iter=4000))
+    res = _drain(N, batch, [h for _, h in built])
+    for (mesh, h), a in zip(built, alone):
+        _same(res[h.handle.value], a)
