@@ -210,7 +210,8 @@ def summarize_counters(args):
            "fetch_scale": ffac, "write_scale": wfac, "traffic_bytes_per_launch": traffic,
            "kernel_source_sha256_16": kernel_source_hash(),
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
-                        "--steps 3 --warmup 1 --no-cpu --no-converge",
+                        f"--workload {args.workload} --precision {args.precision} "
+                        f"--steps {args.steps} --warmup {args.warmup} --no-cpu --no-converge",
                         "rocprofv3 --pmc WRITE_SIZE (same)",
                         f"rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE -- python bench.py --copy-probe {probe >> 20}"]}
     path = os.path.join(ROOT, "profiles", f"sweep_{args.workload}_{args.precision}_counters.json")
