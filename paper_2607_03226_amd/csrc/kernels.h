@@ -105,6 +105,12 @@ struct DeviceView {
     const double NBTE_G *qbias;    // 3: q of a uniform unit equilibrium
     // boundary plan
     const int32_t NBTE_G *bf_owner, *bf_kind, *mirror;
+    // cells owning a reflective face (the correction's wall term): n_wall
+    // cells, ascending; their reflective faces' slots wall_ptr[k] ..
+    // wall_ptr[k+1] in face order; wslot = slot of a reflective face (-1
+    // for a thermalizing one)
+    const int32_t NBTE_G *wall_cell, *wall_ptr, *wslot;
+    int64_t n_wall;
     const int32_t NBTE_G *in_row;  // NBF*D: ghost row of an incoming (face, direction), -1 otherwise
     const double NBTE_G *bf_thw, *bf_p, *sdotS, *win;
     // state
@@ -113,6 +119,7 @@ struct DeviceView {
                                    // deviation from equilibrium at the sweep's theta of the owner cell
     double NBTE_G *Jw;             // NBF: net flux through each boundary face
     double NBTE_G *Jin;            // NBF: its incoming part, from the inflow the stage wrote
+    double NBTE_G *wallJ;          // J_f of the reflective faces in wall-slot order
     double NBTE_G *bsum;           // NBF*B: per band sum_out w (s.S) e of the last sweep
     double NBTE_G *theta[3];       // deviational lattice temperature, rotated by state->rot
     double NBTE_G *theta_seq, *thetaE, *q, *rhs, *delta;
@@ -135,8 +142,12 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 // blocks of this (solve, kind)), 256 threads each.
 //   stage:   kind 0 = boundary inflow, one wave per boundary face;
 //            kind 1 = equilibrium-imbalance term D of every stream entry
-//   flux:    per-band outgoing sums and net flow, one workgroup per boundary face
-//   moments: band x direction reductions, mom_lpc lanes per cell
+//   flux:    per-band outgoing sums and net flow, one wave per boundary face
+//            (items (solve, -, b, nblk): faces b*4 + wave, strided by 4 nblk)
+//   post:    kind 0 = flux mode 0 face groups (as above); kind 1 = band x
+//            direction reductions, mom_lpc lanes per cell, item b = block b
+//   wall rhs: the reflective faces' net flows into the correction's
+//            right-hand side (grid-stride over the cells that own one)
 //   update:  theta update and residual maxima (grid-stride over the cells)
 //   finish:  one thread per solve (a = solve); residual, stop test, rotation
 void launch_stage(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
@@ -146,7 +157,8 @@ void launch_stage(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hi
 //         of every face from the stored values;
 // mode 2: at prepare: the outgoing sums of the initial distribution
 void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int mode, hipStream_t st);
-void launch_moments(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
+void launch_post(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
+void launch_wall_rhs(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 

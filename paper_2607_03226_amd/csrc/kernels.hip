@@ -741,38 +741,31 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
 // net heat flow through each boundary face: one wave per face
 //   J_f = sum_l v_l sum_i w_i (s_i . S_f) e
 // with e the owner's value for outgoing and the inflow for incoming directions
+//   mode 0: inside the iteration (after the sweep, theta[cur] is its
+//           temperature): the outgoing sums per band (bsum, for the next
+//           boundary stage) and J_f = Jin + sum_l v_l bsum_l of every
+//           reflective face (the correction's right-hand side);
+//   mode 1: once the iteration has rotated theta (theta[prev] is the
+//           sweep's): J_f of every face from the stored values (the
+//           energy balance);
+//   mode 2: at prepare: bsum of the initial distribution at theta[prev]
+// Lanes are (direction group, band) pairs, BL = min(B, 64) bands per pass and
+// JG = 64 / BL direction groups; the groups of a band are combined by lane
+// shuffles in a fixed order.
 // --------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
-                                              int mode) {
-    // mode 0: inside the iteration (after the sweep, theta[cur] is its
-    //         temperature): the outgoing sums per band (bsum, for the next
-    //         boundary stage) and J_f = Jin + sum_l v_l bsum_l of every
-    //         reflective face (the correction's right-hand side);
-    // mode 1: once the iteration has rotated theta (theta[prev] is the
-    //         sweep's): J_f of every face from the stored values (the
-    //         energy balance);
-    // mode 2: at prepare: bsum of the initial distribution at theta[prev]
-    // One workgroup per face: the four waves take every fourth direction
-    // group, lanes are (direction group, band) pairs; the partial sums are
-    // combined through LDS in a fixed order.
-    __shared__ double part[4][64];
-    const WorkItem it = wk[blockIdx.x];
-    const DeviceView &v = vs[it.solve];
-    if (mode == 0 && v.state->done) return;
-    const int64_t bf = it.b;
-    if (bf >= v.NBF) return;
+__device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
     if (mode != 1 && v.bf_kind[bf] == NBTE_BC_THERMALIZING) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
     const double th = (mode == 0 ? theta_cur(v) : theta_prev(v))[c];
     const T *g = static_cast<const T *>(v.g);
     const T *gv = static_cast<const T *>(v.gval);
+    const double *sd = v.sdotS + bf * D;
     const int BL = B < 64 ? B : 64, JG = 64 / BL;
     const int jg = lane / BL, ml = lane - jg * BL;
-    const int i0 = wv * JG + jg, di = nw * JG;   // this lane's directions: i0, i0 + di, ...
     double jsum = 0.0;
     for (int l0 = 0; l0 < B; l0 += BL) {
         const int lam = l0 + ml;
@@ -784,56 +777,59 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
             if (mode == 1) {
                 // every direction: the inflow row of an incoming one, the
                 // owner's value otherwise (s.S = 0 contributes exactly zero)
-                for (int i = i0; i < D; i += di) {
-                    const double sd = v.sdotS[bf * D + i];
+                for (int i = jg; i < D; i += JG) {
                     const int32_t row = v.in_row[bf * D + i];
                     const T *src = row >= 0 ? gv + (int64_t)row * B : g + ((int64_t)i * N + c) * B;
                     const double e = ld(src, lc) + cwt;
-                    sum += (row >= 0 || sd > 0.0) ? v.w[i] * sd * e : 0.0;
+                    sum += (row >= 0 || sd[i] > 0.0) ? v.w[i] * sd[i] * e : 0.0;
                 }
             } else {
                 // outgoing directions: the owner's value is read for every
                 // direction (independent loads) and weighted by s.S > 0
 #pragma unroll 8
-                for (int i = i0; i < D; i += di) {
-                    const double sd = v.sdotS[bf * D + i];
+                for (int i = jg; i < D; i += JG) {
                     const double e = ld(g, ((int64_t)i * N + c) * B + lc) + cwt;
-                    sum += sd > 0.0 ? v.w[i] * sd * e : 0.0;
+                    sum += sd[i] > 0.0 ? v.w[i] * sd[i] * e : 0.0;
                 }
             }
         }
-        part[wv][lane] = sum;
-        __syncthreads();
-        if (wv == 0 && on && jg == 0) {
-            double t = 0.0;
-            for (int w = 0; w < nw; ++w)
-                for (int k = 0; k < JG; ++k) t += part[w][k * BL + ml];
+        double t = 0.0;
+        for (int k = 0; k < JG; ++k) t += __shfl(sum, k * BL + ml);
+        if (on && jg == 0) {
             if (mode != 1) v.bsum[bf * B + lam] = t;
             jsum += v.vel[lam] * t;
         }
-        __syncthreads();
     }
-    if (wv == 0) {
-        jsum = wave_sum(jsum);
-        if (lane == 0 && mode != 2) v.Jw[bf] = (mode == 0 ? v.Jin[bf] : 0.0) + jsum;
+    jsum = wave_sum(jsum);
+    if (lane == 0 && mode != 2) {
+        const double J = (mode == 0 ? v.Jin[bf] : 0.0) + jsum;
+        v.Jw[bf] = J;
+        if (mode == 0) v.wallJ[v.wslot[bf]] = J;   // a reflective face always has a slot
     }
+}
+
+// faces b*4 + wave, b*4 + wave + 4*nblk, ... of work item (solve, -, b, nblk)
+template <class T>
+__global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                              int mode) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (mode == 0 && v.state->done) return;
+    const int wv = threadIdx.x >> 6;
+    for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4) flux_face<T>(v, bf, mode);
 }
 
 // --------------------------------------------------------------------------
 // band x direction reductions (Methods, Eqs. (5), (7); T = energy temperature)
 // mom_lpc lanes per cell, FP64 accumulation, shuffle reduction over the lanes.
-// Synthetic schemes also get the V-weighted right-hand side of the correction:
-//   V (Qdot - D_h' q) = V beta (theta_seq - theta) + sum_{reflective f} J_f
-// (collision-divergence identity; reflective walls carry zero net flux at the
-// fixed point, so their transient flux is returned to the cell).
+// Synthetic schemes also get the collision part V beta (theta_seq - theta) of
+// the correction's right-hand side; the reflective walls' net flows are added
+// by k_wall_rhs once the flux is known.
 // --------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_moments(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
-    const WorkItem it = wk[blockIdx.x];
-    const DeviceView &v = vs[it.solve];
-    if (v.state->done) return;
+__device__ __forceinline__ void moments_block(const DeviceView &v, int64_t blk) {
     const int lpc = v.mom_lpc;
-    const int64_t c = ((int64_t)it.b * blockDim.x + threadIdx.x) / lpc;
+    const int64_t c = (blk * blockDim.x + threadIdx.x) / lpc;
     const int lane = threadIdx.x % lpc;
     const int64_t N = v.N;
     const int B = v.B, D = v.D;
@@ -873,14 +869,45 @@ __global__ void __launch_bounds__(256) k_moments(const DeviceView *__restrict__ 
         v.q[3 * c] = qx + th * v.qbias[0];
         v.q[3 * c + 1] = qy + th * v.qbias[1];
         v.q[3 * c + 2] = qz + th * v.qbias[2];
-        if (v.scheme != NBTE_SCHEME_SEQUENTIAL) {
-            double r = v.V[c] * a_tau;
-            for (int f = 0; f < v.F; ++f) {
-                const int n = v.nbr[c * v.F + f];
-                if (n < 0 && v.bf_kind[-n - 1] != NBTE_BC_THERMALIZING) r += v.Jw[-n - 1];
-            }
-            v.rhs[c] = r;
-        }
+        if (v.scheme != NBTE_SCHEME_SEQUENTIAL) v.rhs[c] = v.V[c] * a_tau;
+    }
+}
+
+// The work after a sweep that reads its distribution, in one launch: items
+// (solve, 0, b, nblk) are boundary-face flux (k_flux's mode 0 face groups),
+// items (solve, 1, b, -) moment blocks.  The two read the same distribution
+// and depend on nothing of each other, so the latency-bound face waves run
+// beside the bandwidth-bound moment blocks.
+template <class T>
+__global__ void __launch_bounds__(256) k_post(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    if (it.a == 0) {
+        const int wv = threadIdx.x >> 6;
+        for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4) flux_face<T>(v, bf, 0);
+    } else {
+        moments_block<T>(v, it.b);
+    }
+}
+
+// Right-hand side of the correction, wall part (collision-divergence
+// identity): V (Qdot - D_h' q) = V beta (theta_seq - theta) + sum_{reflective f} J_f.
+// Reflective walls carry zero net flux at the fixed point, so their transient
+// flux is returned to the cell.  One thread per cell with a reflective face
+// (grid-stride); the flux waves stored the net flows of a cell's reflective
+// faces in consecutive slots wall_ptr[k] .. wall_ptr[k+1], in the cell's face
+// order, so a thread needs two memory round trips.
+__global__ void __launch_bounds__(256) k_wall_rhs(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    for (int64_t k = (int64_t)it.b * blockDim.x + threadIdx.x; k < v.n_wall; k += (int64_t)it.c * blockDim.x) {
+        const int c = v.wall_cell[k];
+        const int j0 = v.wall_ptr[k], j1 = v.wall_ptr[k + 1];
+        double r = v.rhs[c];
+        for (int j = j0; j < j1; ++j) r += v.wallJ[j];
+        v.rhs[c] = r;
     }
 }
 
@@ -1332,10 +1359,15 @@ void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int
     else hipLaunchKernelGGL(k_flux<double>, dim3(n), dim3(256), 0, st, vs, wk, mode);
 }
 
-void launch_moments(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
+void launch_post(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
     if (n <= 0) return;
-    if (fp32) hipLaunchKernelGGL(k_moments<float>, dim3(n), dim3(256), 0, st, vs, wk);
-    else hipLaunchKernelGGL(k_moments<double>, dim3(n), dim3(256), 0, st, vs, wk);
+    if (fp32) hipLaunchKernelGGL(k_post<float>, dim3(n), dim3(256), 0, st, vs, wk);
+    else hipLaunchKernelGGL(k_post<double>, dim3(n), dim3(256), 0, st, vs, wk);
+}
+
+void launch_wall_rhs(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_wall_rhs, dim3(n), dim3(256), 0, st, vs, wk);
 }
 
 void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {
@@ -1347,6 +1379,7 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
     if (n <= 0) return;
     hipLaunchKernelGGL(k_finish, dim3((n + 63) / 64), dim3(64), 0, st, vs, wk, n);
 }
+
 
 size_t sweep_lds_bytes(int max_levels, int gring, int ls, int slots, int es) {
     const SweepLdsLayout L = sweep_lds_layout(max_levels, gring, ls, es);

@@ -136,6 +136,9 @@ struct nbte_problem {
     void *t_row(int r) const;        // row r of d_tstream
     nbte::DevBuf d_Cw, d_src, d_vel, d_itau, d_dirs, d_w, d_qbias;
     nbte::DevBuf d_bf_owner, d_bf_kind, d_mirror, d_bf_thw, d_bf_p, d_sdotS, d_win;
+    nbte::DevBuf d_wall, d_wall_ptr, d_wslot;   // cells owning a reflective face, their face slots
+    nbte::DevBuf d_wallJ;            // net flows of the reflective faces in slot order
+    int64_t n_wall = 0, n_wall_faces = 0;
     nbte::DevBuf d_Lrow, d_Lcol, d_Lval, d_Ldinv;
     nbte::DevBuf d_Ecol, d_Eval;     // ELL copy (A D^-1) for the multi-workgroup CG
     nbte::DevBuf d_Jin, d_bsum;      // boundary faces: incoming flow, per-band outgoing sums

@@ -17,7 +17,7 @@ namespace nbte {
 
 namespace {
 
-enum Kind { K_MARK, K_STAGE, K_SWEEP, K_FLUX, K_MOM, K_PCG_BLOCK, K_PCG_MULTI, K_UPDATE, K_FINISH };
+enum Kind { K_MARK, K_STAGE, K_SWEEP, K_POST, K_WALL, K_PCG_BLOCK, K_PCG_MULTI, K_UPDATE, K_FINISH };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -180,27 +180,33 @@ void Runner::build() {
 
     mark(PH_MOM);
     for (bool f : {true, false}) {
+        // boundary flux (every scheme: the outgoing sums feed the next
+        // diffuse inflow; the net flows are used by the synthetic correction
+        // only) first, the moment blocks after it, in one launch
         Launch L;
-        L.kind = K_FLUX;
+        L.kind = K_POST;
         L.fp32 = f;
         L.off = (int)work.size();
         each(f, [&](int s, nbte_problem &p) {
-            // every scheme: the outgoing sums feed the next diffuse inflow
-            // (the net flows are used by the synthetic correction only)
-            const int64_t nb = p.mesh->NBF;   // a workgroup per face
+            const int64_t nb = cdiv(p.mesh->NBF, 4);   // a wave per face
             for (int64_t b = 0; b < nb; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb});
+        });
+        each(f, [&](int s, nbte_problem &p) {
+            const int64_t nb = cdiv(p.mesh->N * p.hv.mom_lpc, 256);
+            for (int64_t b = 0; b < nb; ++b) work.push_back({s, 1, (int32_t)b, (int32_t)nb});
         });
         close(L);
     }
-    for (bool f : {true, false}) {
+    {
         Launch L;
-        L.kind = K_MOM;
-        L.fp32 = f;
+        L.kind = K_WALL;
         L.off = (int)work.size();
-        each(f, [&](int s, nbte_problem &p) {
-            const int64_t nb = cdiv(p.mesh->N * p.hv.mom_lpc, 256);
+        for (int s = 0; s < M; ++s) {
+            const nbte_problem &p = *members_[s];
+            if (!p.synthetic() || p.n_wall == 0) continue;
+            const int64_t nb = std::min<int64_t>(cdiv(p.n_wall, 256), 64);
             for (int64_t b = 0; b < nb; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb});
-        });
+        }
         close(L);
     }
 
@@ -270,8 +276,8 @@ void Runner::enqueue_iteration(int slot) {
             case K_SWEEP:
                 launch_sweep(vs, wk + L.off, L.n, L.fp32, L.maxin, L.bpl, L.one, L.mode, L.block, L.lds, stream_);
                 break;
-            case K_FLUX: launch_flux(vs, wk + L.off, L.n, L.fp32, 0, stream_); break;
-            case K_MOM: launch_moments(vs, wk + L.off, L.n, L.fp32, stream_); break;
+            case K_POST: launch_post(vs, wk + L.off, L.n, L.fp32, stream_); break;
+            case K_WALL: launch_wall_rhs(vs, wk + L.off, L.n, stream_); break;
             case K_PCG_BLOCK: launch_pcg_block(vs, wk + L.off, L.n, 0, stream_); break;
             case K_PCG_MULTI:
                 launch_pcg_multi(vs, wk + L.off, L.n, 0, L.iters, stream_);

@@ -245,6 +245,26 @@ void nbte_problem::upload_device() {
         upload(d_bf_p, plan.p, stream);
         upload(d_sdotS, plan.sdotS, stream);
         upload(d_win, plan.win, stream);
+        // cells owning a reflective face (the correction's wall term) and
+        // the slots of their reflective faces, in the cell's face order
+        std::vector<int32_t> wall, wptr(1, 0), wslot(std::max<int64_t>(m.NBF, 1), -1);
+        for (int64_t c = 0; c < m.N; ++c) {
+            const int32_t j0 = wptr.back();
+            int32_t j = j0;
+            for (int f = 0; f < m.F; ++f) {
+                const int32_t n = m.nbr[c * m.F + f];
+                if (n < 0 && plan.kind[-n - 1] != NBTE_BC_THERMALIZING) wslot[-n - 1] = j++;
+            }
+            if (j > j0) {
+                wall.push_back((int32_t)c);
+                wptr.push_back(j);
+            }
+        }
+        n_wall = (int64_t)wall.size();
+        n_wall_faces = wptr.back();
+        upload(d_wall, wall, stream);
+        upload(d_wall_ptr, wptr, stream);
+        upload(d_wslot, wslot, stream);
         plan_up = true;
     }
     if (!tables_ok) {
@@ -312,7 +332,7 @@ int64_t nbte_problem::state_bytes(int prec) const {
     const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
     const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
     const int64_t ghosts = prog_B > 0 ? (int64_t)prog.ghost_src.size() : NBF * D;   // incoming pairs
-    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + NBF * (B + 2) * 8 + N * 8 * 10 +
+    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + NBF * (B + 3) * 8 + N * 8 * 10 +
            1024;
 }
 
@@ -341,6 +361,7 @@ void nbte_problem::allocate_state(int prec) {
     }
     d_Jw.alloc(std::max<int64_t>(NBF, 1) * 8);
     d_Jin.alloc(std::max<int64_t>(NBF, 1) * 8);
+    d_wallJ.alloc(std::max<int64_t>(n_wall_faces, 1) * 8);
     d_bsum.alloc(std::max<int64_t>(NBF, 1) * B * 8);
     d_Q.alloc(N * 8);
     for (auto &t : d_theta) t.alloc(N * 8);
@@ -357,7 +378,7 @@ int64_t nbte_problem::device_bytes() const {
     int64_t s = 0;
     for (const DevBuf *b :
          {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pint, &d_pupc, &d_tstream, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
-          &d_mirror, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_Ecol, &d_Eval, &d_g, &d_gval,
+          &d_mirror, &d_wall, &d_wall_ptr, &d_wslot, &d_wallJ, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_Ecol, &d_Eval, &d_g, &d_gval,
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work})
         s += (int64_t)b->bytes;
@@ -406,6 +427,11 @@ void nbte_problem::make_view() {
     v.bf_owner = d_bf_owner.as<int32_t>();
     v.bf_kind = d_bf_kind.as<int32_t>();
     v.mirror = d_mirror.as<int32_t>();
+    v.wall_cell = d_wall.as<int32_t>();
+    v.wall_ptr = d_wall_ptr.as<int32_t>();
+    v.wslot = d_wslot.as<int32_t>();
+    v.wallJ = d_wallJ.as<double>();
+    v.n_wall = n_wall;
     v.in_row = d_inrow.as<int32_t>();
     v.bf_thw = d_bf_thw.as<double>();
     v.bf_p = d_bf_p.as<double>();
@@ -477,7 +503,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     NBTE_HIP(hipMemcpyAsync(d_view.ptr, &hv, sizeof(DeviceView), hipMemcpyHostToDevice, stream));
     // work items of the single-solve launches: [one][PCG workgroups][flux workgroups]
     {
-        const int nf = (int)m.NBF;   // flux: a workgroup per boundary face
+        const int nf = (int)std::max<int64_t>((m.NBF + 3) / 4, 1);   // flux: a wave per boundary face
         std::vector<WorkItem> wk;
         wk.push_back({0, 0, 0, 1});
         self_pcg = (int)wk.size();
@@ -956,7 +982,7 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
         // and outflow sums (storage type); inflow rows
         const int64_t es = precision == NBTE_PREC_MIXED ? 4 : 8;
         const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * (8 + es) + es) + NBF * D * 4;
-        const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * D * (8 + 4);
+        const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * 3 * 4 + 8 + NBF * D * (8 + 4);   // + wall cells, slots
         const int64_t lh = 2 * N * (F + 1) * 12 + N * 8 * 8 + 256 * 4 * 8;   // CSR and ELL copies, vectors
         *bytes = geo + sched + plan + lh + p->state_bytes(precision);
         return NBTE_OK;
