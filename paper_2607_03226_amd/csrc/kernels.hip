@@ -435,11 +435,16 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
                                            T NBTE_G *gi, int64_t base, int b0, int lane, int nb_here) {
     const int B = v.B;
     const T NBTE_G *gval = static_cast<const T NBTE_G *>(v.gval);
+    // this lane's bands [lofs, lofs + BPL) of the block, nv of them real;
+    // padding bands read valid rows (band clamped) and are never stored
+    const int lofs = lane * BPL;
+    const int nv = max(0, min(BPL, nb_here - lofs));
+    const bool vst = (B % BPL) == 0 && (b0 % BPL) == 0 && nv == BPL;   // whole-lane stores are aligned
+    T out[BPL];
 #pragma unroll
     for (int jb = 0; jb < BPL; ++jb) {
-        const int lb = lane * BPL + jb;
-        if (lb >= nb_here) break;
-        const int lam = b0 + lb;
+        const int lb = lofs + jb;
+        const int lam = min(b0 + lb, B - 1);
         T gain = 0;
 #pragma unroll
         for (int j = 0; j < MI; ++j) {
@@ -459,9 +464,17 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
             gain += r.cf[j] * up;
         }
         const T vel = bc.vel[jb];
-        const T g = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
-        gi[(int64_t)r.c * B + lam] = g;
-        lds_put<T>(r.mine + lb, g);   // own slot, or the scratch block
+        out[jb] = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
+    }
+    // one LDS access and one store per 16 bytes, as in the LDS-only path
+    lds_write_bands<T, BPL>(r.mine + lofs, out);   // own slot, or the scratch block
+    const uint32_t gc = (uint32_t)r.c * (uint32_t)B + (uint32_t)(b0 + lofs);
+    if (vst) {
+        gstore_bands<T, BPL>(gi, gc, out);
+    } else {
+#pragma unroll
+        for (int jb = 0; jb < BPL; ++jb)
+            if (jb < nv) gstore(gi, gc + jb, out[jb]);
     }
 }
 

@@ -275,3 +275,31 @@ def test_mixed_solve_that_stalls_continues_in_fp64():
         N.nbte_solve_steady(h, p.Q, N.make_opts(scheme="sequential", precision="mixed", T_ref=p.T_ref, tol=1e-11,
                                                 max_iter=3000, refine=False))
     assert e.value.status == N.ERR_NOT_CONVERGED
+
+
+def test_partial_spill_agrees_with_lds_only():
+    """LDS budgets that hold some but not all staged values: values without a
+    slot are read back from their stored copies (the spill path, vector LDS
+    writes and stores), the rest from LDS.  The mixed solution agrees with
+    the all-in-LDS launch to the FP32 sweep's rounding."""
+    N = _N()
+    p = C.config3_small()
+    opts = N.make_opts(scheme="synthetic", precision="mixed", T_ref=p.T_ref, tol=1e-9, max_iter=3000)
+
+    def run(tuning):
+        mesh, h = N.build_problem(p)
+        N.nbte_set_tuning(h, **tuning)
+        out = N.nbte_solve_steady(h, p.Q, opts)
+        return out, N.nbte_get_stats(h)
+
+    base, st0 = run({"bands_per_block": 4, "bands_per_lane": 2, "block_size": 512, "lds_bytes": 163840})
+    assert st0["spilled_values"] == 0
+    dev = np.max(np.abs(base["T_lattice"] - p.T_ref))
+    partial = 0
+    for lds in (4096, 8192, 16384, 32768):
+        out, st = run({"bands_per_block": 4, "bands_per_lane": 2, "block_size": 512, "lds_bytes": lds})
+        partial += st["lds_slots"] > 0 and st["spilled_values"] > 0
+        _log(f"config3_small/partial_spill/lds{lds}", {"slots": st["lds_slots"], "spilled": st["spilled_values"]})
+        assert np.max(np.abs(out["T_lattice"] - base["T_lattice"])) / dev < 1e-6
+        assert np.max(np.abs(out["q"] - base["q"])) / np.max(np.abs(base["q"])) < 1e-5
+    assert partial > 0   # at least one budget staged some values and spilled others
