@@ -155,15 +155,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload_name, precision):
+def _shape_key(shape):
+    """the launch-shape settings that select the sweep kernel and its work"""
+    keys = ("bands_per_block", "bands_per_lane", "block_size", "lds_bytes")
+    return {k: int(shape[k]) for k in keys if shape and k in shape} if shape else None
+
+
+def counter_traffic(workload_name, precision, shape):
     """HBM traffic per sweep launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source with the launch
+    shape the bench uses now."""
     path = os.path.join(ROOT, "profiles", f"sweep_{workload_name}_{precision}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if d.get("shape") != _shape_key(shape):
         return None
     return d.get("traffic_bytes_per_launch")
 
@@ -191,6 +200,12 @@ def _median_counter(rows, name_part, counter, pick_largest_grid=False):
     return xs[len(xs) // 2]
 
 
+def _tuned_shape(workload_name, precision):
+    """the launch shape bench.py runs a workload with (autotuner cache)"""
+    from paper_2607_03226_amd import tune
+    return tune.lookup(workload(workload_name), precision)
+
+
 def summarize_counters(args):
     """Write the sweep's HBM traffic per launch from four rocprofv3 --pmc runs
     (FETCH_SIZE and WRITE_SIZE of the bench, then of the copy probe) into
@@ -209,6 +224,7 @@ def summarize_counters(args):
            "copy_probe_bytes": probe, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": ffac, "write_scale": wfac, "traffic_bytes_per_launch": traffic,
            "kernel_source_sha256_16": kernel_source_hash(),
+           "shape": _shape_key(_tuned_shape(args.workload, args.precision)),
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
                         f"--workload {args.workload} --precision {args.precision} "
                         f"--steps {args.steps} --warmup {args.warmup} --no-cpu --no-converge",
@@ -346,7 +362,7 @@ def main():
 
     alg_bytes, per_update = sweep_algorithmic_bytes(p, args.precision)
     achieved = alg_bytes / (ms_sweep * 1e-3) / 1e9
-    traffic = counter_traffic(args.workload, args.precision)
+    traffic = counter_traffic(args.workload, args.precision, shape)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_sweep", "algorithmic_bytes_per_launch": alg_bytes,

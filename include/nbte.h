@@ -202,11 +202,13 @@ nbte_status nbte_get_schedule(nbte_problem *p, int32_t dir, int32_t *perm, int32
 typedef struct {
     int32_t iterations;
     double ms_total;        /* wall time of the last solve/iterate call, ms */
-    double ms_bc;           /* summed HIP-event times per phase (time_phases = 1) */
-    double ms_sweep;
-    double ms_moments;
-    double ms_synthetic;
-    double ms_update;
+    double ms_bc;           /* summed HIP-event times per phase (time_phases = 1):
+                               boundary inflow and imbalance term */
+    double ms_sweep;        /* transport sweep */
+    double ms_moments;      /* boundary-face flux, band x direction reductions, wall
+                               part of the correction's right-hand side */
+    double ms_synthetic;    /* PCG of the synthetic correction */
+    double ms_update;       /* theta update, residual, stop test */
     int32_t sweep_launches; /* launches of the transport sweep kernel timed above */
     int64_t updates_per_sweep;  /* n_cells * n_bands * n_dirs */
     int32_t max_levels;     /* deepest per-direction sweep schedule */

@@ -214,3 +214,22 @@ def test_setup_call_validates_before_touching_the_device():
     with pytest.raises(N.NbteError) as e:
         N.nbte_problem_setup(h, 7)
     assert e.value.status == N.ERR_INVALID_ARG
+
+
+def test_counter_traffic_needs_same_source_and_shape(tmp_path, monkeypatch):
+    """bench.py reports the committed counter traffic only while the kernel
+    source and the sweep's launch shape are the ones it was measured on."""
+    import json
+    import bench
+    (tmp_path / "profiles").mkdir()
+    shape = {"bands_per_block": 4, "bands_per_lane": 4, "block_size": 512, "lds_bytes": 0}
+    rec = {"kernel_source_sha256_16": "abc", "shape": shape, "traffic_bytes_per_launch": 123.0}
+    (tmp_path / "profiles" / "sweep_configX_mixed_counters.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    assert bench.counter_traffic("configX", "mixed", dict(shape, cg_max_iter=16)) == 123.0
+    assert bench.counter_traffic("configX", "mixed", dict(shape, bands_per_lane=2)) is None
+    assert bench.counter_traffic("configX", "mixed", None) is None
+    assert bench.counter_traffic("configX", "fp64", shape) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "def")
+    assert bench.counter_traffic("configX", "mixed", shape) is None
