@@ -52,9 +52,10 @@ struct PcgWork {
     const int32_t NBTE_G *row_ptr, *col;
     const double NBTE_G *val, *dinv;
     // the same matrix as ELL columns for the multi-workgroup form: slot s of
-    // row r at s n + r, ell_w = 8 slots (every slot is read: no per-slot
-    // branch splits the loads), values pre-scaled by the column's Jacobi
-    // factor (A D^-1); unused slots hold the row itself with value 0
+    // row r at s n + r, ell_w = 4, 5, 7 or 8 slots (the longest row rounded
+    // up; every slot is read: no per-slot branch splits the loads), values
+    // pre-scaled by the column's Jacobi factor (A D^-1); unused slots hold the
+    // row itself with value 0
     int32_t ell_w;
     const int32_t NBTE_G *ecol;
     const double NBTE_G *eval;

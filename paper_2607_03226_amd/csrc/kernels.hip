@@ -1164,20 +1164,30 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c, doub
     c = sc;
 }
 
-constexpr int kEllMax = 8;   // ELL slots per row of the multi-workgroup CG (faces + 1 <= 8)
-
-// r = A D^-1 x at one row, ELL form (values already scaled by D^-1)
+// ELL widths of the multi-workgroup CG (slots per row = faces + 1, rounded up
+// to one of 4, 5, 7, 8: triangles, quadrilaterals and tetrahedra, hexahedra,
+// anything up to seven faces); every slot of a row is read, so the width is a
+// template parameter and no padding slot is loaded
+template <int W>
 __device__ __forceinline__ double ell_row(const PcgWork &w, int64_t n, int64_t r, const double *x) {
-    int c[kEllMax];
-    double e[kEllMax];
+    int c[W];
+    double e[W];
 #pragma unroll
-    for (int s = 0; s < kEllMax; ++s)
+    for (int s = 0; s < W; ++s)
         c[s] = w.ecol[s * n + r], e[s] = w.eval[s * n + r];
     double au = 0.0;
 #pragma unroll
-    for (int s = 0; s < kEllMax; ++s)
+    for (int s = 0; s < W; ++s)
         au += e[s] * x[c[s]];
     return au;
+}
+__device__ __forceinline__ double ell_row_any(const PcgWork &w, int64_t n, int64_t r, const double *x) {
+    switch (w.ell_w) {
+        case 4: return ell_row<4>(w, n, r, x);
+        case 5: return ell_row<5>(w, n, r, x);
+        case 7: return ell_row<7>(w, n, r, x);
+        default: return ell_row<8>(w, n, r, x);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_cg1_init(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
@@ -1195,7 +1205,7 @@ __global__ void __launch_bounds__(256) k_cg1_init(const DeviceView *__restrict__
     for (int64_t r = (int64_t)it.b * blockDim.x + threadIdx.x; r < n; r += (int64_t)w.nblk * blockDim.x) {
         const double bi = b[r];
         const double u = w.dinv[r] * bi;
-        const double au = ell_row(w, n, r, b);
+        const double au = ell_row_any(w, n, r, b);
         x[r] = 0.0;
         r0[r] = bi;
         w0[r] = au;
@@ -1220,12 +1230,9 @@ __global__ void __launch_bounds__(256) k_cg1_init(const DeviceView *__restrict__
 // load a row needs (its vectors, its ELL row and the gathered neighbour
 // values) is issued before the reduction of the previous launch's partial
 // sums, so the launch costs about two memory round trips.
-__global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
-                                                  int mode, int k, double rtol2_o, int max_o) {
-    __shared__ double lds[80];
-    const WorkItem it = wk[blockIdx.x];
-    const DeviceView &v = vs[it.solve];
-    if (pcg_skip(v, mode)) return;
+template <int W>
+__device__ __forceinline__ void cg1_iter_rows(const DeviceView &v, const WorkItem &it, int mode, int k, double rtol2_o,
+                                              int max_o, double *lds) {
     const PcgWork &w = v.pcg;
     const int max_iter = max_o >= 0 ? max_o : w.max_iter;
     if (k >= max_iter) return;
@@ -1251,13 +1258,13 @@ __global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__
     const bool have = r0 < n;
     const int64_t ra = have ? r0 : 0;
     double d_rk = rk[ra], d_wk = wk_[ra], d_sk1 = sk1[ra], d_pp = pp[ra], d_di = w.dinv[ra], d_x = x[ra];
-    int c[kEllMax];
-    double e[kEllMax], gr[kEllMax], gw[kEllMax], gs[kEllMax];
+    int c[W];
+    double e[W], gr[W], gw[W], gs[W];
 #pragma unroll
-    for (int s = 0; s < kEllMax; ++s)
+    for (int s = 0; s < W; ++s)
         c[s] = w.ecol[s * n + ra], e[s] = w.eval[s * n + ra];
 #pragma unroll
-    for (int s = 0; s < kEllMax; ++s)
+    for (int s = 0; s < W; ++s)
         gr[s] = rk[c[s]], gw[s] = wk_[c[s]], gs[s] = sk1[c[s]];
     block_sum3(flag, gamma, delta, lds);
     if (flag != 0.0) return;
@@ -1279,10 +1286,10 @@ __global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__
         if (r != r0) {   // further rows (meshes above nblk x blockDim cells)
             d_rk = rk[r], d_wk = wk_[r], d_sk1 = sk1[r], d_pp = pp[r], d_di = w.dinv[r], d_x = x[r];
 #pragma unroll
-            for (int s = 0; s < kEllMax; ++s)
+            for (int s = 0; s < W; ++s)
                 c[s] = w.ecol[s * n + r], e[s] = w.eval[s * n + r];
 #pragma unroll
-            for (int s = 0; s < kEllMax; ++s)
+            for (int s = 0; s < W; ++s)
                 gr[s] = rk[c[s]], gw[s] = wk_[c[s]], gs[s] = sk1[c[s]];
         }
         const double ui = d_di * d_rk;
@@ -1296,7 +1303,7 @@ __global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__
         const double un = d_di * ri;
         double au = 0.0;
 #pragma unroll
-        for (int s = 0; s < kEllMax; ++s)
+        for (int s = 0; s < W; ++s)
             au += e[s] * (gr[s] - alpha * (gw[s] + beta * gs[s]));
         wn[r] = au;
         ga += ri * un;
@@ -1312,6 +1319,20 @@ __global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__
             w.scal[7 + 2 * cur] = gamma;
             w.scal[5] = k + 1;
         }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                                  int mode, int k, double rtol2_o, int max_o) {
+    __shared__ double lds[80];
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (pcg_skip(v, mode)) return;
+    switch (v.pcg.ell_w) {
+        case 4: cg1_iter_rows<4>(v, it, mode, k, rtol2_o, max_o, lds); break;
+        case 5: cg1_iter_rows<5>(v, it, mode, k, rtol2_o, max_o, lds); break;
+        case 7: cg1_iter_rows<7>(v, it, mode, k, rtol2_o, max_o, lds); break;
+        default: cg1_iter_rows<8>(v, it, mode, k, rtol2_o, max_o, lds); break;
     }
 }
 

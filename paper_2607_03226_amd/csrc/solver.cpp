@@ -304,7 +304,7 @@ void nbte_problem::upload_device() {
             int W = 1;
             for (int64_t c = 0; c < N; ++c) W = std::max<int>(W, diff.row_ptr[c + 1] - diff.row_ptr[c]);
             if (W > 8) throw Error(NBTE_ERR_MESH, "cells with more than 7 faces are not supported");
-            W = 8;   // the kernel reads every slot
+            W = W <= 4 ? 4 : (W == 5 ? 5 : (W <= 7 ? 7 : 8));   // the kernel variants read every slot
             std::vector<int32_t> ecol((size_t)W * N);
             std::vector<double> eval((size_t)W * N, 0.0);
             for (int64_t c = 0; c < N; ++c)
