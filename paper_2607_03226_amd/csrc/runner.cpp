@@ -104,7 +104,10 @@ void Runner::build() {
         L.off = (int)work.size();
         each(f, [&](int s, nbte_problem &p) {
             const int64_t nb0 = std::min<int64_t>(cdiv(p.mesh->NBF, 4), 2048);   // a wave per face
-            const int64_t nb1 = std::min<int64_t>(cdiv((int64_t)p.quad.D * p.mesh->N, 256), 16384);
+            // one stream entry per thread up to 16.8M entries (a grid-stride
+            // loop beyond): config 3's 13.9M entries 0.20 -> 0.18 ms against a
+            // cap of 16384 workgroups
+            const int64_t nb1 = std::min<int64_t>(cdiv((int64_t)p.quad.D * p.mesh->N, 256), 65536);
             for (int64_t b = 0; b < nb0; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb0});
             for (int64_t b = 0; b < nb1; ++b) work.push_back({s, 1, (int32_t)b, (int32_t)nb1});
         });
