@@ -236,7 +236,9 @@ def summarize_counters(args):
     print(json.dumps(out))
 
 
-def cpu_baseline(p, iters):
+def cpu_baseline(p, max_iters, seconds):
+    """The oracle's full synthetic iterations on the host cores, as many as
+    fit in about `seconds` (at least one, at most max_iters)."""
     import oracle
     from oracle.solver import _lib
     t0 = time.perf_counter()
@@ -245,7 +247,9 @@ def cpu_baseline(p, iters):
     theta = oracle.fourier_guess(su)
     e = np.broadcast_to(oracle.equilibrium(su, theta)[:, None, :], (p.n_bands, p.n_dirs, su.g.N))
     t0 = time.perf_counter()
-    for _ in range(iters):
+    iters = 0
+    while iters < max(1, max_iters) and (iters == 0 or time.perf_counter() - t0 < seconds):
+        iters += 1
         inflow = oracle.boundary_inflow(su, e)
         e, outflux = oracle.transport(su, theta, inflow)
         ts, _, _ = oracle.moments(su, e)
@@ -269,7 +273,8 @@ def main():
     ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config3", "config4", "config5"])
     ap.add_argument("--requests", type=int, default=24, help="config5: number of requests")
     ap.add_argument("--precision", default="mixed")
-    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--cpu-iters", type=int, default=40, help="most oracle iterations of the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU baseline sample length (about)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -396,7 +401,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(p, args.cpu_iters)
+        cpu = cpu_baseline(p, args.cpu_iters, args.cpu_seconds)
         log(f"bench: cpu baseline {cpu}")
 
     line = {
