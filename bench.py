@@ -287,8 +287,8 @@ def main():
         summarize_counters(args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the per-GPU path is what is measured, sharding is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the per-GPU path is what "
+              "is measured (every solve and batch lives on one GPU; nothing here uses a second)", file=sys.stderr)
         sys.exit(2)
 
     import torch
