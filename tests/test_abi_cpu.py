@@ -202,6 +202,9 @@ def test_tuner_keys_and_candidates():
     assert all(s["bands_per_lane"] <= s["bands_per_block"] for s in shapes)
     # one lane per cell (bands per lane = bands per workgroup) is among the candidates up to 8 bands
     assert any(s["bands_per_block"] == s["bands_per_lane"] == 8 for s in shapes)
+    # every shape is timed with the default LDS budget and with a whole CU's
+    assert {s["lds_bytes"] for s in shapes} == {0, tune.WHOLE_CU_LDS}
+    assert len(shapes) == 2 * len({(s["bands_per_block"], s["bands_per_lane"], s["block_size"]) for s in shapes})
     # the committed cache holds a CG cap for the synthetic workloads it covers
     cache = tune.load_cache()
     for entry in cache.values():
