@@ -6,17 +6,24 @@ system, the FP64 band x direction reductions, the FP64 synthetic diffusion
 correction and the FP64 residual.  value = cell*band*direction updates per
 second over the timed steps (inputs resident in HBM).
 
-Default workload: the 3D non-gray box (24^3 = 13,824 hex cells, 16 bands,
-128 directions), FP32-stored sweeps with FP64 reductions, synthetic scheme.
+Default workload: the FinFET-like device (144,480 tetrahedra, 32 bands, 96
+directions, Gaussian heat source, partially specular walls), FP32-stored
+sweeps with FP64 reductions, synthetic scheme.  --workload config2 runs the
+3D non-gray box (24^3 = 13,824 hexahedra, 16 bands, 128 directions).
 
 Also reported on the same line:
   roofline      the sweep kernel's algorithmic bytes per launch / its mean
-                HIP-event duration in the timed region, against 8 TB/s;
+                HIP-event duration in the timed region, against 8 TB/s.  The
+                bytes per update are the method's: the distribution read and
+                written once (2 x 4 B in FP32) plus one cached coefficient per
+                face, direction and cell shared by the bands (F x 4 B / B);
+                the kernel's own stream bytes are reported beside them;
   cpu_baseline  the oracle on this host's cores for a bounded number of
-                iterations of the same workload;
+                iterations of the same workload, plus its single-thread
+                sweep rate on a sample of (band, direction) systems;
   converge      time-to-converge of the mixed and the FP64 path (same
                 stopping rule), with their error against the stored oracle
-                reference when one exists.
+                reference on every cell.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config1..config5]
   config4: the 64-solve batch (time to converge, batched vs one by one);
@@ -130,8 +137,19 @@ def bench_serving(args, N):
     return summary
 
 
+def method_bytes_per_update(p, precision):
+    """Algorithmic bytes per cell x band x direction update of the method's
+    transport step (Methods, Eqs. (13)-(14)): the distribution read and
+    written once, 2 s_e, plus the per-(face, direction) coefficient of each
+    cell, cached once and shared by the B bands, F s_c / B, plus the per-cell
+    geometry and fields, (16 F + 48) / (B D)."""
+    es = 4 if precision == "mixed" else 8
+    F = {"tri3": 3, "quad4": 4, "tet4": 4, "hex8": 6}[p.cell_type]
+    return 2 * es + F * es / p.n_bands + (16 * F + 48) / (p.n_bands * p.n_dirs)
+
+
 def sweep_algorithmic_bytes(p, precision):
-    """Compulsory HBM bytes of one sweep launch: every distribution value
+    """Compulsory HBM bytes of one launch of this library's sweep: every distribution value
     written once; the level-ordered streams of every (direction, cell) read
     once (cell, slot, up to F-1 upwind references, their coefficients, the
     outflow sum, the imbalance term D and the source, the real-valued ones in
@@ -206,44 +224,73 @@ def _tuned_shape(workload_name, precision):
     return tune.lookup(workload(workload_name), precision)
 
 
+def counter_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, probe_bytes):
+    """The sweep's HBM traffic per launch from four rocprofv3 --pmc runs
+    (FETCH_SIZE and WRITE_SIZE of the bench, then of the copy probe).  The
+    counters (KiB per dispatch) are scaled by what they read for a device
+    copy of probe_bytes; the raw sum is kept beside the scaled one."""
+    fetch = _median_counter(_counter_rows(fetch_dir), "k_sweep", "FETCH_SIZE")
+    write = _median_counter(_counter_rows(write_dir), "k_sweep", "WRITE_SIZE")
+    cf = _median_counter(_counter_rows(copy_fetch_dir), "copyBuffer", "FETCH_SIZE", pick_largest_grid=True)
+    cw = _median_counter(_counter_rows(copy_write_dir), "copyBuffer", "WRITE_SIZE", pick_largest_grid=True)
+    ffac, wfac = probe_bytes / (cf * 1024.0), probe_bytes / (cw * 1024.0)
+    return {"fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
+            "copy_probe_bytes": probe_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+            "fetch_scale": ffac, "write_scale": wfac,
+            "traffic_bytes_per_launch": fetch * 1024.0 * ffac + write * 1024.0 * wfac,
+            "raw_bytes_per_launch": (fetch + write) * 1024.0}
+
+
 def summarize_counters(args):
-    """Write the sweep's HBM traffic per launch from four rocprofv3 --pmc runs
-    (FETCH_SIZE and WRITE_SIZE of the bench, then of the copy probe) into
-    profiles/sweep_<workload>_<precision>_counters.json.  The counters (KiB per
-    dispatch) are scaled by what they read for a device copy of known size."""
+    """Write profiles/sweep_<workload>_<precision>_counters.json from the four
+    rocprofv3 --pmc output directories."""
     fd, wd, cfd, cwd = args.summarize
     probe = args.copy_probe_bytes
-    fetch = _median_counter(_counter_rows(fd), "k_sweep", "FETCH_SIZE")
-    write = _median_counter(_counter_rows(wd), "k_sweep", "WRITE_SIZE")
-    cf = _median_counter(_counter_rows(cfd), "copyBuffer", "FETCH_SIZE", pick_largest_grid=True)
-    cw = _median_counter(_counter_rows(cwd), "copyBuffer", "WRITE_SIZE", pick_largest_grid=True)
-    ffac, wfac = probe / (cf * 1024.0), probe / (cw * 1024.0)
-    traffic = fetch * 1024.0 * ffac + write * 1024.0 * wfac
-    out = {"kernel": "k_sweep", "workload": args.workload, "precision": args.precision,
-           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
-           "copy_probe_bytes": probe, "copy_fetch_kib": cf, "copy_write_kib": cw,
-           "fetch_scale": ffac, "write_scale": wfac, "traffic_bytes_per_launch": traffic,
-           "kernel_source_sha256_16": kernel_source_hash(),
-           "shape": _shape_key(_tuned_shape(args.workload, args.precision)),
-           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
-                        f"--workload {args.workload} --precision {args.precision} "
-                        f"--steps {args.steps} --warmup {args.warmup} --no-cpu --no-converge",
-                        "rocprofv3 --pmc WRITE_SIZE (same)",
-                        f"rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE -- python bench.py --copy-probe {probe >> 20}"]}
+    out = {"kernel": "k_sweep", "workload": args.workload, "precision": args.precision}
+    out.update(counter_summary(fd, wd, cfd, cwd, probe))
+    out.update({"kernel_source_sha256_16": kernel_source_hash(),
+                "shape": _shape_key(_tuned_shape(args.workload, args.precision)),
+                "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- python bench.py "
+                             f"--workload {args.workload} --precision {args.precision} "
+                             f"--steps {args.steps} --warmup {args.warmup} --no-cpu --no-converge",
+                             "rocprofv3 --pmc WRITE_SIZE (same)",
+                             f"rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE -- python bench.py --copy-probe {probe >> 20}"]})
     path = os.path.join(ROOT, "profiles", f"sweep_{args.workload}_{args.precision}_counters.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
 
 
-def cpu_baseline(p, max_iters, seconds):
-    """The oracle's full synthetic iterations on the host cores, as many as
-    fit in about `seconds` (at least one, at most max_iters)."""
+def _host_cpu():
+    """core count and model of the host the CPU baseline ran on"""
+    info = {"nproc": os.cpu_count()}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    try:
+        info["sched_affinity"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(p, max_iters, seconds, one_thread_seconds=5.0):
+    """The oracle's full synthetic iterations on the host cores (OpenMP over
+    the band x direction systems), as many as fit in about `seconds` (at
+    least one, at most max_iters); then its single-thread sweep rate: the
+    exact transport solve of (band, direction) systems, one after the other
+    on one core, for about `one_thread_seconds`."""
     import oracle
-    from oracle.solver import _lib
     t0 = time.perf_counter()
     su = oracle.prepare(p)
     t_setup = time.perf_counter() - t0
+    threads = oracle.threads()
     theta = oracle.fourier_guess(su)
     e = np.broadcast_to(oracle.equilibrium(su, theta)[:, None, :], (p.n_bands, p.n_dirs, su.g.N))
     t0 = time.perf_counter()
@@ -259,10 +306,22 @@ def cpu_baseline(p, max_iters, seconds):
         np.add.at(r, su.g.bf_owner[refl], flows[refl] / su.g.V[su.g.bf_owner[refl]])
         theta = ts + oracle.diffusion_operator(su)[1].solve(su.g.V * r)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one core: systems in a seeded order, each solved exactly by the C sweep
+    rng = np.random.default_rng(0)
+    order = [(int(b), int(i)) for b, i in zip(rng.integers(p.n_bands, size=4096), rng.integers(p.n_dirs, size=4096))]
+    t1 = time.perf_counter()
+    k = 0
+    while k < len(order) and (k < 4 or time.perf_counter() - t1 < one_thread_seconds):
+        oracle.transport_systems(su, theta, inflow, order[k:k + 4])
+        k += 4
+    dt1 = time.perf_counter() - t1
     return {"value": p.updates_per_sweep * iters / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"{iters} full synthetic iterations of {p.name} (FP64, OpenMP over band x direction "
-                      f"systems), setup {t_setup:.1f} s excluded", "seconds": dt}
+                      f"systems on {threads} threads), setup {t_setup:.1f} s excluded", "seconds": dt,
+            "one_thread_sweep": {"value": p.n_cells * k / dt1, "unit": UNIT, "cores": 1, "seconds": dt1,
+                                 "sample": f"exact transport solves of {k} seeded (band, direction) systems "
+                                           f"of {p.name}, one core"},
+            "host": _host_cpu()}
 
 
 def main():
@@ -270,7 +329,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config3", "config4", "config5"])
+    ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3", "config4", "config5"])
     ap.add_argument("--requests", type=int, default=24, help="config5: number of requests")
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--cpu-iters", type=int, default=40, help="most oracle iterations of the CPU baseline")
@@ -297,7 +356,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     if args.copy_probe:
-        n = args.copy_probe << 18                 # float64 elements
+        n = args.copy_probe << 17                 # float64 elements of MIB MiB
         x = torch.ones(n, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
@@ -365,12 +424,17 @@ def main():
     log(f"bench: {args.steps} steps in {dt:.4f} s -> {value:.4e} updates/s (graphs); with phase events "
         f"{dt_events / args.steps * 1e3:.4f} ms/step; sweep {ms_sweep:.4f} ms; residual {res:.2e}")
 
-    alg_bytes, per_update = sweep_algorithmic_bytes(p, args.precision)
+    per_update = method_bytes_per_update(p, args.precision)
+    alg_bytes = per_update * ups
     achieved = alg_bytes / (ms_sweep * 1e-3) / 1e9
+    own_bytes, own_per_update = sweep_algorithmic_bytes(p, args.precision)
     traffic = counter_traffic(args.workload, args.precision, shape)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_sweep", "algorithmic_bytes_per_launch": alg_bytes,
+                "kernel": "k_sweep", "algorithmic_bytes_per_update": per_update,
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "kernel_stream_bytes_per_update": own_per_update,
+                "frac_kernel_stream_bytes": own_bytes / (ms_sweep * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "sweep_ms_mean": ms_sweep, "sweep_updates_per_s": ups / (ms_sweep * 1e-3)}
 
     converge = None
@@ -391,10 +455,11 @@ def main():
             rec = {"seconds": t_conv, "iterations": out["iterations"], "residual": out["residual"],
                    "energy_defect": out["energy_defect"]}
             if ref is not None:
-                c = ref["cells"]
+                c = ref["cells"] if "cells" in ref.files else slice(None)
                 rec["err_TL"] = float(np.max(np.abs(out["T_lattice"][c] - ref["T_lattice"])) / ref["scale_TL"])
                 rec["err_T"] = float(np.max(np.abs(out["T"][c] - ref["T"])) / ref["scale_T"])
                 rec["err_q"] = float(np.max(np.linalg.norm(out["q"][c] - ref["q"], axis=1)) / ref["scale_q"])
+                rec["cells_compared"] = int(len(ref["T_lattice"]))
             converge[prec] = rec
             log(f"bench: converge {prec}: {rec}")
         converge["speedup_mixed_vs_fp64"] = converge["fp64"]["seconds"] / converge["mixed"]["seconds"]
@@ -414,7 +479,6 @@ def main():
                    "updates_per_step": ups},
         "roofline": roofline, "cpu_baseline": cpu, "converge": converge,
         "phases_ms_per_step": phases, "ms_per_step_with_phase_events": dt_events / args.steps * 1e3,
-        "algorithmic_bytes_per_update": per_update,
         "sweep_shape": {k: st[k] for k in ("bands_per_block", "bands_per_lane", "block_size", "lds_slots",
                                            "spilled_values", "max_levels")},
     }

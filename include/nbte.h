@@ -69,8 +69,12 @@ typedef int32_t nbte_status;
 
 /* precision of the stored distribution */
 #define NBTE_PREC_FP64  0  /* distribution stored and swept in FP64 */
-#define NBTE_PREC_MIXED 1  /* distribution stored in FP32; sweep arithmetic, reductions,
-                              diffusion correction and residual in FP64 */
+#define NBTE_PREC_MIXED 1  /* distribution, sweep streams and boundary inflow stored in FP32
+                              and swept in FP32 arithmetic, in the deviation from the local
+                              equilibrium; the equilibrium-imbalance differences, the band x
+                              direction reductions, the diffusion correction and the residual
+                              in FP64; FP64 sweeps take over when the FP32 iteration stalls
+                              (nbte_solve_opts.refine) */
 
 typedef struct nbte_mesh nbte_mesh;
 typedef struct nbte_problem nbte_problem;
@@ -241,7 +245,15 @@ nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t);
 nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t);
 
 /* Device bytes a solve of this problem would hold at the given precision
- * (set_bands/set_quadrature must have been called). */
+ * (set_bands/set_quadrature must have been called).  Host arithmetic only.
+ * Errors: NBTE_ERR_STATE; NBTE_ERR_INVALID_ARG when the problem is too large
+ * for the sweep's 32-bit buffer offsets at that precision (any of: the
+ * real-valued sweep streams (3 + fan-in rows) x directions x cells x element
+ * size, a direction's distribution slice cells x bands x element size, or the
+ * boundary inflow faces x directions x bands x element size reaching 4 GiB;
+ * fan-in rows: 2 for triangles, 3 for quadrilaterals and tetrahedra, 5 for
+ * hexahedra), the same check nbte_prepare, nbte_problem_setup and
+ * nbte_batch_admit make before touching the device. */
 nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int64_t *bytes);
 
 /* Build and upload the iteration-independent setup of a problem for a
@@ -253,7 +265,9 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
  * their setups concurrently, one thread per problem (different problems share
  * no state).  Errors: those of nbte_prepare's setup (NBTE_ERR_STATE when
  * bands, quadrature or boundaries are missing or the problem is a batch
- * member, NBTE_ERR_MESH, NBTE_ERR_BOUNDARY, NBTE_ERR_ILL_POSED,
+ * member, NBTE_ERR_INVALID_ARG for a problem too large for the sweep's
+ * 32-bit offsets (see nbte_problem_footprint; checked before the device is
+ * touched), NBTE_ERR_MESH, NBTE_ERR_BOUNDARY, NBTE_ERR_ILL_POSED,
  * NBTE_ERR_DEVICE). */
 nbte_status nbte_problem_setup(nbte_problem *p, int32_t precision);
 
@@ -289,7 +303,12 @@ nbte_status nbte_batch_step(nbte_batch *b, int32_t n);
 
 /* Wait for the batch's stream; report up to cap members that have stopped
  * (converged, max_iter or diverged: see nbte_read_result) in done[0..*n_done)
- * and the number still running in *n_running (both nullable). */
+ * and the number still running in *n_running (both nullable).  A mixed member
+ * whose FP32 iteration stalled (refine on) continues with FP64 sweeps when
+ * the budget can hold its FP64 footprint next to everything it holds now
+ * (the switch briefly keeps both distributions); its charge becomes the FP64
+ * footprint.  Otherwise it stays stopped and is reported here as done, its
+ * residual above its tol. */
 nbte_status nbte_batch_poll(nbte_batch *b, nbte_problem **done, int32_t cap, int32_t *n_done,
                             int32_t *n_running);
 

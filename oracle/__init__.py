@@ -11,5 +11,5 @@ tests/test_oracle_*.py.
 """
 from .solver import (OracleError, Result, Setup, boundary_flows, boundary_inflow, diffusion_operator,  # noqa: F401
                      divergence,
-                     energy_defect, equilibrium, fourier_guess, moments, prepare, solve, source, transport,
+                     energy_defect, equilibrium, fourier_guess, moments, prepare, solve, source, threads, transport,
                      transport_systems)

@@ -60,12 +60,20 @@ def _lib():
         lib.oracle_sweep_system.argtypes = [ctypes.c_int64, ctypes.c_int32, i64, d, d, d,
                                             ctypes.c_double, ctypes.c_double, d, d, d, d]
         lib.oracle_sweep_system.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = [ctypes.c_int]
+        lib.oracle_threads.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
 
 def _p(a, t=ctypes.c_double):
     return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def threads(n=0):
+    """OpenMP threads of the per-system loop (n > 0 sets them); returns the
+    number the next transport() uses."""
+    return int(_lib().oracle_threads(int(n)))
 
 
 class OracleError(RuntimeError):

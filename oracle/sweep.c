@@ -137,3 +137,14 @@ void oracle_sweep_all(int64_t N, int32_t F, int32_t B, int32_t D, int64_t NBF,
                                         e + k * N, outflux + k * N);
     }
 }
+
+/*
+ * Threads of the OpenMP loop above: n > 0 sets them, every call returns the
+ * number the next loop will use (the CPU baseline reports it).
+ */
+#include <omp.h>
+int oracle_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}

@@ -86,7 +86,8 @@ nbte_status nbte_batch_admit(nbte_batch *b, nbte_problem *p, const double *Q_cel
         if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is already a batch member");
         if (!(o->tol > 0) || o->max_iter <= 0) throw Error(NBTE_ERR_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
         int64_t need = 0;
-        if (nbte_problem_footprint(p, o->precision, &need) != NBTE_OK) throw Error(NBTE_ERR_STATE, nbte_last_error());
+        const nbte_status fst = nbte_problem_footprint(p, o->precision, &need);
+        if (fst != NBTE_OK) throw Error(fst, nbte_last_error());
         if (b->budget > 0 && b->in_use + need > b->budget)
             throw Error(NBTE_ERR_OUT_OF_MEMORY, "batch budget exceeded: " + std::to_string(b->in_use) + " + " +
                                                     std::to_string(need) + " > " + std::to_string(b->budget) + " bytes");
@@ -117,17 +118,21 @@ nbte_status nbte_batch_poll(nbte_batch *b, nbte_problem **done, int32_t cap, int
     return guarded([&] {
         if (!b || cap < 0 || (cap > 0 && !done)) throw Error(NBTE_ERR_INVALID_ARG, "bad arguments");
         b->runner->collect();
-        // mixed members whose FP32 iteration stalled continue in FP64
+        // mixed members whose FP32 iteration stalled continue in FP64 when
+        // the budget holds the FP64 footprint beside the current one (the
+        // switch widens the distribution into a new buffer before the FP32
+        // one is freed); otherwise they stay stopped and are reported below
+        // as done, with the residual they reached
         bool changed = false;
         for (size_t k = 0; k < b->members.size(); ++k) {
             nbte_problem *p = b->members[k];
-            if (p->hs.done != NBTE_DONE_STALLED) continue;
+            if (p->hs.done != NBTE_DONE_STALLED || !p->refine_possible()) continue;
+            int64_t need = 0;
+            if (nbte_problem_footprint(p, NBTE_PREC_FP64, &need) != NBTE_OK) continue;
+            if (b->budget > 0 && b->in_use + need > b->budget) continue;
             p->promote();
-            int64_t need = 0;   // charge the FP64 footprint from now on
-            if (nbte_problem_footprint(p, NBTE_PREC_FP64, &need) == NBTE_OK) {
-                b->in_use += need - b->charged[k];
-                b->charged[k] = need;
-            }
+            b->in_use += need - b->charged[k];   // the FP64 footprint from now on
+            b->charged[k] = need;
             changed = true;
         }
         if (changed) b->runner->set_members(b->members);

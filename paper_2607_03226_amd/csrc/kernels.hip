@@ -5,8 +5,10 @@
 // in equilibrium at the lattice temperature the sweep used (Methods, Eq. (11)
 // gives the equilibrium C T_L / W).  Layout g[(i*N + c)*B + l]: the bands of
 // one (direction, cell) are contiguous, so the lanes that share a cell read
-// and write one contiguous run.  Arithmetic is FP64 everywhere; g is stored in
-// FP64 or FP32.
+// and write one contiguous run.  g is stored in FP64 or FP32; the sweep runs
+// in the storage type's arithmetic (FP32 for the mixed path), while the
+// equilibrium-imbalance differences, the band x direction reductions, the
+// diffusion correction and the residual accumulate in FP64.
 //
 // Every per-iteration kernel takes the descriptor array of the solves it
 // serves and a work table (one WorkItem per workgroup).  A solve whose state

@@ -176,6 +176,17 @@ struct nbte_problem {
     ~nbte_problem();
 
     Shape resolve_shape() const;
+    // throws NBTE_ERR_INVALID_ARG when a solve at this precision would not
+    // fit the sweep's 32-bit buffer offsets (host check, no device access)
+    void check_addressable(int prec) const;
+    bool addressable(int prec) const {
+        try {
+            check_addressable(prec);
+            return true;
+        } catch (const nbte::Error &) {
+            return false;
+        }
+    }
     int cg_max_iter() const { return tuning.cg_max_iter > 0 ? tuning.cg_max_iter : 8; }
     double cg_rtol() const { return tuning.cg_rtol > 0 ? tuning.cg_rtol : 1e-3; }
     bool fp32() const { return precision == NBTE_PREC_MIXED; }
@@ -199,6 +210,7 @@ struct nbte_problem {
     // the distribution and the iteration count)
     void promote();
     bool refine = true;      // mixed: switch to FP64 when the FP32 iteration stalls
+    bool refine_possible() const { return fp32() && addressable(NBTE_PREC_FP64); }
     int refined_at = -1;
     int stop_mode = 0;
     double stop_tol = 0.0;

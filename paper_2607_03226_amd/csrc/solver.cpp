@@ -163,6 +163,37 @@ nbte_problem::Shape nbte_problem::resolve_shape() const {
     return sh;
 }
 
+// The sweep addresses its streams, the boundary inflow and a direction's
+// slice of the distribution through buffer descriptors and 32-bit byte
+// offsets (row offsets in scalar registers, lane offsets in vector
+// registers), so every one of those extents must stay below 4 GiB; stream
+// positions are int32.  Checked on the sizes alone, before anything is
+// built, with the fan-in bound of the cell type (the streams hold 2, 3 or 5
+// reference rows).
+void nbte_problem::check_addressable(int prec) const {
+    if (!have_bands || !have_quad) return;
+    const int64_t N = mesh->N, F = mesh->F, B = bands.B, D = quad.D, NBF = mesh->NBF;
+    const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
+    const int64_t mi = F - 1 <= 2 ? 2 : (F - 1 == 3 ? 3 : 5);
+    const int64_t DN = D * N;
+    const int64_t lim = (int64_t)1 << 32;
+    struct Extent {
+        const char *what;
+        int64_t bytes;
+    } ext[] = {{"real-valued sweep streams", (3 + mi) * DN * es},
+               {"integer sweep streams", (2 + mi) * DN * 4},
+               {"one direction's distribution slice", N * B * es},
+               {"boundary inflow rows", NBF * D * B * es}};
+    for (const Extent &e : ext)
+        if (e.bytes >= lim)
+            throw Error(NBTE_ERR_INVALID_ARG,
+                        std::string("problem too large for the sweep's 32-bit buffer offsets: ") + e.what + " take " +
+                            std::to_string(e.bytes) + " bytes (limit 4 GiB) at " +
+                            (prec == NBTE_PREC_MIXED ? "mixed" : "FP64") + " precision");
+    if (DN >= (int64_t)INT32_MAX)
+        throw Error(NBTE_ERR_INVALID_ARG, "problem too large: directions x cells must stay below 2^31");
+}
+
 // Host-side setup products (no device access): schedules, sweep program,
 // boundary plan, diffusion operator.  Throws the validation errors of the ABI.
 void nbte_problem::build_host() {
@@ -491,6 +522,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
             t0[c] = o.T_init[c] - T_ref;
         }
     }
+    check_addressable(o.precision);
     prepared = false;
     precision = o.precision;   // the launch shape's LDS budget depends on it
     ensure_setup();
@@ -573,7 +605,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
 }
 
 void nbte_problem::set_controls(int stop, double tol, int max_iter) {
-    const int patience = (stop && fp32() && refine) ? 64 : 0;
+    const int patience = (stop && refine && refine_possible()) ? 64 : 0;
     launch_set_controls(d_state.as<SolveState>(), stop, tol, max_iter, patience, stream);
     NBTE_HIP(hipGetLastError());
     NBTE_HIP(hipStreamSynchronize(stream));
@@ -585,6 +617,13 @@ void nbte_problem::set_controls(int stop, double tol, int max_iter) {
 
 void nbte_problem::promote() {
     if (!fp32()) return;
+    try {
+        check_addressable(NBTE_PREC_FP64);
+    } catch (const Error &e) {
+        throw Error(NBTE_ERR_NOT_CONVERGED, std::string("the FP32 iteration stalled at residual ") +
+                                                std::to_string(hs.residual) + " and FP64 refinement is not possible: " +
+                                                e.what());
+    }
     NBTE_HIP(hipStreamSynchronize(stream));
     const int64_t n = mesh->N * (int64_t)bands.B * quad.D;
     DevBuf old_g;   // the FP32 distribution, widened into the new FP64 one below
@@ -865,6 +904,7 @@ nbte_status nbte_solve_steady(nbte_problem *p, const double *Q_cell, const nbte_
             p->solo->run(every);
             p->solo->collect();
             if (p->hs.done == NBTE_DONE_STALLED) {
+                if (!p->refine_possible()) break;   // stays stalled: reported as not converged below
                 p->promote();   // FP32 floor reached: continue in FP64
                 continue;
             }
@@ -873,6 +913,10 @@ nbte_status nbte_solve_steady(nbte_problem *p, const double *Q_cell, const nbte_
         p->stats.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (out) p->read_result(out);
         if (p->hs.done == NBTE_DONE_DIVERGED) return fail(NBTE_ERR_DIVERGED, "iteration diverged (non-finite temperature)");
+        if (p->hs.done == NBTE_DONE_STALLED)
+            return fail(NBTE_ERR_NOT_CONVERGED, "the FP32 iteration stalled at residual " +
+                                                    std::to_string(p->hs.residual) +
+                                                    "; FP64 refinement would exceed the sweep's 32-bit offsets");
         if (p->hs.done != NBTE_DONE_CONVERGED)
             return fail(NBTE_ERR_NOT_CONVERGED, "not converged after " + std::to_string(p->hs.iterations) +
                                                     " iterations (residual " + std::to_string(p->hs.residual) + ")");
@@ -960,6 +1004,7 @@ nbte_status nbte_problem_setup(nbte_problem *p, int32_t precision) {
         if (!p) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
         if (precision != NBTE_PREC_FP64 && precision != NBTE_PREC_MIXED) throw Error(NBTE_ERR_INVALID_ARG, "bad precision");
         if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member; remove it from the batch first");
+        p->check_addressable(precision);
         require_gfx950();
         p->prepared = false;
         p->precision = precision;   // the launch shape's LDS budget depends on it
@@ -974,6 +1019,8 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
     return guarded([&] {
         if (!p || !bytes) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
         if (!p->have_bands || !p->have_quad) throw Error(NBTE_ERR_STATE, "bands and quadrature must be set");
+        if (precision != NBTE_PREC_FP64 && precision != NBTE_PREC_MIXED) throw Error(NBTE_ERR_INVALID_ARG, "bad precision");
+        p->check_addressable(precision);
         const Mesh &m = *p->mesh;
         const int64_t N = m.N, F = m.F, D = p->quad.D, NBF = m.NBF;
         const int64_t mi = F - 1 <= 2 ? 2 : (F - 1 == 3 ? 3 : 5);   // reference rows (fan-in class)

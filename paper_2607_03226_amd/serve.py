@@ -8,7 +8,8 @@ served).  Every step advances all running solves together (one launch per
 kernel for all of them, replayed from a HIP graph); a solve leaves the batch
 as soon as the device stops it at its tolerance, and its result is read while
 the others keep running.  New requests are set up and admitted while the
-enqueued step runs on the GPU.
+enqueued step runs on the GPU; their device setup starts only once their
+footprint fits the budget beside the running solves (see serve()).
 
 serve() returns per-request latency (finish - arrival), p50/p99 and the
 throughput in solves/s.
@@ -54,10 +55,10 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
 
     requests  list of problem descriptions (see nbte.build_problem)
     arrivals  arrival times in seconds from the start (non-decreasing)
-    budget    device bytes the running solves may hold together
+    budget    device bytes the running solves and the set-up waiting requests
+              may hold together (0: no limit)
     tuning    None, "auto" (autotuner cache) or a dict of launch-shape settings
-    lookahead waiting requests whose setup runs ahead on host threads (their
-              setup holds device memory outside the admission budget)
+    lookahead waiting requests whose setup runs ahead on host threads
     Returns (list of Served, summary dict).
     """
     n = len(requests)
@@ -68,19 +69,24 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
     next_arrival = 0
     done_count = 0
     t0 = clock()
+    peak = [0]                  # most device bytes held by members and set-up waiting requests
 
     def now():
         return clock() - t0
 
-    # setup of waiting requests (mesh, tables, schedules, streams: the
-    # iteration-independent part), run on host threads for the first
-    # `lookahead` requests in the queue while the GPU steps the batch; a
-    # request's setup is kept across admission attempts
+    # Setup of waiting requests, on host threads for the first `lookahead`
+    # requests in the queue while the GPU steps the batch.  The host part
+    # (mesh, tables, the footprint query) holds no device memory; the device
+    # part (nbte_problem_setup: schedules, streams, state) starts only once
+    # the request's footprint is reserved next to the batch's members and the
+    # other reservations, in queue order, so members plus set-up requests
+    # never hold more than the budget.  A reservation becomes the member's
+    # charge at admission.
     from concurrent.futures import ThreadPoolExecutor
     pool = ThreadPoolExecutor(max_workers=max(1, lookahead))
-    built = {}
+    host_built, dev_built, reserved = {}, {}, {}
 
-    def setup(j):
+    def host_part(j):
         p = requests[j]
         mesh, h = N.build_problem(p)
         if tuning == "auto":
@@ -90,22 +96,46 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
                 N.nbte_set_tuning(h, **shape)
         elif tuning:
             N.nbte_set_tuning(h, **tuning)
+        return mesh, h, N.nbte_problem_footprint(h, precision)
+
+    def dev_part(j):
+        mesh, h, _ = host_built[j].result()
         N.nbte_problem_setup(h, precision)
         return mesh, h
 
+    def held():
+        return N.nbte_batch_get_info(batch)["bytes_in_use"] + sum(reserved.values())
+
     def start_setups():
-        for j in list(queue)[:max(1, lookahead)]:
-            if j not in built:
-                built[j] = pool.submit(setup, j)
+        ahead = list(queue)[:max(1, lookahead)]
+        for j in ahead:
+            if j not in host_built:
+                host_built[j] = pool.submit(host_part, j)
+        for j in ahead:                       # reservations in queue order
+            if j in dev_built:
+                continue
+            if not host_built[j].done():
+                break
+            foot = host_built[j].result()[2]
+            if budget_bytes > 0 and held() + foot > budget_bytes:
+                break
+            reserved[j] = foot
+            peak[0] = max(peak[0], held())
+            dev_built[j] = pool.submit(dev_part, j)
 
     def admit_waiting():
-        start_setups()
         while queue:
+            start_setups()
             j = queue[0]
             p = requests[j]
-            if j not in built:
-                built[j] = pool.submit(setup, j)
-            mesh, h = built[j].result()
+            if j not in dev_built:
+                if handles:
+                    return            # running solves free memory, or the host part is still running
+                host_built[j].result()
+                start_setups()
+                if j not in dev_built:
+                    raise RuntimeError(f"request {j} ({p.name}) does not fit the budget even alone")
+            mesh, h = dev_built[j].result()
             opts = N.make_opts(scheme=p.scheme, precision=precision, T_ref=p.T_ref, tol=tol, max_iter=max_iter)
             try:
                 N.nbte_batch_admit(batch, h, p.Q, opts)
@@ -116,8 +146,8 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
                     raise RuntimeError(f"request {j} ({p.name}) does not fit the budget even alone") from e
                 return              # wait for running solves to leave
             queue.popleft()
-            del built[j]
-            start_setups()
+            del reserved[j], host_built[j], dev_built[j]
+            peak[0] = max(peak[0], held())
             handles[h.handle.value] = (j, mesh, h)
             served[j].admitted = now()
             if log:
@@ -159,7 +189,7 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
     summary = {"requests": n, "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
                "mean_s": float(np.mean(lat)), "solves_per_s": n / span if span > 0 else float("inf"),
                "span_s": span, "all_converged": all(s.converged for s in served),
-               "budget_bytes": int(budget_bytes)}
+               "budget_bytes": int(budget_bytes), "peak_bytes_held": int(peak[0])}
     return served, summary
 
 

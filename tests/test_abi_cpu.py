@@ -236,3 +236,80 @@ def test_counter_traffic_needs_same_source_and_shape(tmp_path, monkeypatch):
     assert bench.counter_traffic("configX", "fp64", shape) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "def")
     assert bench.counter_traffic("configX", "mixed", shape) is None
+
+
+def test_cyclic_upwind_graph_is_reported_as_a_mesh_error():
+    """A non-convex (dart) cell closes a cycle in the upwind graph of some
+    directions (the mesh is built in the oracle pins, where the oracle's
+    direct-solve fallback is checked): the library's level schedule cannot
+    order it and says so."""
+    from tests.test_oracle_pins import dart_mesh
+    xyz, cells, bf, tags = dart_mesh()
+    mesh = N.nbte_mesh_create(2, xyz, "quad4", cells, bf, tags)
+    h = N.nbte_problem_create(mesh)
+    s, w = inplane_quadrature(8)
+    # only the acyclic directions (22.5, 67.5, 202.5, 247.5 degrees): fine
+    N.nbte_set_quadrature(h, s[[0, 1, 4, 5]], w[[0, 1, 4, 5]])
+    for i in range(4):
+        perm, lvl = N.nbte_get_schedule(h, i)
+        assert sorted(perm) == [0, 1, 2]
+    N.nbte_set_quadrature(h, s, w)
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_get_schedule(h, 0)
+    assert e.value.status == N.ERR_MESH and "cycle" in e.value.message
+
+
+def test_problem_too_large_for_32bit_offsets_is_refused_before_the_device():
+    """10,000 quads x 10,000 directions: the FP64 sweep streams (3 + 3 rows
+    of 8 bytes per direction and cell) pass 4 GiB, the FP32 ones (4 bytes)
+    do not.  The footprint query and the setup call refuse the FP64 solve
+    with INVALID_ARG before any device work; the mixed one gets through to
+    the device check."""
+    xs = np.linspace(0, 1e-6, 101)
+    xyz, cells, bf, tags = M.structured_quad(xs, xs)
+    mesh = N.nbte_mesh_create(2, xyz, "quad4", cells, bf, tags)
+    h = N.nbte_problem_create(mesh)
+    N.nbte_set_bands(h, [1e6], [5000.0], [1e-11])
+    s, w = inplane_quadrature(10000)
+    N.nbte_set_quadrature(h, s, w)
+    N.nbte_set_boundaries(h, [(1, "thermalizing", 301.0, 0), (2, "thermalizing", 299.0, 0), (3, "specular", 0, 0),
+                              (4, "specular", 0, 0)])
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_problem_footprint(h, "fp64")
+    assert e.value.status == N.ERR_INVALID_ARG and "32-bit" in e.value.message
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_problem_setup(h, "fp64")
+    assert e.value.status == N.ERR_INVALID_ARG
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_prepare(h, None, N.make_opts(precision="fp64"))
+    assert e.value.status == N.ERR_INVALID_ARG
+    assert N.nbte_problem_footprint(h, "mixed") > 10000 * 10000 * 4
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(N.NbteError) as e:
+            N.nbte_problem_setup(h, "mixed")
+        assert e.value.status == N.ERR_DEVICE
+
+
+def test_counter_summary_scales_by_the_copy_probe(tmp_path):
+    """The counter summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
+    by what the same counters read for a device copy of known size."""
+    import bench
+
+    def csv(d, rows):
+        d.mkdir()
+        lines = ["Kernel_Name,Grid_Size,Counter_Name,Counter_Value"]
+        lines += [f"{k},{g},{c},{v}" for k, g, c, v in rows]
+        (d / "run_counter_collection.csv").write_text("\n".join(lines) + "\n")
+
+    probe = 1 << 30
+    csv(tmp_path / "f", [("k_sweep<float>", 100, "FETCH_SIZE", 1000.0)] * 3)
+    csv(tmp_path / "w", [("k_sweep<float>", 100, "WRITE_SIZE", 3000.0)] * 3)
+    # the copy reads and writes 1 GiB; the counters see 1.25x and 0.5x that
+    csv(tmp_path / "cf", [("copyBuffer", 10, "FETCH_SIZE", 1.0), ("copyBuffer", 99, "FETCH_SIZE", 1.25 * probe / 1024)])
+    csv(tmp_path / "cw", [("copyBuffer", 99, "WRITE_SIZE", 0.5 * probe / 1024)])
+    out = bench.counter_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"),
+                                probe)
+    assert out["fetch_scale"] == pytest.approx(0.8) and out["write_scale"] == pytest.approx(2.0)
+    assert out["traffic_bytes_per_launch"] == pytest.approx(1000 * 1024 * 0.8 + 3000 * 1024 * 2.0)
+    assert out["raw_bytes_per_launch"] == pytest.approx(4000 * 1024)

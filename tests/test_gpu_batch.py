@@ -3,14 +3,34 @@
 A member of a batch runs the same kernels with the same per-solve reduction
 order as a stand-alone solve, so its result must be bitwise equal to the
 stand-alone result with the same options, whatever else is in the batch and
-whenever it was admitted.
+whenever it was admitted.  Every member is also compared with the FP64
+oracle's solution of its own problem (bars as in the parity tests: 1e-9 for
+the FP64 path, 1e-6 for the mixed path, relative to the deviation scale).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
+import oracle
 from workloads import configs as C
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _oracle_errors(out, T_L, T, q, scale_TL, scale_T, scale_q, cells=slice(None)):
+    return {"err_TL": float(np.max(np.abs(out["T_lattice"][cells] - T_L)) / scale_TL),
+            "err_T": float(np.max(np.abs(out["T"][cells] - T)) / scale_T),
+            "err_q": float(np.max(np.linalg.norm(out["q"][cells] - q, axis=1)) / scale_q)}
+
+
+def _vs_oracle(out, p):
+    r = oracle.solve(p, tol=1e-13, max_iter=20000, defect_tol=1e-11)
+    return _oracle_errors(out, r.T_lattice, r.T, r.q, np.max(np.abs(r.T_lattice - p.T_ref)),
+                          np.max(np.abs(r.T - p.T_ref)), np.max(np.linalg.norm(r.q, axis=1)))
 
 
 def _N():
@@ -64,8 +84,48 @@ def test_batch_members_equal_their_standalone_solves(precision, tol):
                                                        tol=tol, max_iter=4000))
         handles.append(h)
     res = _drain(N, batch, handles)
-    for h, a in zip(handles, alone):
+    bar = 1e-9 if precision == "fp64" else 1e-6
+    for h, a, p in zip(handles, alone, probs):
         _same(res[h.handle.value], a)
+        err = _vs_oracle(res[h.handle.value], p)
+        print(p.name, precision, json.dumps(err), flush=True)
+        assert max(err.values()) < bar, (p.name, err)
+
+
+def test_full_size_porous_batch_against_the_oracle():
+    """The 64 porous films of the batch workload (2k-40k triangles, 8 bands,
+    32 directions, Kn 0.1-10), iterated together in mixed precision with the
+    tuned shapes, each compared with the stored oracle solution of its film
+    on a seeded sample of cells."""
+    N = _N()
+    path = os.path.join(GOLDEN, "config4_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle solutions of the porous films (tests/golden/make_reference.py config4)")
+    z = np.load(path)
+    from paper_2607_03226_amd import tune
+    probs = C.config4()
+    assert int(z["members"]) == len(probs)
+    batch = N.nbte_batch_create()
+    handles, keep = [], []
+    for p in probs:
+        mesh, h = N.build_problem(p)
+        shape = tune.lookup(p, "mixed")
+        if shape:
+            N.nbte_set_tuning(h, **shape)
+        keep.append(mesh)
+        N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision="mixed", T_ref=p.T_ref, tol=1e-8,
+                                                       max_iter=20000))
+        handles.append(h)
+    res = _drain(N, batch, handles, limit=40000)
+    worst = 0.0
+    for j, (h, p) in enumerate(zip(handles, probs)):
+        assert str(z[f"{j}/name"]) == p.name
+        err = _oracle_errors(res[h.handle.value], z[f"{j}/T_lattice"], z[f"{j}/T"], z[f"{j}/q"],
+                             float(z[f"{j}/scale_TL"]), float(z[f"{j}/scale_T"]), float(z[f"{j}/scale_q"]),
+                             cells=z[f"{j}/cells"])
+        worst = max(worst, max(err.values()))
+        assert max(err.values()) < 1e-6, (p.name, err)
+    print("config4 full batch: worst error", worst, flush=True)
 
 
 def test_continuous_admission_mixed_precisions_and_schemes():
@@ -124,6 +184,9 @@ def test_admission_budget():
     assert e.value.status == N.ERR_OUT_OF_MEMORY
     info = N.nbte_batch_get_info(batch)
     assert info["members"] == 2 and info["bytes_in_use"] == need[0] + need[1]
+    # the footprint the budget charges covers what a member really holds
+    for h, f in zip(handles[:2], need[:2]):
+        assert 0 < N.nbte_get_stats(h)["device_bytes"] <= f
     # a member cannot be driven on its own
     with pytest.raises(N.NbteError) as e:
         N.nbte_iterate(handles[0], 1)

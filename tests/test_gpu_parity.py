@@ -4,6 +4,10 @@ Errors are deviation-relative and stated per result:
   err_TL = max|T_L,gpu - T_L,ora| / max|T_L,ora - T_ref|   (same for T)
   err_q  = max ||q_gpu - q_ora|| / max ||q_ora||
 Bars: plain FP64 path 1e-9 (iteration-tolerance limited), mixed path 1e-6.
+Every case runs with the library's default launch shape and, where the
+autotuner has an entry for it, with the tuned shape the benchmark times.
+The full-size workloads are compared on every cell with the stored oracle
+solutions (tests/golden/make_reference.py).
 """
 import json
 import os
@@ -67,8 +71,11 @@ def _oracle(key, p):
         if os.path.exists(path):
             z = np.load(path)
             assert str(z["name"]) == p.name
-            ref = _Ref(z["cells"], z["T_lattice"], z["T"], z["q"], float(z["scale_TL"]), float(z["scale_T"]),
+            cells = z["cells"] if "cells" in z.files else np.arange(p.n_cells)
+            ref = _Ref(cells, z["T_lattice"], z["T"], z["q"], float(z["scale_TL"]), float(z["scale_T"]),
                        float(z["scale_q"]), int(z["iterations"]))
+        elif key in STORED_ONLY:
+            pytest.skip(f"no stored oracle solution for {key} (tests/golden/make_reference.py {key})")
         else:
             r = oracle.solve(p, tol=1e-13, max_iter=20000, defect_tol=1e-11)
             ref = _Ref(np.arange(p.n_cells), r.T_lattice, r.T, r.q, np.max(np.abs(r.T_lattice - p.T_ref)),
@@ -76,6 +83,9 @@ def _oracle(key, p):
         _ORACLE_CACHE[key] = ref
     return _ORACLE_CACHE[key]
 
+
+# full-size cases whose oracle solution takes minutes to hours: stored only
+STORED_ONLY = {"config2", "config3", "serving_5008", "serving_5027"}
 
 CASES = [
     ("config1", C.config1, "sequential"),
@@ -91,25 +101,46 @@ CASES = [
     # requests of the serving stream (reduced cell counts)
     ("serving_5001", lambda: C.serving_request(5001, size_scale=0.03), "synthetic"),
     ("serving_5007", lambda: C.serving_request(5007, size_scale=0.03), "synthetic"),
+    # full-size 3D requests of the serving stream: FinFET-like tets and a box
+    ("serving_5008", lambda: C.serving_request(5008), "synthetic"),
+    ("serving_5027", lambda: C.serving_request(5027), "synthetic"),
 ]
 
 
+def _tuned(p, precision):
+    from paper_2607_03226_amd import tune
+    return tune.lookup(p, precision)
+
+
+@pytest.mark.parametrize("tuning", ["default", "auto"])
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-9), ("mixed", 1e-6)])
 @pytest.mark.parametrize("name,maker,scheme", CASES)
-def test_converged_parity(name, maker, scheme, precision, bar):
+def test_converged_parity(name, maker, scheme, precision, bar, tuning):
     N = _N()
     p = maker()
+    if tuning == "auto" and not _tuned(p, precision):
+        pytest.skip("the autotuner has no entry for this workload (the default shape is the one run)")
     ref = _oracle(name, p)
     # FP32 storage leaves a residual floor near 1e-8, so the mixed path stops at 1e-8
     tol = 1e-12 if precision == "fp64" else 1e-8
-    out = N.solve(p, precision=precision, scheme=scheme, tol=tol, max_iter=5000, allow_not_converged=True)
+    out = N.solve(p, precision=precision, scheme=scheme, tol=tol, max_iter=5000, allow_not_converged=True,
+                  tuning="auto" if tuning == "auto" else None)
+    st = N.nbte_get_stats(out["_handles"][1])
     rec = _errors(out, ref, p.T_ref)
     rec.update(iterations=out["iterations"], residual=out["residual"], energy_defect=out["energy_defect"],
-               oracle_iterations=ref.iterations, precision=precision)
-    _log(f"{name}/{precision}", rec)
+               oracle_iterations=ref.iterations, precision=precision, cells_compared=len(ref.cells),
+               shape={k: st[k] for k in ("bands_per_block", "bands_per_lane", "block_size", "lds_slots",
+                                         "spilled_values")})
+    _log(f"{name}/{precision}/{tuning}", rec)
     assert rec["err_TL"] < bar and rec["err_T"] < bar and rec["err_q"] < bar, rec
     if precision == "fp64":
         assert out["energy_defect"] < 1e-9
+    else:
+        # the energy defect equals sum_c V_c beta (theta_seq - theta) / scale
+        # (collision-divergence identity), i.e. it measures the last update,
+        # which the stop rule bounds at 1e-8 of the deviation scale; the FP32
+        # storage of the wall values adds a relative 2^-24 per term
+        assert out["energy_defect"] < MIXED_DEFECT_BAR, rec
 
 
 @pytest.mark.parametrize("scheme", ["sequential", "synthetic_literal"])
@@ -123,7 +154,10 @@ def test_other_schemes_reach_the_same_fixed_point(scheme):
     assert max(rec["err_TL"], rec["err_T"], rec["err_q"]) < 1e-8, rec
 
 
-def _one_sweep_check(p, precision, systems, bar):
+MIXED_DEFECT_BAR = 1e-5
+
+
+def _one_sweep_check(p, precision, systems, bar, tuning=None):
     """One iteration from a given T_init: the distribution of sampled
     (band, direction) systems against the oracle's exact sweeps."""
     N = _N()
@@ -133,6 +167,8 @@ def _one_sweep_check(p, precision, systems, bar):
     span = np.ptp(xc, axis=0) + 1e-30
     theta0 = np.sin(2.1 * xc[:, 0] / span[0]) + 0.5 * np.cos(3.3 * xc[:, 1] / span[1]) + 0.2 * rng.standard_normal(su.g.N)
     mesh, h = N.build_problem(p)
+    if tuning:
+        N.nbte_set_tuning(h, **tuning)
     opts = N.make_opts(scheme="sequential", precision=precision, T_ref=p.T_ref, T_init=p.T_ref + theta0)
     N.nbte_prepare(h, p.Q, opts)
     N.nbte_iterate(h, 1)
@@ -150,21 +186,29 @@ def _one_sweep_check(p, precision, systems, bar):
     return worst, N.nbte_get_stats(h)["max_levels"]
 
 
+@pytest.mark.parametrize("tuning", ["default", "auto"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("which", ["config2", "config3"])
-def test_one_sweep_full_size_sampled_systems(which, precision):
+def test_one_sweep_full_size_sampled_systems(which, precision, tuning):
     """One sweep from a rough theta (smooth field plus noise).  FP64: 1e-12.
     Mixed: the sweep runs in FP32; each upwind update rounds at most seven
-    times (three products of the gain, numerator, denominator, reciprocal and
-    product) and passes its error on with a weight below one, so along a
-    path of L levels the relative error stays below 7 L 2^-24."""
+    times (products of the gain, numerator, denominator, reciprocal and
+    quotient), each rounding within 2^-24 relative, and passes its error on
+    with a weight below one.  The worst case along a path of L levels is
+    7 L 2^-24; independent roundings add like a random walk instead, with an
+    RMS near 7 2^-24 sqrt(L / 3), and the bar is 10 2^-24 sqrt(L), about 2.5
+    times that RMS (config 2: L = 70, config 3: L = 251)."""
     p = C.config2() if which == "config2" else C.config3()
+    shape = _tuned(p, precision) if tuning == "auto" else None
+    if tuning == "auto" and not shape:
+        pytest.skip("no tuned shape for this workload")
     rng = np.random.default_rng(7)
     systems = [(int(rng.integers(p.n_bands)), int(rng.integers(p.n_dirs))) for _ in range(12)]
     systems += [(0, 0), (p.n_bands - 1, p.n_dirs - 1)]
-    worst, levels = _one_sweep_check(p, precision, systems, None)
-    bar = 1e-12 if precision == "fp64" else 7 * levels * 2.0 ** -24
-    _log(f"{which}/one_sweep/{precision}", {"err_e": worst, "systems": len(systems), "bar": bar})
+    worst, levels = _one_sweep_check(p, precision, systems, None, tuning=shape)
+    bar = 1e-12 if precision == "fp64" else 10 * np.sqrt(levels) * 2.0 ** -24
+    _log(f"{which}/one_sweep/{precision}/{tuning}", {"err_e": worst, "systems": len(systems), "bar": bar,
+                                                     "levels": levels})
     assert worst < bar
 
 
@@ -175,19 +219,28 @@ SHAPES = [  # (bands_per_block, bands_per_lane, block_size, lds_bytes)
 ]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("bpb,bpl,block,lds", SHAPES)
-def test_sweep_launch_shapes_agree(bpb, bpl, block, lds):
-    """Every launch shape computes the same solution (B = 5: ragged band blocks).
-    Staged values skip one round trip through the stored g, so shapes agree to
-    rounding, not bitwise."""
+def test_sweep_launch_shapes_agree(bpb, bpl, block, lds, precision):
+    """Every launch shape computes the same solution (B = 5 and 6: ragged band
+    blocks).  FP64: staged values skip one round trip through the stored g,
+    so shapes agree to rounding, not bitwise.  Mixed: every shape's FP32
+    sweeps reach the oracle's solution within the mixed bar."""
     N = _N()
-    for maker in (C.config2_small, C.config3_small):
+    tuning = {"bands_per_block": bpb, "bands_per_lane": bpl, "block_size": block, "lds_bytes": lds}
+    for name, maker in (("config2_small", C.config2_small), ("config3_small", C.config3_small)):
         p = maker()
-        base = N.solve(p, precision="fp64", scheme="synthetic", tol=1e-12, max_iter=3000)
-        out = N.solve(p, precision="fp64", scheme="synthetic", tol=1e-12, max_iter=3000,
-                      tuning={"bands_per_block": bpb, "bands_per_lane": bpl, "block_size": block, "lds_bytes": lds})
-        dev = np.max(np.abs(base["T_lattice"] - p.T_ref))
-        assert np.max(np.abs(out["T_lattice"] - base["T_lattice"])) / dev < 1e-11
+        if precision == "fp64":
+            base = N.solve(p, precision="fp64", scheme="synthetic", tol=1e-12, max_iter=3000)
+            out = N.solve(p, precision="fp64", scheme="synthetic", tol=1e-12, max_iter=3000, tuning=tuning)
+            dev = np.max(np.abs(base["T_lattice"] - p.T_ref))
+            assert np.max(np.abs(out["T_lattice"] - base["T_lattice"])) / dev < 1e-11
+        else:
+            ref = _oracle(name, p)
+            out = N.solve(p, precision="mixed", scheme="synthetic", tol=1e-8, max_iter=3000, tuning=tuning)
+            rec = _errors(out, ref, p.T_ref)
+            _log(f"{name}/shape{bpb}-{bpl}-{block}-{lds}/mixed", rec)
+            assert max(rec["err_TL"], rec["err_T"], rec["err_q"]) < 1e-6, rec
 
 
 def test_deterministic_bitwise():

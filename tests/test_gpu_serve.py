@@ -30,6 +30,8 @@ def test_serving_results_equal_alone():
     served, summary = serve.serve(reqs, arrivals, budget, precision="mixed", tol=1e-8, max_iter=5000, step=4,
                                   keep_results=True)
     assert summary["all_converged"]
+    # members and the waiting requests set up ahead never held more than the budget
+    assert 0 < summary["peak_bytes_held"] <= budget
     assert summary["p50_s"] <= summary["p99_s"]
     assert all(s.admitted >= s.arrival and s.finished > s.admitted for s in served)
     # the mix really overlapped: some request was admitted before an earlier one finished

@@ -404,3 +404,124 @@ def test_P7_weight_scaling_renumbering_and_symmetry():
     th = (r1.T_lattice - 300.0).reshape(16, 16)
     assert np.max(np.abs(th + th[:, ::-1])) < 1e-12
     assert np.max(np.abs(th - th[:1])) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# cyclic upwind graphs: a non-convex (dart) quad makes the upwind graph of
+# some directions cyclic; the oracle then solves that system with a sparse
+# direct solve, which must still equal the dense solve (P1) and give the
+# coupled fixed point (P2)
+# ----------------------------------------------------------------------------
+
+def dart_mesh(R=50 * NM):
+    """Three quads around the point P = 0: two convex sectors between the rays
+    at 10, 60 and 110 degrees, and a dart that closes the fan through the
+    lower half-plane (reflex angle at P).  The three interior edges are rays
+    from P inside one half-plane, so for every in-plane direction at an
+    angle in (110, 190) degrees (and its opposite) each cell is upwind of the
+    next one counter-clockwise: the cycle 0 -> 1 -> 2 -> 0.  The dart is
+    numbered last so that every interior edge takes its orientation from a
+    convex cell."""
+    ang = np.radians([10.0, 60.0, 110.0])
+    V = R * np.c_[np.cos(ang), np.sin(ang)]
+    Wo = 1.5 * R * np.c_[np.cos(np.radians([35.0, 85.0])), np.sin(np.radians([35.0, 85.0]))]
+    xyz = np.vstack([[0.0, 0.0], V, Wo, [0.0, -2.0 * R]])          # P=0, V1..V3 = 1..3, W1 = 4, W2 = 5, W3 = 6
+    cells = np.array([[0, 1, 4, 2], [0, 2, 5, 3], [0, 3, 6, 1]], np.int64)
+    bf = np.array([[1, 4], [4, 2], [2, 5], [5, 3], [3, 6], [6, 1]], np.int64)
+    tags = np.array([2, 2, 2, 2, 1, 2], np.int32)
+    return xyz, cells, bf, tags
+
+
+def tiny_dart(rng, B=2, D=8):
+    xyz, cells, bf, tags = dart_mesh()
+    s, w = inplane_quadrature(D)
+    C_, v, tau = _bands(B, rng)
+    return Problem("dart", 2, xyz, "quad4", cells, bf, tags,
+                   [Boundary(1, "thermalizing", 301.0), Boundary(2, "diffuse")],
+                   C_, v, tau, s, w, rng.uniform(0, 1e17, len(cells)))
+
+
+def test_dart_mesh_has_cyclic_directions_and_the_oracle_solves_them_exactly():
+    from oracle.solver import _lib, _p
+    import ctypes
+    rng = np.random.default_rng(17)
+    p = tiny_dart(rng)
+    su = oracle.prepare(p)
+    g = su.g
+    assert np.all(g.V > 0)
+    assert np.max(np.abs(g.S.sum(axis=1))) < 1e-12 * np.max(np.abs(g.S))   # every cell closes
+    phi = np.degrees(np.arctan2(p.s[:, 1], p.s[:, 0])) % 360
+    cyclic = (phi > 110) & (phi < 190) | (phi > 290) & (phi < 370)
+    assert cyclic.any() and not cyclic.all()
+    nbr = np.ascontiguousarray(g.nbr, np.int64)
+    S = np.ascontiguousarray(g.S)
+    for i in range(len(p.w)):
+        e = np.empty(g.N)
+        fl = np.empty(g.N)
+        st = _lib().oracle_sweep_system(g.N, g.F, _p(nbr, ctypes.c_int64), _p(S), _p(g.V),
+                                        _p(np.ascontiguousarray(p.s[i])), 1.0, 1.0, _p(np.ones(g.N)),
+                                        _p(np.zeros(len(g.bf_owner))), _p(e), _p(fl))
+        assert st == (1 if cyclic[i] else 0), (i, phi[i])
+    # P1 on the cyclic systems: the direct fallback equals the dense solve
+    theta = rng.uniform(-1, 1, g.N)
+    inflow = rng.uniform(-1, 1, (len(p.C), len(p.w), len(g.bf_owner))) * 1e4
+    e, _ = oracle.transport(su, theta, inflow)
+    for b in range(len(p.C)):
+        for i in np.flatnonzero(cyclic):
+            A = np.zeros((g.N, g.N))
+            r = p.C[b] * theta / (su.W * p.tau[b]) + p.Q * p.C[b] / (su.C_tot * su.W)
+            for c in range(g.N):
+                a = g.S[c] @ p.s[i] / g.V[c]
+                A[c, c] = 1 / p.tau[b] + p.v[b] * a[a > 0].sum()
+                for f in range(g.F):
+                    if a[f] < 0:
+                        nb = g.nbr[c, f]
+                        if nb >= 0:
+                            A[c, nb] -= p.v[b] * -a[f]
+                        else:
+                            r[c] += p.v[b] * -a[f] * inflow[b, i, -(nb + 1)]
+            assert _rel(e[b, i], np.linalg.solve(A, r)) < 1e-13
+    # P2 on the cyclic mesh
+    thL, th, q = dense_coupled(p)
+    res = oracle.solve(p, scheme="synthetic", tol=1e-14, max_iter=20000)
+    assert _rel(res.theta_L, thL) < 1e-11
+    assert np.max(np.linalg.norm(res.q - q, axis=1)) / np.max(np.linalg.norm(q, axis=1)) < 1e-11
+
+
+# ----------------------------------------------------------------------------
+# energy temperature T (the macroscopic temperature of the outputs): exact
+# special cases that fix its normalisation
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,maker", TINY)
+def test_energy_temperature_of_local_equilibrium_is_the_lattice_temperature(name, maker):
+    """e = C theta / W in every direction (local equilibrium at an arbitrary
+    field theta) carries the energy C theta per volume, so T - T_ref = theta
+    exactly; it also has no net flux (q = 0 for a quadrature with
+    sum_i w_i s_i = 0) and the collision-weighted temperature is theta too."""
+    rng = np.random.default_rng(23)
+    p = maker(rng)
+    su = oracle.prepare(p)
+    theta = rng.uniform(-3, 3, su.g.N)
+    e = np.broadcast_to(oracle.equilibrium(su, theta)[:, None, :], (len(p.C), len(p.w), su.g.N))
+    ts, th, q = oracle.moments(su, e)
+    assert np.max(np.abs(th - theta)) <= 1e-14 * np.max(np.abs(theta))
+    assert np.max(np.abs(ts - theta)) <= 1e-14 * np.max(np.abs(theta))
+    assert np.max(np.abs(p.w @ p.s)) < 1e-14
+    assert np.max(np.abs(q)) <= 1e-12 * np.max(p.C * p.v) * np.max(np.abs(theta))
+
+
+def test_gray_medium_energy_and_lattice_temperatures_coincide():
+    """With one band the collision weight 1/tau is common to every mode, so
+    the lattice temperature of Eq. (5) and the energy temperature are the
+    same moment of ANY distribution; the converged gray solve (config 1,
+    sequential) therefore has T = T_L on every cell, and the iteration's
+    sequential update equals the energy temperature of each iterate."""
+    rng = np.random.default_rng(29)
+    p = C.config1(n=6, D=8)
+    su = oracle.prepare(p)
+    e = rng.standard_normal((1, len(p.w), su.g.N))
+    ts, th, _ = oracle.moments(su, e)
+    assert np.max(np.abs(ts - th)) <= 1e-14 * np.max(np.abs(th))
+    r = oracle.solve(p, scheme="sequential", tol=1e-13)
+    assert np.max(np.abs(r.T - r.T_lattice)) <= 1e-12 * np.max(np.abs(r.T_lattice - p.T_ref))
