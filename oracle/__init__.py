@@ -9,7 +9,7 @@ may import it.
 Parity status of each function (what pins it) is recorded in the tests under
 tests/test_oracle_*.py.
 """
-from .solver import (OracleError, Result, Setup, boundary_flows, boundary_inflow, diffusion_operator,  # noqa: F401
-                     divergence,
-                     energy_defect, equilibrium, fourier_guess, moments, prepare, solve, source, threads, transport,
+from .solver import (OracleError, Result, Setup, accel_state, accel_unpack, anderson_next,  # noqa: F401
+                     boundary_flows, boundary_inflow, diffusion_operator, divergence, energy_defect,
+                     equilibrium, fourier_guess, moments, prepare, solve, source, threads, transport,
                      transport_systems)

@@ -383,6 +383,58 @@ def boundary_flows(su: Setup, e, inflow):
 
 
 # ----------------------------------------------------------------------------
+# outer acceleration (an addition to the method; the fixed point is unchanged)
+# ----------------------------------------------------------------------------
+
+def anderson_next(X_hist, G_hist):
+    """Anderson acceleration of a fixed-point iteration x = G(x) (D. G.
+    Anderson, J. ACM 12 (1965); the unconstrained least-squares form of
+    H. F. Walker and P. Ni, SIAM J. Numer. Anal. 49 (2011)).
+
+    X_hist, G_hist: the last m+1 iterates x_j and their images G(x_j), oldest
+    first.  With the residuals f_j = G(x_j) - x_j and the columns
+    dF_j = f_{j+1} - f_j, dG_j = G(x_{j+1}) - G(x_j) (j over the history),
+    the next iterate is
+        x_new = G(x_k) - dG gamma,   gamma = argmin_gamma || f_k - dF gamma ||_2
+    (least squares by a library routine).  One entry of history (m = 0)
+    gives the plain iteration x_new = G(x_k)."""
+    g = G_hist[-1]
+    if len(X_hist) < 2:
+        return g.copy()
+    F = [gj - xj for xj, gj in zip(X_hist, G_hist)]
+    dF = np.stack([F[j + 1] - F[j] for j in range(len(F) - 1)], axis=1)
+    dG = np.stack([G_hist[j + 1] - G_hist[j] for j in range(len(G_hist) - 1)], axis=1)
+    gamma = np.linalg.lstsq(dF, F[-1], rcond=None)[0]
+    return g - dG @ gamma
+
+
+def _accel_mask(su: Setup):
+    """(B, D, NBF) mask of the inflow entries that change between iterations:
+    incoming directions of the specular, diffuse and partial walls."""
+    B = len(su.C)
+    m = ((su.sdotS < 0) & (su.bc_kind != 0)[:, None]).T        # (D, NBF)
+    return np.broadcast_to(m[None, :, :], (B,) + m.shape)
+
+
+def accel_state(su: Setup, theta, inflow):
+    """The state of the outer iteration as one vector: the lattice
+    temperature theta (N) followed by the reflective walls' incoming values
+    in temperature units, inflow * W / C_lambda, band-major over the masked
+    (band, direction, face) entries."""
+    return np.concatenate([theta, (inflow * (su.W / su.C)[:, None, None])[_accel_mask(su)]])
+
+
+def accel_unpack(su: Setup, x, inflow_like):
+    """Inverse of accel_state: (theta, inflow); entries outside the mask
+    (thermalizing walls, outgoing directions) are taken from inflow_like."""
+    N = su.g.N
+    inflow = np.array(inflow_like, copy=True)
+    m = _accel_mask(su)
+    inflow[m] = x[N:] * np.broadcast_to((su.C / su.W)[:, None, None], inflow.shape)[m]
+    return x[:N].copy(), inflow
+
+
+# ----------------------------------------------------------------------------
 # the iteration
 # ----------------------------------------------------------------------------
 
@@ -409,7 +461,8 @@ def energy_defect(su: Setup, flows):
 
 
 def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_tol=None,
-          setup: Setup = None, keep_e=False, verbose=False, time_limit=None, dsa_kappa="consistent"):
+          setup: Setup = None, keep_e=False, verbose=False, time_limit=None, dsa_kappa="consistent",
+          accel=None, depth=5):
     """Iterate to the steady state.
 
     scheme: "sequential" (Eq. (5)), "synthetic" (default; the DSA reading of
@@ -422,8 +475,14 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
     amplified by the correction.  dsa_kappa selects the conductivity of L
     (see _face_conductivity).
 
+    accel="anderson": Anderson acceleration of depth `depth` (anderson_next)
+    of the outer iteration, whose state is the lattice temperature and the
+    lagged inflow of the reflective walls (accel_state); the converged fields
+    are those of the plain iteration.
+
     Stops when max|theta^{n+1} - theta^n| / max|theta^{n+1}| <= tol and, if
-    defect_tol is given, the energy defect is <= defect_tol."""
+    defect_tol is given, the energy defect is <= defect_tol; theta^{n+1} is
+    the image of theta^n under one iteration (before any acceleration)."""
     t0 = time.perf_counter()
     su = setup if setup is not None else prepare(problem)
     scheme = scheme or problem.scheme
@@ -434,12 +493,15 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
     else:
         theta = np.asarray(T_init, float) - su.T_ref
     e = np.broadcast_to(equilibrium(su, theta)[:, None, :], (len(su.C), len(su.w), su.g.N))
+    if accel not in (None, "anderson"):
+        raise OracleError(f"unknown outer acceleration {accel}")
     hist = []
     res = np.inf
     it = 0
-    inflow = None
+    inflow = boundary_inflow(su, e)
+    inflow_used, theta_new = inflow, theta
+    X_hist, G_hist = [], []
     while it < max_iter:
-        inflow = boundary_inflow(su, e)
         e, outflux = transport(su, theta, inflow)
         theta_seq, th_energy, q = moments(su, e)
         if scheme == "sequential":
@@ -455,9 +517,10 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
         if not np.all(np.isfinite(theta_new)):
             raise OracleError("iteration diverged (non-finite temperature)")
         res = float(np.max(np.abs(theta_new - theta)) / denom) if denom > 0 else 0.0
+        theta_prev, inflow_used = theta, inflow
         theta = theta_new
         it += 1
-        flows = boundary_flows(su, e, inflow)
+        flows = boundary_flows(su, e, inflow_used)
         dfc = energy_defect(su, flows)
         hist.append((res, dfc))
         if verbose:
@@ -466,6 +529,15 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
             break
         if time_limit is not None and time.perf_counter() - t0 > time_limit:
             break
+        inflow = boundary_inflow(su, e)
+        if accel == "anderson" and depth > 0:
+            # x_n = (theta^n, inflow^n) -> G(x_n) = (theta^{n+1}, inflow from e^{n+1})
+            X_hist.append(accel_state(su, theta_prev, inflow_used))
+            G_hist.append(accel_state(su, theta, inflow))
+            del X_hist[:-(depth + 1)], G_hist[:-(depth + 1)]
+            theta, inflow = accel_unpack(su, anderson_next(X_hist, G_hist), inflow)
+    inflow = inflow_used
+    theta = theta_new
     flows = boundary_flows(su, e, inflow)
     by_tag = {int(t): float(np.sum(flows[su.g.bf_tag == t])) for t in np.unique(su.g.bf_tag)}
     return Result(T_lattice=su.T_ref + theta, T=su.T_ref + th_energy, q=q, theta_L=theta,
