@@ -194,6 +194,16 @@ nbte_status nbte_read_result(nbte_problem *p, nbte_result *out);
  * unit weight, FP64) of one (band, direction) system into host out[n_cells]. */
 nbte_status nbte_get_distribution(nbte_problem *p, int32_t band, int32_t dir, double *out);
 
+/* The same read for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it):
+ * nothing is allocated; the values are staged through a library-owned,
+ * file-scope device array of 2^21 FP64 values (16 MiB per GPU, held until the
+ * process ends) on the current device.  Meshes of more than 2^21 cells get
+ * NBTE_ERR_INVALID_ARG.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (problems on different streams, host threads) race, so
+ * the caller serialises them.  Errors as nbte_get_distribution. */
+nbte_status nbte_get_distribution_noalloc(nbte_problem *p, int32_t band, int32_t dir, double *out);
+
 /* Sweep schedule of one direction (host data, no device needed): the cells in
  * upwind order (perm[n_cells], nullable) grouped in topological levels
  * lvl_ptr[0..n_levels] (nullable; capacity cap_levels entries), such that

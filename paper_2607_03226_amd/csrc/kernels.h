@@ -229,4 +229,11 @@ void launch_gather(int64_t n, const int32_t *idx, const double *in, void *out, b
 // e(band, dir, c) of the last sweep of a solve
 void launch_distribution(const DeviceView *v, bool fp32, int band, int dir, double *out, int64_t N, hipStream_t st);
 
+// The file-scope staging array of the allocation-free distribution read
+// (FP64, one value per cell) on the current device: its device address,
+// looked up with hipGetSymbolAddress on the first call per device and kept.
+constexpr int64_t kDistributionScratchCells = 1 << 21;   // 16 MiB per device
+constexpr int kMaxDevices = 64;
+hipError_t distribution_scratch(double **out);
+
 }  // namespace nbte

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/nbte.h"
 #include "kernels.h"
@@ -1478,6 +1479,35 @@ void launch_distribution(const DeviceView *v, bool fp32, int band, int dir, doub
     dim3 grid((unsigned)((N + 255) / 256));
     if (fp32) hipLaunchKernelGGL(k_distribution<float>, grid, dim3(256), 0, st, v, band, dir, out);
     else hipLaunchKernelGGL(k_distribution<double>, grid, dim3(256), 0, st, v, band, dir, out);
+}
+
+// Staging buffer of the allocation-free distribution read: one FP64 value per
+// cell, kDistributionScratchCells at most.  Every GPU the library runs on
+// holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address): the device address is looked up once per device, with that
+// device current, and used everywhere instead.
+static __device__ __align__(256) double scratch[kDistributionScratchCells];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t distribution_scratch(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace nbte

@@ -940,6 +940,27 @@ nbte_status nbte_get_distribution(nbte_problem *p, int32_t band, int32_t dir, do
     });
 }
 
+nbte_status nbte_get_distribution_noalloc(nbte_problem *p, int32_t band, int32_t dir, double *out) {
+    return guarded([&] {
+        if (!p || !out) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        if (!p->prepared) throw Error(NBTE_ERR_STATE, "no distribution yet");
+        if (band < 0 || band >= p->bands.B || dir < 0 || dir >= p->quad.D)
+            throw Error(NBTE_ERR_INVALID_ARG, "band or direction out of range");
+        if (p->mesh->N > kDistributionScratchCells)
+            throw Error(NBTE_ERR_INVALID_ARG, "mesh of " + std::to_string(p->mesh->N) +
+                                                  " cells exceeds the allocation-free read's staging array of " +
+                                                  std::to_string(kDistributionScratchCells) + " cells");
+        double *stage = nullptr;
+        NBTE_HIP(distribution_scratch(&stage));
+        p->sync_state();
+        // every staged value is written by the kernel before the copy reads it
+        launch_distribution(p->d_view.as<DeviceView>(), p->fp32(), band, dir, stage, p->mesh->N, p->stream);
+        NBTE_HIP(hipMemcpyAsync(out, stage, p->mesh->N * 8, hipMemcpyDeviceToHost, p->stream));
+        NBTE_HIP(hipStreamSynchronize(p->stream));
+        return NBTE_OK;
+    });
+}
+
 nbte_status nbte_get_schedule(nbte_problem *p, int32_t dir, int32_t *perm, int32_t *lvl_ptr, int32_t cap_levels,
                               int32_t *n_levels) {
     return guarded([&] {

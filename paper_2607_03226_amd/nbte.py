@@ -86,6 +86,7 @@ SIGNATURES = [
     ("nbte_iterate", ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_int32, _d]),
     ("nbte_read_result", ct.c_int32, [ct.c_void_p, ct.POINTER(Result)]),
     ("nbte_get_distribution", ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_int32, _d]),
+    ("nbte_get_distribution_noalloc", ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_int32, _d]),
     ("nbte_get_schedule", ct.c_int32, [ct.c_void_p, ct.c_int32, _i32, _i32, ct.c_int32, _i32]),
     ("nbte_get_stats", ct.c_int32, [ct.c_void_p, ct.POINTER(Stats)]),
     ("nbte_set_tuning", ct.c_int32, [ct.c_void_p, ct.POINTER(Tuning)]),
@@ -313,6 +314,12 @@ def nbte_read_result(p):
 def nbte_get_distribution(p, band, direction):
     out = np.empty(p.n_cells)
     _check(_lib.nbte_get_distribution(p.handle, int(band), int(direction), _ptr(out)))
+    return out
+
+
+def nbte_get_distribution_noalloc(p, band, direction):
+    out = np.empty(p.n_cells)
+    _check(_lib.nbte_get_distribution_noalloc(p.handle, int(band), int(direction), _ptr(out)))
     return out
 
 
