@@ -250,6 +250,17 @@ typedef struct {
     int32_t no_graphs;        /* 1: launch every kernel eagerly instead of replaying HIP graphs
                                  of one and of eight iterations (phase timing always runs
                                  eagerly) */
+    int32_t accel_depth;      /* Anderson acceleration of the outer iteration (0 = off, at most 8):
+                                 the iterate (lattice temperature and the boundary inflow of every
+                                 incoming face row and band) is replaced after each iteration by
+                                 G(x) - dG gamma, gamma the least-squares fit of the residual
+                                 f = G(x) - x by the differences dF of the last accel_depth steps
+                                 (D. G. Anderson 1965; Walker & Ni 2011).  An addition to the
+                                 method's iteration: the fixed point, the stop test (on the plain
+                                 image's residual) and the results at convergence are those of the
+                                 plain iteration.  Holds about (2 accel_depth + 4) state vectors of
+                                 n_cells + n_rows x n_bands values on the device (counted by
+                                 nbte_problem_footprint). */
 } nbte_tuning;
 nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t);
 nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t);

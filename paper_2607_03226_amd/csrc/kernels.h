@@ -64,6 +64,28 @@ struct PcgWork {
     double NBTE_G *scal;         // [-, r0.u0, -, -, converged flag, iterations, alpha/gamma per parity (6..9)]
 };
 
+// Anderson acceleration of the outer iteration (an addition to the method: it
+// changes the path of the iteration, not its fixed point).  The state of the
+// iteration is x = (theta, inflow): the lattice temperature (N values) and the
+// boundary inflow of every incoming (face, direction) row and band (NR = rows
+// x B values) in temperature units, e W / C_l.  After an iteration has formed
+// its image G(x) (the new theta and the inflow of the new distribution),
+//   f = G(x) - x,  dF_j = f_{j+1} - f_j,  dG_j = G_{j+1} - G_j  (last m steps),
+//   gamma = argmin || f - dF gamma ||,   x_next = G(x) - dG gamma.
+// Per-solve work arrays; the state vectors are [theta part | inflow part].
+struct AccelWork {
+    int32_t m;                   // depth (columns kept); 0 = off
+    int32_t nblk;                // workgroups of the state-length launches
+    int64_t NR;                  // inflow entries: ghost rows x bands
+    double NBTE_G *ain_x;        // NR: inflow of the current iterate x (temperature units)
+    double NBTE_G *ain_G;        // NR: inflow of its image G(x)
+    double NBTE_G *fprev;        // N + NR: f of the previous step
+    double NBTE_G *Gprev;        // N + NR: G of the previous step (then of this step)
+    void NBTE_G *dF, *dG;        // m (N + NR) each, in the storage type: column j at j (N + NR)
+    double NBTE_G *part;         // nblk x 2m partial sums of a step
+    double NBTE_G *scal;         // [0] steps done; [1..m*m] Gram matrix dF_i . dF_j; then m gammas
+};
+
 // Everything the kernels read and write of one solve, as raw device pointers.
 struct DeviceView {
     int64_t N;       // cells
@@ -126,6 +148,7 @@ struct DeviceView {
     double NBTE_G *theta_seq, *thetaE, *q, *rhs, *delta;
     SolveState NBTE_G *state;
     PcgWork pcg;
+    AccelWork acc;
 };
 
 // One workgroup's share of a launch: the solve (index into the descriptor
@@ -142,7 +165,8 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 // Work tables of the elementwise kernels: items (solve, kind, local block,
 // blocks of this (solve, kind)), 256 threads each.
 //   stage:   kind 0 = boundary inflow, one wave per boundary face;
-//            kind 1 = equilibrium-imbalance term D of every stream entry
+//            kind 1 = equilibrium-imbalance term D of every stream entry;
+//            kinds 2, 3 = the accelerated iteration's absolute inflow (below)
 //   flux:    per-band outgoing sums and net flow, one wave per boundary face
 //            (items (solve, -, b, nblk): faces b*4 + wave, strided by 4 nblk)
 //   post:    kind 0 = flux mode 0 face groups (as above); kind 1 = band x
@@ -161,6 +185,18 @@ void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int
 void launch_post(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
 void launch_wall_rhs(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
+// Anderson step after an iteration's finish (solves with acc.m > 0; each
+// kernel skips a solve that has stopped):
+//   inflow: items (solve, 2, b, nblk) of the stage kernel's face waves: the
+//           inflow of the new distribution into acc.ain_G (kind 3: into
+//           acc.ain_x, the inflow of the initial state at prepare);
+//   cols:   items (solve, -, b, acc.nblk): f, the newest columns, partial sums;
+//   solve:  one workgroup per solve (items (solve, ...)): Gram matrix, gamma;
+//   mix:    items as cols: x_next into theta[cur] and acc.ain_x.
+void launch_accel_cols(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
+void launch_accel_solve(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
+void launch_accel_mix(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
+constexpr int kAccelMaxDepth = 8;
 void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 
 // One sweep launch over a work list (solve, direction, band block).  All

@@ -93,8 +93,99 @@ __global__ void k_fill_zero(uint32_t *p, size_t n) {
 // sweep), so only specular parts read the distribution.  The face's incoming
 // flow sum_l v_l sum_in w (s.S) e_in, with the values just written, is kept
 // for the flux kernel of this iteration (Jin).
+// Accelerated iteration: the inflow of the coming sweep is the mixed iterate's
+// (acc.ain_x, temperature units), written as the deviation from the owner's
+// equilibrium at the coming sweep's theta; the face's incoming flow as above.
+template <class T>
+__device__ void bc_face_mixed(const DeviceView &v, int64_t bf) {
+    const int lane = threadIdx.x & 63;
+    const int D = v.D, B = v.B;
+    const int c = v.bf_owner[bf];
+    T *gv = static_cast<T *>(v.gval);
+    const double *sd = v.sdotS + bf * D;
+    const int32_t *row = v.in_row + bf * D;
+    const double thc = theta_cur(v)[c];
+    const double *ax = v.acc.ain_x;
+    const bool refl = v.bf_kind[bf] != NBTE_BC_THERMALIZING;
+    const int BL = B < 64 ? B : 64;
+    const int JG = 64 / BL;
+    const int jg = lane / BL, ml = lane - jg * BL;
+    double jin = 0.0;
+    for (int l0 = 0; l0 < B; l0 += BL) {
+        const int lam = l0 + ml;
+        if (jg >= JG || lam >= B) continue;
+        const double cw = v.Cw[lam];
+        double acc = 0.0;
+#pragma unroll 8
+        for (int i = jg; i < D; i += JG) {
+            const int r = row[i];
+            if (r >= 0) {
+                const double t = ax[(int64_t)r * B + lam];
+                gv[(int64_t)r * B + lam] = static_cast<T>(cw * (t - thc));
+                acc += v.w[i] * sd[i] * t;
+            }
+        }
+        jin += v.vel[lam] * cw * acc;
+    }
+    jin = wave_sum(jin);
+    if (lane == 0 && refl) v.Jin[bf] = jin;
+}
+
+// The inflow a boundary face's incoming rows receive from the distribution of
+// the last sweep (the boundary conditions above applied to it), in
+// temperature units (e W / C_l), into dst (acc.ain_G: the image of an
+// accelerated step; acc.ain_x: the initial state at prepare).  Runs after the
+// iteration's rotation, so theta[prev] is the last sweep's temperature and
+// bsum holds the outgoing sums of its distribution.
+template <class T>
+__device__ void bc_face_abs(const DeviceView &v, int64_t bf, double *dst) {
+    const int lane = threadIdx.x & 63;
+    const int D = v.D, B = v.B;
+    const int64_t N = v.N;
+    const int c = v.bf_owner[bf];
+    const T *g = static_cast<const T *>(v.g);
+    const int32_t *row = v.in_row + bf * D;
+    const int BL = B < 64 ? B : 64;
+    const int JG = 64 / BL;
+    const int jg = lane / BL, ml = lane - jg * BL;
+    if (v.bf_kind[bf] == NBTE_BC_THERMALIZING) {
+        const double thw = v.bf_thw[bf];
+        for (int l0 = 0; l0 < B; l0 += BL) {
+            const int lam = l0 + ml;
+            if (jg >= JG || lam >= B) continue;
+            for (int i = jg; i < D; i += JG) {
+                const int r = row[i];
+                if (r >= 0) dst[(int64_t)r * B + lam] = thw;
+            }
+        }
+        return;
+    }
+    const double thp = theta_prev(v)[c];
+    const double p = v.bf_p[bf];
+    const double iw = 1.0 / v.win[bf];
+    const int32_t *mir = v.mirror + bf * D;
+    for (int l0 = 0; l0 < B; l0 += BL) {
+        const int lam = l0 + ml;
+        if (jg >= JG || lam >= B) continue;
+        const double cw = v.Cw[lam];
+        const double diff = p < 1.0 ? v.bsum[bf * B + lam] * iw / cw : 0.0;
+#pragma unroll 8
+        for (int i = jg; i < D; i += JG) {
+            const int r = row[i];
+            if (r < 0) continue;
+            double t = (1.0 - p) * diff;
+            if (p > 0.0) t += p * (ld(g, ((int64_t)mir[i] * N + c) * B + lam) / cw + thp);
+            dst[(int64_t)r * B + lam] = t;
+        }
+    }
+}
+
 template <class T>
 __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
+    if (v.acc.m > 0) {
+        bc_face_mixed<T>(v, bf);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
@@ -203,6 +294,10 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
         const int wv = threadIdx.x >> 6;
         for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4)
             bc_face<T>(v, bf, red + 64 * wv);
+    } else if (it.a >= 2) {
+        double *dst = it.a == 2 ? v.acc.ain_G : v.acc.ain_x;
+        const int wv = threadIdx.x >> 6;
+        for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4) bc_face_abs<T>(v, bf, dst);
     } else {
         // D = sum_j |a_j| (theta_up_j - theta_c): the closed cell's
         // sum_{a<0} |a| - sum_{a>0} a vanishes (divergence theorem, to the
@@ -987,6 +1082,166 @@ __global__ void k_finish(const DeviceView *__restrict__ vs, const WorkItem *__re
     else if (s->stop && s->patience > 0 && s->since >= s->patience) s->done = NBTE_DONE_STALLED;
 }
 
+// --------------------------------------------------------------------------
+// Anderson acceleration of the outer iteration (see AccelWork).  After the
+// finish of an iteration: theta[prev] is x's temperature, theta[cur] its
+// image, ain_x / ain_G the inflow parts.  Step k (k = steps done before it):
+// k = 0 keeps f and G only (x_next = G); k >= 1 writes the newest columns
+// into slot (k - 1) mod m and the partial sums a_j = dF_new . dF_j and
+// b_j = dF_j . f of the w = min(k, m) columns in the window.  The columns are
+// stored in the storage type; the sums use the stored values.
+// --------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_accel_cols(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    __shared__ double lds[2 * kAccelMaxDepth * 4];
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    const AccelWork &a = v.acc;
+    const int64_t N = v.N, NS = N + a.NR;
+    const int m = a.m;
+    const int k = (int)a.scal[0];
+    const int c = k > 0 ? (k - 1) % m : 0;
+    const int w = k < m ? k : m;
+    const double *tx = theta_prev(v), *tg = theta_cur(v);
+    T *dF = static_cast<T *>(a.dF);
+    T *dG = static_cast<T *>(a.dG);
+    double sa[kAccelMaxDepth], sb[kAccelMaxDepth];
+#pragma unroll
+    for (int j = 0; j < kAccelMaxDepth; ++j) sa[j] = sb[j] = 0.0;
+    for (int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x; s < NS; s += (int64_t)it.c * blockDim.x) {
+        const double xv = s < N ? tx[s] : a.ain_x[s - N];
+        const double gv = s < N ? tg[s] : a.ain_G[s - N];
+        const double f = gv - xv;
+        if (k > 0) {
+            const T dfn = static_cast<T>(f - a.fprev[s]);
+            dF[c * NS + s] = dfn;
+            dG[c * NS + s] = static_cast<T>(gv - a.Gprev[s]);
+            const double dn = static_cast<double>(dfn);
+#pragma unroll
+            for (int j = 0; j < kAccelMaxDepth; ++j) {
+                if (j >= w) break;
+                const double dj = j == c ? dn : static_cast<double>(dF[j * NS + s]);
+                sa[j] += dn * dj;
+                sb[j] += dj * f;
+            }
+        }
+        a.fprev[s] = f;
+        a.Gprev[s] = gv;
+    }
+    if (k == 0) return;
+    // fixed-order block sums of the 2w values (lanes, then waves)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = 0; j < w; ++j) {
+        const double x = wave_sum(sa[j]), y = wave_sum(sb[j]);
+        if (lane == 0) {
+            lds[(2 * j) * 4 + wv] = x;
+            lds[(2 * j + 1) * 4 + wv] = y;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * w) {
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += lds[threadIdx.x * 4 + q];
+        a.part[(int64_t)it.b * 2 * kAccelMaxDepth + threadIdx.x] = t;
+    }
+}
+
+// One workgroup per solve: the partial sums of the step (fixed order), the
+// newest row and column of the Gram matrix H = dF^T dF, and gamma from
+// H gamma = dF^T f by Cholesky over the columns from newest to oldest,
+// truncated at the first column that is (to 1e-12 of its norm) a combination
+// of newer ones.  Thread 0 does the m x m algebra.
+__global__ void __launch_bounds__(64) k_accel_solve(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    __shared__ double tot[2 * kAccelMaxDepth];
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    const AccelWork &a = v.acc;
+    const int m = a.m;
+    const int k = (int)a.scal[0];
+    const int w = k < m ? k : m;
+    if (k > 0 && threadIdx.x < 2 * w) {
+        double t = 0.0;
+        for (int b = 0; b < a.nblk; ++b) t += a.part[(int64_t)b * 2 * kAccelMaxDepth + threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double *H = a.scal + 1;
+    double *gam = a.scal + 1 + m * m;
+    for (int j = 0; j < m; ++j) gam[j] = 0.0;
+    if (k > 0) {
+        const int c = (k - 1) % m;
+        for (int j = 0; j < w; ++j) {
+            H[c * m + j] = tot[2 * j];
+            H[j * m + c] = tot[2 * j];
+        }
+        int ord[kAccelMaxDepth];
+        for (int p = 0; p < w; ++p) ord[p] = ((c - p) % m + m) % m;   // newest first
+        double L[kAccelMaxDepth][kAccelMaxDepth], y[kAccelMaxDepth];
+        int used = 0;
+        for (int p = 0; p < w; ++p) {
+            const double hpp = H[ord[p] * m + ord[p]];
+            if (!(hpp > 0.0)) break;
+            bool ok = true;
+            for (int q = 0; q <= p; ++q) {
+                double sum = H[ord[p] * m + ord[q]];
+                for (int r = 0; r < q; ++r) sum -= L[p][r] * L[q][r];
+                if (q < p) {
+                    L[p][q] = sum / L[q][q];
+                } else {
+                    if (!(sum > 1e-12 * hpp)) ok = false;
+                    else L[p][p] = sqrt(sum);
+                }
+            }
+            if (!ok) break;
+            used = p + 1;
+        }
+        // forward and back substitution over the accepted columns
+        for (int p = 0; p < used; ++p) {
+            double sum = tot[2 * ord[p] + 1];
+            for (int r = 0; r < p; ++r) sum -= L[p][r] * y[r];
+            y[p] = sum / L[p][p];
+        }
+        for (int p = used - 1; p >= 0; --p) {
+            double sum = y[p];
+            for (int r = p + 1; r < used; ++r) sum -= L[r][p] * y[r];
+            y[p] = sum / L[p][p];
+            gam[ord[p]] = y[p];
+        }
+    }
+    a.scal[0] = k + 1;
+}
+
+// x_next = G - sum_j gamma_j dG_j into theta[cur] and ain_x.
+template <class T>
+__global__ void __launch_bounds__(256) k_accel_mix(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    const AccelWork &a = v.acc;
+    const int64_t N = v.N, NS = N + a.NR;
+    const int m = a.m;
+    const int k = (int)a.scal[0];   // steps done, this one included
+    const int w = k - 1 < m ? k - 1 : m;
+    double gam[kAccelMaxDepth];
+#pragma unroll
+    for (int j = 0; j < kAccelMaxDepth; ++j) gam[j] = j < m ? a.scal[1 + m * m + j] : 0.0;
+    const T *dG = static_cast<const T *>(a.dG);
+    double *tn = theta_at(v, th_cur(v.state));
+    for (int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x; s < NS; s += (int64_t)it.c * blockDim.x) {
+        double x = a.Gprev[s];
+#pragma unroll
+        for (int j = 0; j < kAccelMaxDepth; ++j) {
+            if (j >= w) break;
+            x -= gam[j] * static_cast<double>(dG[j * NS + s]);
+        }
+        if (s < N) tn[s] = x;
+        else a.ain_x[s - N] = x;
+    }
+}
+
 __global__ void k_set_controls(SolveState *s, int stop, double tol, int max_iter, int patience) {
     if (threadIdx.x == 0) {
         s->done = 0;
@@ -1410,6 +1665,23 @@ void launch_wall_rhs(const DeviceView *vs, const WorkItem *wk, int n, hipStream_
 void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_update, dim3(n), dim3(256), 0, st, vs, wk);
+}
+
+void launch_accel_cols(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_accel_cols<float>, dim3(n), dim3(256), 0, st, vs, wk);
+    else hipLaunchKernelGGL(k_accel_cols<double>, dim3(n), dim3(256), 0, st, vs, wk);
+}
+
+void launch_accel_solve(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_accel_solve, dim3(n), dim3(64), 0, st, vs, wk);
+}
+
+void launch_accel_mix(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_accel_mix<float>, dim3(n), dim3(256), 0, st, vs, wk);
+    else hipLaunchKernelGGL(k_accel_mix<double>, dim3(n), dim3(256), 0, st, vs, wk);
 }
 
 void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {

@@ -146,6 +146,12 @@ struct nbte_problem {
     nbte::DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta;
     nbte::DevBuf d_pcg_vec, d_pcg_part, d_pcg_scal;
     nbte::DevBuf d_view, d_state, d_self_work;
+    // Anderson acceleration of the outer iteration (tuning.accel_depth > 0)
+    nbte::DevBuf d_acc_x, d_acc_G, d_acc_fprev, d_acc_Gprev, d_acc_dF, d_acc_dG, d_acc_part, d_acc_scal;
+    int acc_nblk = 1;
+    int self_acc = 0, n_self_acc = 0;   // offsets in d_self_work: initial inflow state (face waves)
+    int accel_m() const { return tuning.accel_depth; }
+    int64_t accel_rows() const;         // NR: ghost rows x bands
     int pcg_nblk = 1;
     int ell_w = 0;                   // ELL width of the correction's matrix
 
@@ -156,7 +162,7 @@ struct nbte_problem {
     } shape;
     int slots_for_cap = -2;   // slot budget the current slot table was built for
     int prog_B = -1, prog_gcap = -1, prog_gring = -1, prog_ls = -1, prog_es = -1;
-    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0};
+    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0, 0};
 
     // iteration state
     bool prepared = false;

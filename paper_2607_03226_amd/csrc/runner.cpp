@@ -17,7 +17,8 @@ namespace nbte {
 
 namespace {
 
-enum Kind { K_MARK, K_STAGE, K_SWEEP, K_POST, K_WALL, K_PCG_BLOCK, K_PCG_MULTI, K_UPDATE, K_FINISH };
+enum Kind { K_MARK, K_STAGE, K_SWEEP, K_POST, K_WALL, K_PCG_BLOCK, K_PCG_MULTI, K_UPDATE, K_FINISH, K_ACC_COLS,
+            K_ACC_SOLVE, K_ACC_MIX };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -250,6 +251,50 @@ void Runner::build() {
         F.off = (int)work.size();
         for (int s = 0; s < M; ++s) work.push_back({s, 0, 0, 0});
         close(F);
+        // Anderson step of the accelerated members: the image's inflow (stage
+        // face waves of kind 2), columns and partial sums, gamma, the mix
+        for (bool f : {true, false}) {
+            Launch A;
+            A.kind = K_STAGE;
+            A.fp32 = f;
+            A.off = (int)work.size();
+            each(f, [&](int s, nbte_problem &p) {
+                if (p.accel_m() <= 0) return;
+                const int64_t nb = std::min<int64_t>(cdiv(p.mesh->NBF, 4), 2048);
+                for (int64_t b = 0; b < nb; ++b) work.push_back({s, 2, (int32_t)b, (int32_t)nb});
+            });
+            close(A);
+        }
+        for (bool f : {true, false}) {
+            Launch A;
+            A.kind = K_ACC_COLS;
+            A.fp32 = f;
+            A.off = (int)work.size();
+            each(f, [&](int s, nbte_problem &p) {
+                if (p.accel_m() <= 0) return;
+                for (int b = 0; b < p.acc_nblk; ++b) work.push_back({s, 0, b, p.acc_nblk});
+            });
+            close(A);
+        }
+        {
+            Launch A;
+            A.kind = K_ACC_SOLVE;
+            A.off = (int)work.size();
+            for (int s = 0; s < M; ++s)
+                if (members_[s]->accel_m() > 0) work.push_back({s, 0, 0, 0});
+            close(A);
+        }
+        for (bool f : {true, false}) {
+            Launch A;
+            A.kind = K_ACC_MIX;
+            A.fp32 = f;
+            A.off = (int)work.size();
+            each(f, [&](int s, nbte_problem &p) {
+                if (p.accel_m() <= 0) return;
+                for (int b = 0; b < p.acc_nblk; ++b) work.push_back({s, 0, b, p.acc_nblk});
+            });
+            close(A);
+        }
     }
     mark(PH_END);
 
@@ -287,6 +332,9 @@ void Runner::enqueue_iteration(int slot) {
                 break;
             case K_UPDATE: launch_update(vs, wk + L.off, L.n, stream_); break;
             case K_FINISH: launch_finish(vs, wk + L.off, L.n, stream_); break;
+            case K_ACC_COLS: launch_accel_cols(vs, wk + L.off, L.n, L.fp32, stream_); break;
+            case K_ACC_SOLVE: launch_accel_solve(vs, wk + L.off, L.n, stream_); break;
+            case K_ACC_MIX: launch_accel_mix(vs, wk + L.off, L.n, L.fp32, stream_); break;
         }
     }
     NBTE_HIP(hipGetLastError());

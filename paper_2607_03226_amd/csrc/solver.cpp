@@ -359,12 +359,22 @@ void nbte_problem::upload_device() {
     NBTE_HIP(hipStreamSynchronize(stream));
 }
 
+int64_t nbte_problem::accel_rows() const {
+    const int64_t ghosts = prog_B > 0 ? (int64_t)prog.ghost_src.size() : mesh->NBF * quad.D;   // incoming pairs
+    return std::max<int64_t>(ghosts, 1) * bands.B;
+}
+
 int64_t nbte_problem::state_bytes(int prec) const {
     const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
     const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
     const int64_t ghosts = prog_B > 0 ? (int64_t)prog.ghost_src.size() : NBF * D;   // incoming pairs
+    int64_t acc = 0;
+    if (accel_m() > 0) {
+        const int64_t NR = accel_rows(), NS = N + NR;
+        acc = (2 * NR + 2 * NS) * 8 + 2 * (int64_t)accel_m() * NS * es + 1024 * 2 * kAccelMaxDepth * 8 + 1024;
+    }
     return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + NBF * (B + 3) * 8 + N * 8 * 10 +
-           1024;
+           1024 + acc;
 }
 
 void nbte_problem::allocate_state(int prec) {
@@ -403,6 +413,21 @@ void nbte_problem::allocate_state(int prec) {
     d_delta.alloc(N * 8);
     d_state.alloc(sizeof(SolveState));
     d_view.alloc(sizeof(DeviceView));
+    if (accel_m() > 0) {
+        const int64_t NR = accel_rows(), NS = N + NR;
+        d_acc_x.alloc(NR * 8);
+        d_acc_G.alloc(NR * 8);
+        d_acc_fprev.alloc(NS * 8);
+        d_acc_Gprev.alloc(NS * 8);
+        d_acc_dF.alloc((size_t)accel_m() * NS * es);
+        d_acc_dG.alloc((size_t)accel_m() * NS * es);
+        acc_nblk = (int)std::min<int64_t>(1024, cdiv(NS, 256));
+        d_acc_part.alloc((size_t)acc_nblk * 2 * kAccelMaxDepth * 8);
+        d_acc_scal.alloc((1 + kAccelMaxDepth * kAccelMaxDepth + kAccelMaxDepth) * 8);
+    } else {
+        for (DevBuf *b : {&d_acc_x, &d_acc_G, &d_acc_fprev, &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal})
+            b->release();
+    }
 }
 
 int64_t nbte_problem::device_bytes() const {
@@ -411,7 +436,8 @@ int64_t nbte_problem::device_bytes() const {
          {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pint, &d_pupc, &d_tstream, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
           &d_mirror, &d_wall, &d_wall_ptr, &d_wslot, &d_wallJ, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_Ecol, &d_Eval, &d_g, &d_gval,
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
-          &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work})
+          &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work, &d_acc_x, &d_acc_G, &d_acc_fprev,
+          &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -495,6 +521,18 @@ void nbte_problem::make_view() {
     w.vec = d_pcg_vec.as<double>();
     w.partial = d_pcg_part.as<double>();
     w.scal = d_pcg_scal.as<double>();
+    AccelWork &a = v.acc;
+    a.m = accel_m();
+    a.nblk = acc_nblk;
+    a.NR = a.m > 0 ? accel_rows() : 0;
+    a.ain_x = d_acc_x.as<double>();
+    a.ain_G = d_acc_G.as<double>();
+    a.fprev = d_acc_fprev.as<double>();
+    a.Gprev = d_acc_Gprev.as<double>();
+    a.dF = d_acc_dF.ptr;
+    a.dG = d_acc_dG.ptr;
+    a.part = d_acc_part.as<double>();
+    a.scal = d_acc_scal.as<double>();
     hv = v;
 }
 
@@ -544,6 +582,9 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
         self_flux = (int)wk.size();
         for (int b = 0; b < nf; ++b) wk.push_back({0, 0, b, nf});
         n_self_flux = nf;
+        self_acc = (int)wk.size();   // stage items of kind 3: the initial inflow state
+        for (int b = 0; b < nf; ++b) wk.push_back({0, 3, b, nf});
+        n_self_acc = nf;
         upload(d_self_work, wk, stream);
         NBTE_HIP(hipStreamSynchronize(stream));
     }
@@ -587,6 +628,11 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     launch_fill_zero(d_gval.ptr, d_gval.bytes, stream);
     // the first boundary stage's diffuse sums, from the initial distribution
     launch_flux(d_view.as<DeviceView>(), d_self_work.as<WorkItem>() + self_flux, n_self_flux, fp32(), 2, stream);
+    if (accel_m() > 0) {
+        // the accelerated iteration starts from the initial state's inflow, with no history
+        launch_fill_zero(d_acc_scal.ptr, d_acc_scal.bytes, stream);
+        launch_stage(d_view.as<DeviceView>(), d_self_work.as<WorkItem>() + self_acc, n_self_acc, fp32(), stream);
+    }
     NBTE_HIP(hipGetLastError());
     NBTE_HIP(hipStreamSynchronize(stream));
     hs = s0;
@@ -636,6 +682,12 @@ void nbte_problem::promote() {
     launch_gather((int64_t)quad.D * mesh->N, p_cell(), d_Q.as<double>(), t_row(2), false, stream);
     make_view();
     NBTE_HIP(hipMemcpyAsync(d_view.ptr, &hv, sizeof(DeviceView), hipMemcpyHostToDevice, stream));
+    if (accel_m() > 0) {
+        // the acceleration restarts, in FP64 columns, from the last plain image:
+        // theta[cur] and the inflow of the last distribution
+        launch_fill_zero(d_acc_scal.ptr, d_acc_scal.bytes, stream);
+        launch_stage(d_view.as<DeviceView>(), d_self_work.as<WorkItem>() + self_acc, n_self_acc, fp32(), stream);
+    }
     NBTE_HIP(hipGetLastError());
     NBTE_HIP(hipStreamSynchronize(stream));
     refined_at = hs.iterations;
@@ -1005,6 +1057,8 @@ nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t) {
         if (t->block_size != 0 && (t->block_size < 64 || t->block_size > 1024 || t->block_size % 64))
             throw Error(NBTE_ERR_INVALID_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
         if (t->cg_max_iter < 0 || !(t->cg_rtol >= 0)) throw Error(NBTE_ERR_INVALID_ARG, "bad CG settings");
+        if (t->accel_depth < 0 || t->accel_depth > kAccelMaxDepth)
+            throw Error(NBTE_ERR_INVALID_ARG, "accel_depth must be in [0, 8]");
         if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member");
         p->tuning = *t;
         p->prepared = false;   // launch shape and slot table are rebuilt by the next prepare

@@ -66,7 +66,7 @@ class BatchInfo(ct.Structure):
 class Tuning(ct.Structure):
     _fields_ = [("bands_per_block", ct.c_int32), ("bands_per_lane", ct.c_int32), ("block_size", ct.c_int32),
                 ("lds_bytes", ct.c_int32), ("cg_max_iter", ct.c_int32), ("cg_rtol", ct.c_double),
-                ("no_graphs", ct.c_int32)]
+                ("no_graphs", ct.c_int32), ("accel_depth", ct.c_int32)]
 
 
 # (name, restype, argtypes) of every exported symbol declared in include/nbte.h
@@ -339,9 +339,9 @@ def nbte_get_stats(p):
 
 
 def nbte_set_tuning(p, bands_per_block=0, bands_per_lane=0, block_size=0, lds_bytes=0, cg_max_iter=0, cg_rtol=0.0,
-                    no_graphs=0):
+                    no_graphs=0, accel_depth=0):
     t = Tuning(int(bands_per_block), int(bands_per_lane), int(block_size), int(lds_bytes), int(cg_max_iter),
-               float(cg_rtol), int(no_graphs))
+               float(cg_rtol), int(no_graphs), int(accel_depth))
     _check(_lib.nbte_set_tuning(p.handle, ct.byref(t)))
 
 
@@ -428,14 +428,17 @@ def build_problem(problem, stream=None):
 
 
 def solve(problem, precision=None, scheme=None, tol=1e-8, max_iter=10000, check_every=8, T_init=None,
-          stream=None, allow_not_converged=False, tuning=None):
+          stream=None, allow_not_converged=False, tuning=None, accel=None):
     """tuning: None (library defaults), "auto" (autotuner cache, defaults if
-    the workload was never tuned) or a dict of nbte_set_tuning arguments."""
+    the workload was never tuned) or a dict of nbte_set_tuning arguments;
+    accel: Anderson depth of the outer iteration (overrides the tuning's)."""
     mesh, p = build_problem(problem, stream)
     precision = precision or problem.precision
     if tuning == "auto":
         from . import tune
         tuning = tune.lookup(problem, precision)
+    if accel is not None:
+        tuning = dict(tuning or {}, accel_depth=int(accel))
     if tuning:
         nbte_set_tuning(p, **tuning)
     opts = make_opts(scheme=scheme or problem.scheme, precision=precision,

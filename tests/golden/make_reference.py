@@ -11,7 +11,9 @@ file with the members' arrays under "<j>/<field>".
 Every reference runs the oracle to a residual of 1e-12 and an energy defect
 of 1e-10 (the oracle's stopping rule, Methods: convergence criterion), so the
 stored fields sit on the discrete fixed point to about 1e-11 of the
-deviation scale.
+deviation scale.  The largest cases (the FinFET-like device, the 64-film
+batch) iterate with the oracle's Anderson acceleration, which changes the
+path of the outer iteration and not its fixed point.
 
 Usage: python tests/golden/make_reference.py config2 [config3] [serving_5008] [config4] ...
 """
@@ -42,8 +44,13 @@ MAKERS = {
 CONFIG4_SAMPLE = 1024   # cells stored per porous film of the 64-film batch
 
 
-def _solve(p, tol, defect_tol, verbose):
-    return oracle.solve(p, tol=tol, defect_tol=defect_tol, max_iter=100000, verbose=verbose)
+# cases whose plain oracle iteration takes hours: the oracle's Anderson
+# acceleration of the outer iteration (same fixed point; tests/test_oracle_accel.py)
+ACCEL = {"config3", "config4"}
+
+
+def _solve(p, tol, defect_tol, verbose, accel=None):
+    return oracle.solve(p, tol=tol, defect_tol=defect_tol, max_iter=100000, verbose=verbose, accel=accel)
 
 
 def _fields(p, r, n_sample, seed=12345):
@@ -64,7 +71,7 @@ def make(name, tol=1e-12, defect_tol=1e-10, verbose=True):
     if name == "config4":
         d = {}
         for j, p in enumerate(C.config4()):
-            r = _solve(p, tol, defect_tol, False)
+            r = _solve(p, tol, defect_tol, False, accel="anderson")
             for k, x in _fields(p, r, CONFIG4_SAMPLE, seed=12345 + j).items():
                 d[f"{j}/{k}"] = x
             print(f"config4[{j}] {p.name}: {r.iterations} iterations, residual {r.residual:.2e}, "
@@ -73,7 +80,7 @@ def make(name, tol=1e-12, defect_tol=1e-10, verbose=True):
     else:
         maker, n_sample = MAKERS[name]
         p = maker()
-        r = _solve(p, tol, defect_tol, verbose)
+        r = _solve(p, tol, defect_tol, verbose, accel="anderson" if name in ACCEL else None)
         d = _fields(p, r, n_sample)
         print(f"{name}: {r.iterations} iterations, residual {r.residual:.2e}, defect {r.energy_defect:.2e}",
               flush=True)
