@@ -22,8 +22,9 @@ Also reported on the same line:
                 iterations of the same workload, plus its single-thread
                 sweep rate on a sample of (band, direction) systems;
   converge      time-to-converge of the mixed and the FP64 path (same
-                stopping rule), with their error against the stored oracle
-                reference on every cell.
+                stopping rule), plain and with Anderson acceleration of the
+                outer iteration (--accel), with their error against the
+                stored oracle reference.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config1..config5]
   config4: the 64-solve batch (time to converge, batched vs one by one);
@@ -336,6 +337,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU baseline sample length (about)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--accel", type=int, default=8,
+                    help="Anderson depth of the extra time-to-converge legs (0: plain iteration only)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--summarize", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -442,9 +445,10 @@ def main():
         converge = {}
         ref_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_reference.npz")
         ref = np.load(ref_path) if os.path.exists(ref_path) else None
-        for prec in ("mixed", "fp64"):
-            sh = tune.lookup(p, prec)
-            N.nbte_set_tuning(h, **(sh or {}))
+        legs = [("mixed", 0), ("fp64", 0)] + ([("mixed", args.accel), ("fp64", args.accel)] if args.accel else [])
+        for prec, acc in legs:
+            sh = dict(tune.lookup(p, prec) or {}, accel_depth=acc)
+            N.nbte_set_tuning(h, **sh)
             o2 = N.make_opts(scheme=p.scheme, precision=prec, T_ref=p.T_ref, tol=1e-8, max_iter=20000)
             N.nbte_solve_steady(h, p.Q, o2)       # setup for this precision cached by the first call
             torch.cuda.synchronize()
@@ -453,16 +457,22 @@ def main():
             torch.cuda.synchronize()
             t_conv = time.perf_counter() - t1
             rec = {"seconds": t_conv, "iterations": out["iterations"], "residual": out["residual"],
-                   "energy_defect": out["energy_defect"]}
+                   "energy_defect": out["energy_defect"], "accel_depth": acc}
             if ref is not None:
                 c = ref["cells"] if "cells" in ref.files else slice(None)
                 rec["err_TL"] = float(np.max(np.abs(out["T_lattice"][c] - ref["T_lattice"])) / ref["scale_TL"])
                 rec["err_T"] = float(np.max(np.abs(out["T"][c] - ref["T"])) / ref["scale_T"])
                 rec["err_q"] = float(np.max(np.linalg.norm(out["q"][c] - ref["q"], axis=1)) / ref["scale_q"])
                 rec["cells_compared"] = int(len(ref["T_lattice"]))
-            converge[prec] = rec
-            log(f"bench: converge {prec}: {rec}")
+            leg = prec if acc == 0 else f"{prec}_anderson{acc}"
+            converge[leg] = rec
+            log(f"bench: converge {leg}: {rec}")
         converge["speedup_mixed_vs_fp64"] = converge["fp64"]["seconds"] / converge["mixed"]["seconds"]
+        if args.accel:
+            # the fastest mixed form against the plain FP64 per-system path
+            best = min(converge["mixed"]["seconds"], converge[f"mixed_anderson{args.accel}"]["seconds"])
+            converge["speedup_best_mixed_vs_plain_fp64"] = converge["fp64"]["seconds"] / best
+            converge["speedup_anderson_fp64"] = converge["fp64"]["seconds"] / converge[f"fp64_anderson{args.accel}"]["seconds"]
 
     cpu = None
     if not args.no_cpu:

@@ -1091,6 +1091,39 @@ __global__ void k_finish(const DeviceView *__restrict__ vs, const WorkItem *__re
 // b_j = dF_j . f of the w = min(k, m) columns in the window.  The columns are
 // stored in the storage type; the sums use the stored values.
 // --------------------------------------------------------------------------
+template <class T, int W>
+__device__ __forceinline__ void accel_cols_rows(const DeviceView &v, const WorkItem &it, int k, int c, double *sa,
+                                                double *sb) {
+    const AccelWork &a = v.acc;
+    const int64_t N = v.N, NS = N + a.NR;
+    const double *tx = theta_prev(v), *tg = theta_cur(v);
+    T *dF = static_cast<T *>(a.dF);
+    T *dG = static_cast<T *>(a.dG);
+    for (int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x; s < NS; s += (int64_t)it.c * blockDim.x) {
+        const double xv = s < N ? tx[s] : a.ain_x[s - N];
+        const double gv = s < N ? tg[s] : a.ain_G[s - N];
+        const double fp = a.fprev[s], gp = a.Gprev[s];
+        double dj[W > 0 ? W : 1];
+#pragma unroll
+        for (int j = 0; j < W; ++j) dj[j] = j == c ? 0.0 : static_cast<double>(dF[j * NS + s]);
+        const double f = gv - xv;
+        if (k > 0) {
+            const T dfn = static_cast<T>(f - fp);
+            dF[c * NS + s] = dfn;
+            dG[c * NS + s] = static_cast<T>(gv - gp);
+            const double dn = static_cast<double>(dfn);
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const double d = j == c ? dn : dj[j];
+                sa[j] += dn * d;
+                sb[j] += d * f;
+            }
+        }
+        a.fprev[s] = f;
+        a.Gprev[s] = gv;
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_accel_cols(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
     __shared__ double lds[2 * kAccelMaxDepth * 4];
@@ -1098,36 +1131,23 @@ __global__ void __launch_bounds__(256) k_accel_cols(const DeviceView *__restrict
     const DeviceView &v = vs[it.solve];
     if (v.state->done) return;
     const AccelWork &a = v.acc;
-    const int64_t N = v.N, NS = N + a.NR;
     const int m = a.m;
     const int k = (int)a.scal[0];
     const int c = k > 0 ? (k - 1) % m : 0;
     const int w = k < m ? k : m;
-    const double *tx = theta_prev(v), *tg = theta_cur(v);
-    T *dF = static_cast<T *>(a.dF);
-    T *dG = static_cast<T *>(a.dG);
     double sa[kAccelMaxDepth], sb[kAccelMaxDepth];
 #pragma unroll
     for (int j = 0; j < kAccelMaxDepth; ++j) sa[j] = sb[j] = 0.0;
-    for (int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x; s < NS; s += (int64_t)it.c * blockDim.x) {
-        const double xv = s < N ? tx[s] : a.ain_x[s - N];
-        const double gv = s < N ? tg[s] : a.ain_G[s - N];
-        const double f = gv - xv;
-        if (k > 0) {
-            const T dfn = static_cast<T>(f - a.fprev[s]);
-            dF[c * NS + s] = dfn;
-            dG[c * NS + s] = static_cast<T>(gv - a.Gprev[s]);
-            const double dn = static_cast<double>(dfn);
-#pragma unroll
-            for (int j = 0; j < kAccelMaxDepth; ++j) {
-                if (j >= w) break;
-                const double dj = j == c ? dn : static_cast<double>(dF[j * NS + s]);
-                sa[j] += dn * dj;
-                sb[j] += dj * f;
-            }
-        }
-        a.fprev[s] = f;
-        a.Gprev[s] = gv;
+    switch (w) {   // the window's columns as a compile-time count: every load of an entry issued together
+        case 0: accel_cols_rows<T, 0>(v, it, k, c, sa, sb); break;
+        case 1: accel_cols_rows<T, 1>(v, it, k, c, sa, sb); break;
+        case 2: accel_cols_rows<T, 2>(v, it, k, c, sa, sb); break;
+        case 3: accel_cols_rows<T, 3>(v, it, k, c, sa, sb); break;
+        case 4: accel_cols_rows<T, 4>(v, it, k, c, sa, sb); break;
+        case 5: accel_cols_rows<T, 5>(v, it, k, c, sa, sb); break;
+        case 6: accel_cols_rows<T, 6>(v, it, k, c, sa, sb); break;
+        case 7: accel_cols_rows<T, 7>(v, it, k, c, sa, sb); break;
+        default: accel_cols_rows<T, 8>(v, it, k, c, sa, sb); break;
     }
     if (k == 0) return;
     // fixed-order block sums of the 2w values (lanes, then waves)
@@ -1147,12 +1167,14 @@ __global__ void __launch_bounds__(256) k_accel_cols(const DeviceView *__restrict
     }
 }
 
-// One workgroup per solve: the partial sums of the step (fixed order), the
-// newest row and column of the Gram matrix H = dF^T dF, and gamma from
-// H gamma = dF^T f by Cholesky over the columns from newest to oldest,
-// truncated at the first column that is (to 1e-12 of its norm) a combination
-// of newer ones.  Thread 0 does the m x m algebra.
-__global__ void __launch_bounds__(64) k_accel_solve(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+// One workgroup per solve: the partial sums of the step (fixed order: wave q
+// sums values q, q + 4, ...; its lanes take the workgroups' partials in a
+// fixed stride, then a shuffle tree), the newest row and column of the Gram
+// matrix H = dF^T dF, and gamma from H gamma = dF^T f by Cholesky over the
+// columns from newest to oldest, truncated at the first column that is (to
+// 1e-12 of its norm) a combination of newer ones.  Thread 0 does the m x m
+// algebra.
+__global__ void __launch_bounds__(256) k_accel_solve(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
     __shared__ double tot[2 * kAccelMaxDepth];
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
@@ -1161,22 +1183,32 @@ __global__ void __launch_bounds__(64) k_accel_solve(const DeviceView *__restrict
     const int m = a.m;
     const int k = (int)a.scal[0];
     const int w = k < m ? k : m;
-    if (k > 0 && threadIdx.x < 2 * w) {
-        double t = 0.0;
-        for (int b = 0; b < a.nblk; ++b) t += a.part[(int64_t)b * 2 * kAccelMaxDepth + threadIdx.x];
-        tot[threadIdx.x] = t;
+    if (k > 0) {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int t = wv; t < 2 * w; t += 4) {
+            double x = 0.0;
+            for (int b = lane; b < a.nblk; b += 64) x += a.part[(int64_t)b * 2 * kAccelMaxDepth + t];
+            x = wave_sum(x);
+            if (lane == 0) tot[t] = x;
+        }
+    }
+    __syncthreads();
+    // the Gram matrix into LDS (one load per thread), its newest row and column replaced
+    __shared__ double H[kAccelMaxDepth * kAccelMaxDepth];
+    const int c = k > 0 ? (k - 1) % m : 0;
+    if (threadIdx.x < m * m) {
+        const int i = threadIdx.x / m, j = threadIdx.x % m;
+        double h = a.scal[1 + threadIdx.x];
+        if (k > 0 && j < w && i == c) h = tot[2 * j];
+        if (k > 0 && i < w && j == c) h = tot[2 * i];
+        H[threadIdx.x] = h;
+        a.scal[1 + threadIdx.x] = h;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    double *H = a.scal + 1;
-    double *gam = a.scal + 1 + m * m;
-    for (int j = 0; j < m; ++j) gam[j] = 0.0;
+    double gam[kAccelMaxDepth];
+    for (int j = 0; j < kAccelMaxDepth; ++j) gam[j] = 0.0;
     if (k > 0) {
-        const int c = (k - 1) % m;
-        for (int j = 0; j < w; ++j) {
-            H[c * m + j] = tot[2 * j];
-            H[j * m + c] = tot[2 * j];
-        }
         int ord[kAccelMaxDepth];
         for (int p = 0; p < w; ++p) ord[p] = ((c - p) % m + m) % m;   // newest first
         double L[kAccelMaxDepth][kAccelMaxDepth], y[kAccelMaxDepth];
@@ -1211,34 +1243,51 @@ __global__ void __launch_bounds__(64) k_accel_solve(const DeviceView *__restrict
             gam[ord[p]] = y[p];
         }
     }
+    for (int j = 0; j < m; ++j) a.scal[1 + m * m + j] = gam[j];
     a.scal[0] = k + 1;
 }
 
 // x_next = G - sum_j gamma_j dG_j into theta[cur] and ain_x.
+template <class T, int W>
+__device__ __forceinline__ void accel_mix_rows(const DeviceView &v, const WorkItem &it, const double *gam) {
+    const AccelWork &a = v.acc;
+    const int64_t N = v.N, NS = N + a.NR;
+    const T *dG = static_cast<const T *>(a.dG);
+    double *tn = theta_at(v, th_cur(v.state));
+    for (int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x; s < NS; s += (int64_t)it.c * blockDim.x) {
+        double d[W > 0 ? W : 1];
+#pragma unroll
+        for (int j = 0; j < W; ++j) d[j] = static_cast<double>(dG[j * NS + s]);
+        double x = a.Gprev[s];
+#pragma unroll
+        for (int j = 0; j < W; ++j) x -= gam[j] * d[j];
+        if (s < N) tn[s] = x;
+        else a.ain_x[s - N] = x;
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_accel_mix(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (v.state->done) return;
     const AccelWork &a = v.acc;
-    const int64_t N = v.N, NS = N + a.NR;
     const int m = a.m;
     const int k = (int)a.scal[0];   // steps done, this one included
     const int w = k - 1 < m ? k - 1 : m;
     double gam[kAccelMaxDepth];
 #pragma unroll
     for (int j = 0; j < kAccelMaxDepth; ++j) gam[j] = j < m ? a.scal[1 + m * m + j] : 0.0;
-    const T *dG = static_cast<const T *>(a.dG);
-    double *tn = theta_at(v, th_cur(v.state));
-    for (int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x; s < NS; s += (int64_t)it.c * blockDim.x) {
-        double x = a.Gprev[s];
-#pragma unroll
-        for (int j = 0; j < kAccelMaxDepth; ++j) {
-            if (j >= w) break;
-            x -= gam[j] * static_cast<double>(dG[j * NS + s]);
-        }
-        if (s < N) tn[s] = x;
-        else a.ain_x[s - N] = x;
+    switch (w) {
+        case 0: accel_mix_rows<T, 0>(v, it, gam); break;
+        case 1: accel_mix_rows<T, 1>(v, it, gam); break;
+        case 2: accel_mix_rows<T, 2>(v, it, gam); break;
+        case 3: accel_mix_rows<T, 3>(v, it, gam); break;
+        case 4: accel_mix_rows<T, 4>(v, it, gam); break;
+        case 5: accel_mix_rows<T, 5>(v, it, gam); break;
+        case 6: accel_mix_rows<T, 6>(v, it, gam); break;
+        case 7: accel_mix_rows<T, 7>(v, it, gam); break;
+        default: accel_mix_rows<T, 8>(v, it, gam); break;
     }
 }
 
@@ -1675,7 +1724,7 @@ void launch_accel_cols(const DeviceView *vs, const WorkItem *wk, int n, bool fp3
 
 void launch_accel_solve(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_accel_solve, dim3(n), dim3(64), 0, st, vs, wk);
+    hipLaunchKernelGGL(k_accel_solve, dim3(n), dim3(256), 0, st, vs, wk);
 }
 
 void launch_accel_mix(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
