@@ -11,5 +11,5 @@ tests/test_oracle_*.py.
 """
 from .solver import (OracleError, Result, Setup, accel_state, accel_unpack, anderson_next,  # noqa: F401
                      boundary_flows, boundary_inflow, diffusion_operator, divergence, energy_defect,
-                     equilibrium, fourier_guess, moments, prepare, solve, source, threads, transport,
-                     transport_systems)
+                     equilibrium, fourier_guess, lsq_weights, moments, prepare, reconstruct, reconstruct_fields,
+                     solve, solve_system_order2, source, threads, transport, transport_systems)

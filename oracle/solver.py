@@ -60,6 +60,8 @@ def _lib():
         lib.oracle_sweep_system.argtypes = [ctypes.c_int64, ctypes.c_int32, i64, d, d, d,
                                             ctypes.c_double, ctypes.c_double, d, d, d, d]
         lib.oracle_sweep_system.restype = ctypes.c_int
+        lib.oracle_sweep_all_sys.argtypes = lib.oracle_sweep_all.argtypes
+        lib.oracle_sweep_all_sys.restype = None
         lib.oracle_threads.argtypes = [ctypes.c_int]
         lib.oracle_threads.restype = ctypes.c_int
         _LIB = lib
@@ -248,18 +250,22 @@ def source(su: Setup):
     return su.Q[None, :] * su.C[:, None] / (su.C_tot * su.W)
 
 
-def boundary_inflow(su: Setup, e):
+def boundary_inflow(su: Setup, e, bdelta=None):
     """Inflow values on every boundary face for every (band, direction), from
     the previous iterate e (lagged), shape (B, D, NBF).  Only the entries with
     s_i . S_f < 0 are used.
       thermalizing: C theta_w / W
       specular:     e of the mirror direction at the owner cell
       diffuse:      sum_{out j} w_j (s_j.S) e_j / sum_{in k} w_k |s_k.S|
-      partial(p):   p * specular + (1 - p) * diffuse"""
+      partial(p):   p * specular + (1 - p) * diffuse
+    bdelta (B, D, NBF), optional: second-order increments of the outgoing
+    face values (the owner's value plus its reconstruction on the face)."""
     g = su.g
     B, D = len(su.C), len(su.w)
     NBF = len(g.bf_owner)
     eo = e[:, :, g.bf_owner]                     # (B, D, NBF) values at the owners
+    if bdelta is not None:
+        eo = eo + bdelta
     out = su.sdotS > 0                           # (NBF, D)
     inn = su.sdotS < 0
     wout = np.where(out, su.w[None, :] * su.sdotS, 0.0)          # (NBF, D)
@@ -283,9 +289,11 @@ def boundary_inflow(su: Setup, e):
     return inflow
 
 
-def transport(su: Setup, theta, inflow):
+def transport(su: Setup, theta, inflow, corr=None):
     """Solve every (band, direction) system for the given lattice temperature
-    and boundary inflow.  Returns e and per-volume outflow, shape (B, D, N)."""
+    and boundary inflow.  Returns e and per-volume outflow, shape (B, D, N).
+    corr (B, D, N), optional: an extra right-hand side per system (the
+    second-order scheme's deferred correction)."""
     g = su.g
     B, D, N = len(su.C), len(su.w), g.N
     rhs = np.ascontiguousarray(equilibrium(su, theta) / su.tau[:, None] + source(su))
@@ -297,14 +305,18 @@ def transport(su: Setup, theta, inflow):
     inflow = np.ascontiguousarray(inflow)
     s = np.ascontiguousarray(su.s)
     inv_tau = 1.0 / su.tau
-    _lib().oracle_sweep_all(N, g.F, B, D, len(g.bf_owner), _p(nbr, ctypes.c_int64), _p(S), _p(g.V), _p(s),
-                            _p(su.v), _p(inv_tau), _p(rhs), _p(inflow), _p(e), _p(outflux),
-                            _p(status, ctypes.c_int32))
+    args = (N, g.F, B, D, len(g.bf_owner), _p(nbr, ctypes.c_int64), _p(S), _p(g.V), _p(s), _p(su.v), _p(inv_tau))
+    if corr is None:
+        _lib().oracle_sweep_all(*args, _p(rhs), _p(inflow), _p(e), _p(outflux), _p(status, ctypes.c_int32))
+    else:
+        rhs = np.ascontiguousarray(rhs[:, None, :] + corr)
+        _lib().oracle_sweep_all_sys(*args, _p(rhs), _p(inflow), _p(e), _p(outflux), _p(status, ctypes.c_int32))
     if np.any(status == 2):
         raise MemoryError("oracle sweep allocation failed")
     for k in np.flatnonzero(status == 1):    # cyclic upwind graph: sparse direct solve
         b, i = divmod(int(k), D)
-        e[b, i], outflux[b, i] = _direct_system(su, b, i, rhs[b], inflow[b, i])
+        r = rhs[b] if corr is None else rhs[b, i]
+        e[b, i], outflux[b, i] = _direct_system(su, b, i, r, inflow[b, i])
     return e, outflux
 
 
@@ -373,13 +385,109 @@ def divergence(su: Setup, outflux):
     return np.einsum("b,i,bic->c", su.v, su.w, outflux)
 
 
-def boundary_flows(su: Setup, e, inflow):
+def boundary_flows(su: Setup, e, inflow, bdelta=None):
     """Heat leaving through every boundary face (positive outward):
-       sum_lambda sum_i w_i v_lambda (s_i . S_f) e_up."""
+       sum_lambda sum_i w_i v_lambda (s_i . S_f) e_up
+    (bdelta: second-order increments of the outgoing face values)."""
     g = su.g
     eo = e[:, :, g.bf_owner]
+    if bdelta is not None:
+        eo = eo + bdelta
     up = np.where((su.sdotS > 0).T[None, :, :], eo, inflow)    # (B, D, NBF)
     return np.einsum("b,i,fi,bif->f", su.v, su.w, su.sdotS, up)
+
+
+# ----------------------------------------------------------------------------
+# second-order upwind by deferred correction (an extension of the method's
+# first-order face values; the implicit sweep stays first order)
+# ----------------------------------------------------------------------------
+
+def lsq_weights(su: Setup):
+    """Least-squares cell gradients over the interior face neighbours:
+    G_c = sum_f w_cf (e_n(f) - e_c), with d_f = x_n(f) - x_c (cell centres),
+    M_c = sum_f d_f d_f^T and w_cf = M_c^-1 d_f in the mesh's dimension.  A
+    cell whose neighbour offsets do not span the dimension (smallest to largest
+    eigenvalue of M_c below 1e-8) has no gradient: w = 0, its faces stay first
+    order.  Returns (N, F, 3); cached on the setup."""
+    if "lsq" in su.L_cache:
+        return su.L_cache["lsq"]
+    g = su.g
+    dim = g.dim
+    inter = g.nbr >= 0
+    nbc = np.where(inter, g.nbr, 0)
+    d = np.where(inter[:, :, None], g.xc[nbc] - g.xc[:, None, :], 0.0)[:, :, :dim]
+    M = np.einsum("cfi,cfj->cij", d, d)
+    ev = np.linalg.eigvalsh(M)
+    ok = ev[:, 0] > 1e-8 * ev[:, -1]
+    Wt = np.zeros((g.N, g.F, 3))
+    Mi = np.linalg.inv(np.where(ok[:, None, None], M, np.eye(dim)[None]))
+    Wt[:, :, :dim] = np.einsum("cij,cfj->cfi", Mi, d) * ok[:, None, None]
+    su.L_cache["lsq"] = Wt
+    return Wt
+
+
+def reconstruct_fields(su: Setup, E, dirs):
+    """Second-order increments of the fields E (K, N) of the directions dirs
+    (K,): with the gradient G_c of each field, the face value seen from cell
+    c on its face f is e_c + G_c . (x_f - x_c).  Returns
+      div (K, N):     sum_f a_cf delta_f, the per-volume net outflow carried by
+                      the increments of the upwind side: outgoing faces
+                      (a_cf > 0) take the cell's own, incoming interior faces
+                      the neighbour's G_n . (x_f - x_n), boundary inflow none;
+      bdelta (K, NBF): G_owner . (x_f - x_owner) on every boundary face (the
+                      increment of its outgoing values)."""
+    g = su.g
+    Wt = lsq_weights(su)
+    inter = g.nbr >= 0
+    nbc = np.where(inter, g.nbr, 0)
+    de = np.where(inter[None], E[:, nbc] - E[:, :, None], 0.0)          # (K, N, F)
+    G = np.einsum("kcf,cfx->kcx", de, Wt)                                 # (K, N, 3)
+    d_own = np.einsum("kcx,cfx->kcf", G, g.xf - g.xc[:, None, :])        # own side of every face
+    d_nbr = np.einsum("kcfx,cfx->kcf", G[:, nbc], g.xf - g.xc[nbc])       # neighbour's side
+    a = np.einsum("cfx,kx->kcf", g.S, su.s[dirs]) / g.V[None, :, None]
+    div = np.where(a > 0, a * d_own, np.where((a < 0) & inter[None], a * d_nbr, 0.0)).sum(axis=2)
+    bdelta = d_own[:, g.bf_owner, g.bf_local]
+    return div, bdelta
+
+
+def reconstruct(su: Setup, e):
+    """reconstruct_fields for every (band, direction) system of e (B, D, N):
+    div (B, D, N) and bdelta (B, D, NBF)."""
+    B, D = e.shape[0], e.shape[1]
+    div = np.empty(e.shape)
+    bdelta = np.empty((B, D, len(su.g.bf_owner)))
+    for b in range(B):
+        div[b], bdelta[b] = reconstruct_fields(su, e[b], np.arange(D))
+    return div, bdelta
+
+
+def solve_system_order2(su: Setup, b, i, rhs, inflow_bi, tol=1e-13, max_iter=10000):
+    """One (band, direction) system with second-order face values, by
+    deferred correction: e^{k+1} = A1^-1 (rhs - v div(e^k)), A1 the
+    first-order upwind matrix (exact sweep).  Returns (e, iterations)."""
+    g = su.g
+    N = g.N
+    nbr = np.ascontiguousarray(g.nbr, np.int64)
+    S = np.ascontiguousarray(g.S)
+    s = np.ascontiguousarray(su.s[i])
+    inf = np.ascontiguousarray(inflow_bi, float)
+    e = np.zeros(N)
+    flux = np.empty(N)
+    for k in range(1, max_iter + 1):
+        div, _ = reconstruct_fields(su, e[None, :], np.array([i]))
+        r = np.ascontiguousarray(rhs - su.v[b] * div[0])
+        new = np.empty(N)
+        st = _lib().oracle_sweep_system(N, g.F, _p(nbr, ctypes.c_int64), _p(S), _p(g.V), _p(s), float(su.v[b]),
+                                        float(1.0 / su.tau[b]), _p(r), _p(inf), _p(new), _p(flux))
+        if st == 1:
+            new, _ = _direct_system(su, b, i, r, inf)
+        elif st != 0:
+            raise MemoryError("oracle sweep allocation failed")
+        ch = np.max(np.abs(new - e)) / max(np.max(np.abs(new)), 1e-300)
+        e = new
+        if ch <= tol:
+            return e, k
+    raise OracleError("deferred correction did not converge")
 
 
 # ----------------------------------------------------------------------------
@@ -462,7 +570,7 @@ def energy_defect(su: Setup, flows):
 
 def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_tol=None,
           setup: Setup = None, keep_e=False, verbose=False, time_limit=None, dsa_kappa="consistent",
-          accel=None, depth=5):
+          accel=None, depth=5, order=1):
     """Iterate to the steady state.
 
     scheme: "sequential" (Eq. (5)), "synthetic" (default; the DSA reading of
@@ -480,6 +588,13 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
     lagged inflow of the reflective walls (accel_state); the converged fields
     are those of the plain iteration.
 
+    order=2: second-order upwind face values (reconstruct_fields) by deferred
+    correction: each sweep keeps the first-order implicit operator and moves
+    the reconstruction increments of the previous distribution to its
+    right-hand side; the boundary conditions, the divergence of the synthetic
+    correction and the boundary flows use the same second-order face values.
+    At the fixed point the discrete equations are the second-order ones.
+
     Stops when max|theta^{n+1} - theta^n| / max|theta^{n+1}| <= tol and, if
     defect_tol is given, the energy defect is <= defect_tol; theta^{n+1} is
     the image of theta^n under one iteration (before any acceleration)."""
@@ -495,20 +610,32 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
     e = np.broadcast_to(equilibrium(su, theta)[:, None, :], (len(su.C), len(su.w), su.g.N))
     if accel not in (None, "anderson"):
         raise OracleError(f"unknown outer acceleration {accel}")
+    if order not in (1, 2):
+        raise OracleError(f"unknown spatial order {order}")
+    if order == 2 and accel is not None:
+        raise OracleError("outer acceleration of the second-order scheme is not provided")
     hist = []
     res = np.inf
     it = 0
-    inflow = boundary_inflow(su, e)
-    inflow_used, theta_new = inflow, theta
+    div_o = bd_o = None
+    if order == 2:
+        e = np.ascontiguousarray(e)
+        div_o, bd_o = reconstruct(su, e)
+    inflow = boundary_inflow(su, e, bd_o)
+    inflow_used, theta_new, bd_used = inflow, theta, bd_o
     X_hist, G_hist = [], []
     while it < max_iter:
-        e, outflux = transport(su, theta, inflow)
+        corr = None if order == 1 else -su.v[:, None, None] * div_o
+        e, outflux = transport(su, theta, inflow, corr)
+        if order == 2:
+            outflux = outflux + div_o
+        bd_used = bd_o
         theta_seq, th_energy, q = moments(su, e)
         if scheme == "sequential":
             theta_new = theta_seq
         else:
             r = su.Q - divergence(su, outflux)
-            flows = boundary_flows(su, e, inflow)
+            flows = boundary_flows(su, e, inflow, bd_used)
             refl = su.bc_kind != 0
             np.add.at(r, su.g.bf_owner[refl], flows[refl] / su.g.V[su.g.bf_owner[refl]])
             delta = diffusion_operator(su, dsa_kappa)[1].solve(su.g.V * r)
@@ -520,7 +647,7 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
         theta_prev, inflow_used = theta, inflow
         theta = theta_new
         it += 1
-        flows = boundary_flows(su, e, inflow_used)
+        flows = boundary_flows(su, e, inflow_used, bd_used)
         dfc = energy_defect(su, flows)
         hist.append((res, dfc))
         if verbose:
@@ -529,7 +656,9 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
             break
         if time_limit is not None and time.perf_counter() - t0 > time_limit:
             break
-        inflow = boundary_inflow(su, e)
+        if order == 2:
+            div_o, bd_o = reconstruct(su, e)
+        inflow = boundary_inflow(su, e, bd_o)
         if accel == "anderson" and depth > 0:
             # x_n = (theta^n, inflow^n) -> G(x_n) = (theta^{n+1}, inflow from e^{n+1})
             X_hist.append(accel_state(su, theta_prev, inflow_used))
@@ -538,7 +667,7 @@ def solve(problem, scheme=None, tol=1e-13, max_iter=100000, T_init=None, defect_
             theta, inflow = accel_unpack(su, anderson_next(X_hist, G_hist), inflow)
     inflow = inflow_used
     theta = theta_new
-    flows = boundary_flows(su, e, inflow)
+    flows = boundary_flows(su, e, inflow, bd_used)
     by_tag = {int(t): float(np.sum(flows[su.g.bf_tag == t])) for t in np.unique(su.g.bf_tag)}
     return Result(T_lattice=su.T_ref + theta, T=su.T_ref + th_energy, q=q, theta_L=theta,
                   iterations=it, residual=res, energy_defect=energy_defect(su, flows),

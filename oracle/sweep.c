@@ -139,6 +139,24 @@ void oracle_sweep_all(int64_t N, int32_t F, int32_t B, int32_t D, int64_t NBF,
 }
 
 /*
+ * The same with a right-hand side per system, rhs[(b*D + i)*N + c] (the
+ * second-order scheme's deferred correction differs between directions).
+ */
+void oracle_sweep_all_sys(int64_t N, int32_t F, int32_t B, int32_t D, int64_t NBF,
+                          const int64_t *nbr, const double *S, const double *V,
+                          const double *dirs, const double *vel, const double *inv_tau, const double *rhs,
+                          const double *inflow, double *e, double *outflux, int32_t *status)
+{
+    int64_t nsys = (int64_t)B * D;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nsys; ++k) {
+        int32_t b = (int32_t)(k / D), i = (int32_t)(k % D);
+        status[k] = oracle_sweep_system(N, F, nbr, S, V, dirs + 3 * i, vel[b], inv_tau[b],
+                                        rhs + k * N, inflow + k * NBF, e + k * N, outflux + k * N);
+    }
+}
+
+/*
  * Threads of the OpenMP loop above: n > 0 sets them, every call returns the
  * number the next loop will use (the CPU baseline reports it).
  */
