@@ -155,6 +155,19 @@ typedef struct {
     int32_t refine;          /* mixed precision only (default 1): when the FP32 iteration stops
                                 improving (no 2% residual gain in 64 iterations) before reaching
                                 tol, the solve continues with FP64 sweeps from where it stands */
+    int32_t spatial_order;   /* 1 (default): first-order upwind face values.  2: second order: the
+                                upwind side's value reconstructed linearly on the face with the
+                                least-squares gradient of its cell over the interior face
+                                neighbours (first order in cells whose neighbours do not span the
+                                dimension), in the transport solve, the boundary conditions and the
+                                heat flows; solved by deferred correction (each sweep keeps the
+                                first-order operator and moves the previous distribution's
+                                reconstruction to its right-hand side).  The deferred correction
+                                converges where it contracts (structured meshes); where it does not
+                                (ballistic bands on unstructured tetrahedra or triangles) the solve
+                                ends with NBTE_ERR_DIVERGED.  Holds five more distribution-sized
+                                arrays; not combined with nbte_tuning.accel_depth > 0
+                                (NBTE_ERR_INVALID_ARG). */
 } nbte_solve_opts;
 
 /* Fill opts with the defaults listed above. */

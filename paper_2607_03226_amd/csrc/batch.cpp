@@ -88,6 +88,8 @@ nbte_status nbte_batch_admit(nbte_batch *b, nbte_problem *p, const double *Q_cel
         int64_t need = 0;
         const nbte_status fst = nbte_problem_footprint(p, o->precision, &need);
         if (fst != NBTE_OK) throw Error(fst, nbte_last_error());
+        if (o->spatial_order == 2)   // the second-order arrays on top of the first-order footprint
+            need += p->state_bytes(o->precision, 2) - p->state_bytes(o->precision, 1);
         if (b->budget > 0 && b->in_use + need > b->budget)
             throw Error(NBTE_ERR_OUT_OF_MEMORY, "batch budget exceeded: " + std::to_string(b->in_use) + " + " +
                                                     std::to_string(need) + " > " + std::to_string(b->budget) + " bytes");

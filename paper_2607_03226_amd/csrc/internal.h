@@ -173,6 +173,13 @@ struct BoundaryPlan {
 BoundaryPlan build_boundary_plan(const Mesh &m, const Quadrature &q,
                                  const std::vector<nbte_boundary> &bcs, double T_ref);
 
+// Least-squares cell gradients of the second-order scheme: weights w_cf
+// (N*F*3) with G_c = sum_f w_cf (e_n(f) - e_c) over the interior face
+// neighbours (offsets d = x_n - x_c of the vertex-average centres,
+// w = (sum d d^T)^-1 d in the mesh's dimension); zero for a cell whose
+// offsets do not span the dimension (eigenvalue ratio below 1e-8).
+std::vector<double> build_lsq_weights(const Mesh &m);
+
 // Diffusion operator of the synthetic correction (V-weighted, SPD) in CSR.
 struct DiffusionOperator {
     std::vector<int32_t> row_ptr, col;

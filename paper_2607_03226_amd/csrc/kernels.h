@@ -38,7 +38,8 @@ struct SolveState {
     double best;          // smallest residual so far (since the last controls were set)
     int32_t since;        // iterations since best improved by 2%
     int32_t pad;
-    unsigned long long maxbuf[2];   // running maxima of the update (ordered bit patterns)
+    unsigned long long maxbuf[3];   // running maxima (ordered bit patterns): of the update, of the new
+                                    // theta, and (second order) of the distribution in temperature units
 };
 enum { NBTE_DONE_CONVERGED = 1, NBTE_DONE_MAX_ITER = 2, NBTE_DONE_DIVERGED = 3, NBTE_DONE_STALLED = 4 };
 
@@ -149,6 +150,19 @@ struct DeviceView {
     SolveState NBTE_G *state;
     PcgWork pcg;
     AccelWork acc;
+    // second-order face values (order 2): least-squares weights, geometry, the
+    // gradients of the last distribution, the deferred correction of the
+    // coming sweep and the increments of the outgoing boundary face values
+    int32_t order;
+    const double NBTE_G *lsq;      // N*F*3: G_c = sum_f lsq_cf (e_n(f) - e_c)
+    const double NBTE_G *Sv;       // N*F*3 outward area vectors
+    const double NBTE_G *xf;       // N*F*3 face centroids
+    const double NBTE_G *xc;       // N*3 cell centres (vertex average)
+    const int32_t NBTE_G *bf_local;// NBF: the boundary face's index among its owner's faces
+    void NBTE_G *grad;             // 3 planes of D*N*B, storage type: gradient components per system
+    void NBTE_G *corr;             // D*N*B in stream order: -v sum_f a delta_f of the coming sweep
+    void NBTE_G *bdelta;           // 2 slots of NBF*D*B: increments of the outgoing face values;
+                                   // slot m & 1 belongs to the distribution of sweep m - 1
 };
 
 // One workgroup's share of a launch: the solve (index into the descriptor
@@ -183,6 +197,13 @@ void launch_stage(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hi
 // mode 2: at prepare: the outgoing sums of the initial distribution
 void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int mode, hipStream_t st);
 void launch_post(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
+// Second-order scheme, after a sweep (phase 0), at prepare (phase 1) or after
+// the rotation of a stopped iteration (phase 2): gradients of the stored
+// distribution (items (solve, -, b, nblk), grid-stride over D*N*B), then the
+// deferred correction of the next sweep (items (solve, 0, b, nblk)) and the
+// outgoing increments of the boundary faces (items (solve, 1, b, nblk)).
+void launch_grad(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int phase, hipStream_t st);
+void launch_recon(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int phase, hipStream_t st);
 void launch_wall_rhs(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 // Anderson step after an iteration's finish (solves with acc.m > 0; each
@@ -207,7 +228,7 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
 // values spilled to HBM (LDS budget too small).  one: one lane per cell
 // (bpl = bands per block, up to 8); otherwise bpl is 1, 2 or 4.
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
-                  int block, size_t lds_bytes, hipStream_t st);
+                  int block, size_t lds_bytes, hipStream_t st, bool order2 = false);
 size_t sweep_lds_bytes(int max_levels, int gring, int lstride, int slots, int elem_bytes);
 
 // Dynamic LDS of a sweep workgroup, in elements of the storage type (es

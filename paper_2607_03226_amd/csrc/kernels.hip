@@ -44,6 +44,11 @@ __device__ __forceinline__ double NBTE_G *theta_spare(const DeviceView &v) {
     return theta_at(v, (th_cur(v.state) + 2) % 3);
 }
 
+// bit pattern of a non-negative double: ordered like the values (atomic maxima)
+__device__ __forceinline__ unsigned long long dbits(double x) {
+    return static_cast<unsigned long long>(__double_as_longlong(x));
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
     return x;
@@ -216,6 +221,11 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
     const double p = v.bf_p[bf];
     const double iw = 1.0 / v.win[bf];
     const int32_t *mir = v.mirror + bf * D;
+    // second order: the owner's outgoing face values carry their increments
+    // (slot of the distribution this stage reads)
+    const T *bd = v.order == 2 ? static_cast<const T *>(v.bdelta) + (int64_t)(v.state->iterations & 1) * v.NBF * D * B +
+                                     bf * D * B
+                               : nullptr;
     double jin = 0.0;
     for (int l0 = 0; l0 < B; l0 += BL) {
         const int lam = l0 + ml;
@@ -230,7 +240,7 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
                 const int mi = mir[i] >= 0 ? mir[i] : 0;   // outgoing directions have no mirror entry
-                const double em = ld(g, ((int64_t)mi * N + c) * B + lam) + eq;
+                const double em = ld(g, ((int64_t)mi * N + c) * B + lam) + eq + (bd ? ld(bd, (int64_t)mi * B + lam) : 0.0);
                 const double e = (1.0 - p) * diff + p * em;
                 if (r >= 0) {
                     gv[(int64_t)r * B + lam] = static_cast<T>(e - eqc);
@@ -528,9 +538,19 @@ __device__ __forceinline__ void gstore_bands(T NBTE_G *base, uint32_t k, const T
 __device__ __forceinline__ double quot(double a, double b) { return a / b; }
 __device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
-template <class T, int MI, int BPL>
+// The second-order scheme's deferred correction of a record's bands
+// (requested with the record; empty for the first-order kernels).
+template <class T, int BPL, bool ON>
+struct CorrVals {
+    T v[BPL];
+};
+template <class T, int BPL>
+struct CorrVals<T, BPL, false> {};
+
+template <class T, int MI, int BPL, bool SO2 = false>
 __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const DeviceView &v, const BandConst<T, BPL> &bc,
-                                           T NBTE_G *gi, int64_t base, int b0, int lane, int nb_here) {
+                                           T NBTE_G *gi, int64_t base, int b0, int lane, int nb_here,
+                                           const CorrVals<T, BPL, SO2> &cv = CorrVals<T, BPL, SO2>{}) {
     const int B = v.B;
     const T NBTE_G *gval = static_cast<const T NBTE_G *>(v.gval);
     // this lane's bands [lofs, lofs + BPL) of the block, nv of them real;
@@ -562,7 +582,9 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
             gain += r.cf[j] * up;
         }
         const T vel = bc.vel[jb];
-        out[jb] = quot(r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc), bc.itau[jb] + vel * r.sout);
+        T num = r.q * bc.src[jb] + vel * (gain + bc.cw[jb] * r.dc);
+        if constexpr (SO2) num += cv.v[jb];
+        out[jb] = quot(num, bc.itau[jb] + vel * r.sout);
     }
     // one LDS access and one store per 16 bytes, as in the LDS-only path
     lds_write_bands<T, BPL>(r.mine + lofs, out);   // own slot, or the scratch block
@@ -649,7 +671,7 @@ struct LevelWindow {
 // keeps its registers while its loads are in flight (moving it would force
 // the wait).
 // --------------------------------------------------------------------------
-template <class T, int MI, int BPL, int MODE, bool ONE>
+template <class T, int MI, int BPL, int MODE, bool ONE, bool SO2 = false>
 __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs,
                                                 const WorkItem *__restrict__ wk) {
     // ONE: one lane per cell (it sweeps all BPL bands of the block), so the
@@ -706,6 +728,9 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     }
     const SweepStreams S = sweep_streams<T>(v, base, MI);
     const __amdgpu_buffer_rsrc_t rg = make_rsrc(v.gval, (uint64_t)max<int64_t>(v.NBF, 1) * v.D * B * sizeof(T));
+    // second order: this direction's corrections in stream order (N B values)
+    const __amdgpu_buffer_rsrc_t rcor =
+        SO2 ? make_rsrc(static_cast<const T NBTE_G *>(v.corr) + base * B, (uint64_t)N * B * sizeof(T)) : rg;
     // the ghost entries this thread moves: entry e = threadIdx.x + m blockDim.x
     // of a level is band gl[m] of the level's ghost gq[m]
     int gq[kGhostPerThread], gl[kGhostPerThread];
@@ -740,6 +765,7 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     struct Set {
         SweepRec<T, MI> r;
         Ghosts h;
+        CorrVals<T, BPL, SO2> cv;
     };
     auto ghost_load = [&](Ghosts &h, int g0, int ne) {
         // branch-free like load_rec: entries past the level read element 0.
@@ -783,6 +809,13 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     auto fetch = [&](Set &st) {
         const bool live = lf < nlev;
         load_rec(st.r, S, kf + slot, live ? kendf : 0);
+        if constexpr (SO2) {
+            // past-the-end records read position 0, like their stream loads
+            const uint32_t at = (live && kf + slot < kendf) ? (uint32_t)(kf + slot) : 0u;
+#pragma unroll
+            for (int jb = 0; jb < BPL; ++jb)
+                st.cv.v[jb] = bload<T>(rcor, (at * (uint32_t)B + (uint32_t)(b0 + lofs + jb)) * (uint32_t)sizeof(T), 0);
+        }
         ghost_load(st.h, g0f, (live && firstf) ? min(gnf, gcap) * bands_per_block : 0);
         if (live) {
             kf += nslots;
@@ -812,7 +845,7 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
         if constexpr (MODE == kModeLds)
             sweep_cell_lds<T, MI, BPL>(cur.r, bc, gi, B, b0, lofs, nv, vst, lay.trash_off);
         else if (cur.r.ok)
-            sweep_cell<T, MI, BPL>(cur.r, v, bc, gi, base, b0, lane, nb_here);
+            sweep_cell<T, MI, BPL, SO2>(cur.r, v, bc, gi, base, b0, lane, nb_here, cur.cv);
         kc += nslots;
         if (lc < nlev && kc >= kendc) {   // level done
             ++lc;
@@ -849,6 +882,117 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
 #undef gp
 
 // --------------------------------------------------------------------------
+// second-order face values by deferred correction
+//
+// The face value of a (band, direction) system on face f is the upwind side's
+// e_U + G_U . (x_f - x_U), G the least-squares cell gradient of the system's
+// last distribution.  The sweep keeps the first-order operator and takes
+//   corr_c = -v sum_f a_cf delta_f     (delta_f = G_U . (x_f - x_U); boundary
+//                                       inflow faces have none)
+// as an extra right-hand side, from the previous distribution.  phase 0: after
+// a sweep (distribution relative to theta[cur]; increments into slot
+// (iterations + 1) & 1); phase 1: at prepare (theta[cur] = theta^0, slot 0);
+// phase 2: after the rotation of a stopped iteration (theta[prev]; slot
+// iterations & 1).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ const double *recon_theta(const DeviceView &v, int phase) {
+    return phase == 2 ? theta_prev(v) : theta_cur(v);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_grad(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                              int phase) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (phase == 0 && v.state->done) return;
+    const double *th = recon_theta(v, phase);
+    const int64_t N = v.N;
+    const int B = v.B, F = v.F;
+    const int64_t total = (int64_t)v.D * N * B;
+    const T *g = static_cast<const T *>(v.g);
+    T *gr = static_cast<T *>(v.grad);
+    for (int64_t t = (int64_t)it.b * blockDim.x + threadIdx.x; t < total; t += (int64_t)it.c * blockDim.x) {
+        const int lam = (int)(t % B);
+        const int64_t ic = t / B;
+        const int64_t c = ic % N, i = ic / N;
+        const double cw = v.Cw[lam];
+        const double gc = ld(g, t), thc = th[c];
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int f = 0; f < F; ++f) {
+            const int32_t n = v.nbr[c * F + f];
+            if (n < 0) continue;
+            const double d = (ld(g, (i * N + n) * B + lam) - gc) + cw * (th[n] - thc);
+            const double *w = v.lsq + (c * F + f) * 3;
+            gx += w[0] * d;
+            gy += w[1] * d;
+            gz += w[2] * d;
+        }
+        gr[t] = static_cast<T>(gx);
+        gr[total + t] = static_cast<T>(gy);
+        gr[2 * total + t] = static_cast<T>(gz);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ double grad_dot(const T *gr, int64_t total, int64_t at, const double *x, const double *y) {
+    return ld(gr, at) * (x[0] - y[0]) + ld(gr, total + at) * (x[1] - y[1]) + ld(gr, 2 * total + at) * (x[2] - y[2]);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_recon(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk,
+                                               int phase) {
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (phase == 0 && v.state->done) return;
+    const int64_t N = v.N;
+    const int B = v.B, F = v.F, D = v.D;
+    const int64_t total = (int64_t)D * N * B;
+    const T *gr = static_cast<const T *>(v.grad);
+    if (it.a == 0) {
+        // the correction of every stream entry (position p = i N + k of direction i)
+        T *corr = static_cast<T *>(v.corr);
+        for (int64_t t = (int64_t)it.b * blockDim.x + threadIdx.x; t < total; t += (int64_t)it.c * blockDim.x) {
+            const int lam = (int)(t % B);
+            const int64_t pos = t / B;
+            const int64_t i = pos / N;
+            const int64_t c = v.p_cell[pos];
+            const double *sd = v.dirs + 3 * i;
+            const double *xc = v.xc + 3 * c;
+            const double iv = 1.0 / v.V[c];
+            double acc = 0.0;
+            for (int f = 0; f < F; ++f) {
+                const double *S = v.Sv + (c * F + f) * 3;
+                const double a = (sd[0] * S[0] + sd[1] * S[1] + sd[2] * S[2]) * iv;
+                const double *xf = v.xf + (c * F + f) * 3;
+                if (a > 0.0) {
+                    acc += a * grad_dot(gr, total, (i * N + c) * B + lam, xf, xc);
+                } else if (a < 0.0) {
+                    const int32_t n = v.nbr[c * F + f];
+                    if (n >= 0) acc += a * grad_dot(gr, total, (i * N + n) * B + lam, xf, v.xc + 3 * (int64_t)n);
+                }
+            }
+            corr[t] = static_cast<T>(-v.vel[lam] * acc);
+        }
+    } else {
+        // increments of the outgoing values on the boundary faces
+        const int64_t nb = v.NBF * D * B;
+        const int slot = phase == 1 ? 0 : (phase == 0 ? (v.state->iterations + 1) & 1 : v.state->iterations & 1);
+        T *bd = static_cast<T *>(v.bdelta) + (int64_t)slot * nb;
+        for (int64_t t = (int64_t)it.b * blockDim.x + threadIdx.x; t < nb; t += (int64_t)it.c * blockDim.x) {
+            const int lam = (int)(t % B);
+            const int64_t fi = t / B;
+            const int64_t bf = fi / D, i = fi % D;
+            double x = 0.0;
+            if (v.sdotS[fi] > 0.0) {
+                const int64_t c = v.bf_owner[bf];
+                x = grad_dot(gr, total, (i * N + c) * B + lam, v.xf + (c * F + v.bf_local[bf]) * 3, v.xc + 3 * c);
+            }
+            bd[t] = static_cast<T>(x);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // net heat flow through each boundary face: one wave per face
 //   J_f = sum_l v_l sum_i w_i (s_i . S_f) e
 // with e the owner's value for outgoing and the inflow for incoming directions
@@ -875,6 +1019,23 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
     const T *g = static_cast<const T *>(v.g);
     const T *gv = static_cast<const T *>(v.gval);
     const double *sd = v.sdotS + bf * D;
+    // second order: increments of the outgoing face values.  The net flow
+    // takes those the sweep used (mode 0: the slot of the sweep's own
+    // correction; mode 1, after the rotation: the last sweep's), the outgoing
+    // sums of the next boundary stage those of the new distribution (mode 0:
+    // the slot the reconstruction after the sweep wrote; mode 2: slot 0, the
+    // initial distribution)
+    const T *bj = nullptr, *bs = nullptr;
+    if (v.order == 2) {
+        const T *bd = static_cast<const T *>(v.bdelta);
+        const int64_t slot = (int64_t)v.NBF * D * B;
+        const int it = v.state->iterations;
+        if (mode == 0) bj = bd + (it & 1) * slot, bs = bd + ((it + 1) & 1) * slot;
+        else if (mode == 1) bj = bd + ((it + 1) & 1) * slot;
+        else bs = bd;
+        if (bj) bj += bf * D * B;
+        if (bs) bs += bf * D * B;
+    }
     const int BL = B < 64 ? B : 64, JG = 64 / BL;
     const int jg = lane / BL, ml = lane - jg * BL;
     double jsum = 0.0;
@@ -883,7 +1044,7 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
         const bool on = jg < JG && lam < B;
         const int lc = on ? lam : 0;
         const double cwt = v.Cw[lc] * th;
-        double sum = 0.0;
+        double sum = 0.0, sumj = 0.0;
         if (on) {
             if (mode == 1) {
                 // every direction: the inflow row of an incoming one, the
@@ -891,8 +1052,17 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
                 for (int i = jg; i < D; i += JG) {
                     const int32_t row = v.in_row[bf * D + i];
                     const T *src = row >= 0 ? gv + (int64_t)row * B : g + ((int64_t)i * N + c) * B;
-                    const double e = ld(src, lc) + cwt;
+                    double e = ld(src, lc) + cwt;
+                    if (bj && row < 0) e += ld(bj, (int64_t)i * B + lc);
                     sum += (row >= 0 || sd[i] > 0.0) ? v.w[i] * sd[i] * e : 0.0;
+                }
+                sumj = sum;
+            } else if (v.order == 2) {
+                for (int i = jg; i < D; i += JG) {
+                    const double e = ld(g, ((int64_t)i * N + c) * B + lc) + cwt;
+                    const double wsd = sd[i] > 0.0 ? v.w[i] * sd[i] : 0.0;
+                    sum += wsd * (e + (bs ? ld(bs, (int64_t)i * B + lc) : 0.0));
+                    sumj += wsd * (e + (bj ? ld(bj, (int64_t)i * B + lc) : 0.0));
                 }
             } else {
                 // outgoing directions: the owner's value is read for every
@@ -902,13 +1072,17 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
                     const double e = ld(g, ((int64_t)i * N + c) * B + lc) + cwt;
                     sum += sd[i] > 0.0 ? v.w[i] * sd[i] * e : 0.0;
                 }
+                sumj = sum;
             }
         }
-        double t = 0.0;
-        for (int k = 0; k < JG; ++k) t += __shfl(sum, k * BL + ml);
+        double t = 0.0, tj = 0.0;
+        for (int k = 0; k < JG; ++k) {
+            t += __shfl(sum, k * BL + ml);
+            tj += __shfl(sumj, k * BL + ml);
+        }
         if (on && jg == 0) {
             if (mode != 1) v.bsum[bf * B + lam] = t;
-            jsum += v.vel[lam] * t;
+            jsum += v.vel[lam] * tj;
         }
     }
     jsum = wave_sum(jsum);
@@ -946,9 +1120,14 @@ __device__ __forceinline__ void moments_block(const DeviceView &v, int64_t blk) 
     const int B = v.B, D = v.D;
     const T *g = static_cast<const T *>(v.g);
     double a_tau = 0, a_w = 0, qx = 0, qy = 0, qz = 0;
+    double gmax = 0.0;   // second order: largest |g| W / C, the divergence watch of the deferred correction
     if (c < N) {
         for (int lam = lane; lam < B; lam += lpc) {
             double sw = 0, s_x = 0, s_y = 0, s_z = 0;
+            if (v.order == 2) {
+                const double icw = 1.0 / v.Cw[lam];
+                for (int i = 0; i < D; ++i) gmax = fmax(gmax, fabs(ld(g, ((int64_t)i * N + c) * B + lam)) * icw);
+            }
             // independent loads, eight directions in flight (summation order unchanged)
 #pragma unroll 8
             for (int i = 0; i < D; ++i) {
@@ -972,6 +1151,11 @@ __device__ __forceinline__ void moments_block(const DeviceView &v, int64_t blk) 
         qx += __shfl_xor(qx, off);
         qy += __shfl_xor(qy, off);
         qz += __shfl_xor(qz, off);
+    }
+    if (v.order == 2) {
+        if (!(gmax <= 1e300)) gmax = INFINITY;
+        for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(&v.state->maxbuf[2], dbits(gmax));
     }
     if (c < N && lane == 0) {
         const double th = theta_cur(v)[c];
@@ -1022,9 +1206,6 @@ __global__ void __launch_bounds__(256) k_wall_rhs(const DeviceView *__restrict__
     }
 }
 
-__device__ __forceinline__ unsigned long long dbits(double x) {
-    return static_cast<unsigned long long>(__double_as_longlong(x));
-}
 
 // theta_new = base + delta: sequential base = theta_seq (Eq. (5)); synthetic
 // base = theta_seq + correction (Eq. (12)); the literal variant adds the
@@ -1064,10 +1245,12 @@ __global__ void k_finish(const DeviceView *__restrict__ vs, const WorkItem *__re
     if (s->done) return;
     const double md = __longlong_as_double((long long)s->maxbuf[0]);
     const double mt = __longlong_as_double((long long)s->maxbuf[1]);
+    const double mg = __longlong_as_double((long long)s->maxbuf[2]);
     const double res = mt > 0.0 ? md / mt : 0.0;
     s->residual = res;
     s->maxbuf[0] = 0ull;
     s->maxbuf[1] = 0ull;
+    s->maxbuf[2] = 0ull;
     s->iterations += 1;
     s->rot = (s->rot + 1) % 3;
     if (res < 0.98 * s->best) {
@@ -1076,7 +1259,13 @@ __global__ void k_finish(const DeviceView *__restrict__ vs, const WorkItem *__re
     } else {
         s->since += 1;
     }
-    if (!(res <= 1e300)) s->done = NBTE_DONE_DIVERGED;
+    // a relative update above 1e6 cannot come from a contracting iteration
+    // (a non-contracting deferred correction grows geometrically)
+    // second order: a distribution whose departure from equilibrium exceeds the
+    // temperature scale by 1e6 has left any contracting iteration (the
+    // deferred correction's growing modes may have no collision moment, so
+    // theta alone would not show them)
+    if (!(res <= 1e300) || (mt > 0.0 && res > 1e6) || !(mg <= 1e6 * mt)) s->done = NBTE_DONE_DIVERGED;
     else if (s->stop && res <= s->tol) s->done = NBTE_DONE_CONVERGED;
     else if (s->stop && s->iterations >= s->max_iter) s->done = NBTE_DONE_MAX_ITER;
     else if (s->stop && s->patience > 0 && s->since >= s->patience) s->done = NBTE_DONE_STALLED;
@@ -1671,6 +1860,19 @@ void dispatch_sweep_mi(const DeviceView *vs, const WorkItem *wk, int n, int maxi
     else dispatch_sweep_bpl<T, 5, MODE>(vs, wk, n, bpl, one, block, lds, st);
 }
 
+// second-order kernels: the general mode (LDS, ghosts and spilled values
+// from HBM) with several lanes per cell, up to four bands per lane
+template <class T, int MI>
+void dispatch_sweep_so2(const DeviceView *vs, const WorkItem *wk, int n, int bpl, int block, size_t lds,
+                        hipStream_t st) {
+    dim3 grid(n);
+    switch (bpl) {
+        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, kModeSpill, false, true>), grid, dim3(block), lds, st, vs, wk); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, kModeSpill, false, true>), grid, dim3(block), lds, st, vs, wk); break;
+        default: hipLaunchKernelGGL((k_sweep<T, MI, 4, kModeSpill, false, true>), grid, dim3(block), lds, st, vs, wk); break;
+    }
+}
+
 template <class T>
 void dispatch_sweep(const DeviceView *vs, const WorkItem *wk, int n, int maxin, int bpl, bool one, int mode,
                     int block, size_t lds, hipStream_t st) {
@@ -1698,6 +1900,18 @@ void launch_flux(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int
     if (n <= 0) return;
     if (fp32) hipLaunchKernelGGL(k_flux<float>, dim3(n), dim3(256), 0, st, vs, wk, mode);
     else hipLaunchKernelGGL(k_flux<double>, dim3(n), dim3(256), 0, st, vs, wk, mode);
+}
+
+void launch_grad(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int phase, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_grad<float>, dim3(n), dim3(256), 0, st, vs, wk, phase);
+    else hipLaunchKernelGGL(k_grad<double>, dim3(n), dim3(256), 0, st, vs, wk, phase);
+}
+
+void launch_recon(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int phase, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_recon<float>, dim3(n), dim3(256), 0, st, vs, wk, phase);
+    else hipLaunchKernelGGL(k_recon<double>, dim3(n), dim3(256), 0, st, vs, wk, phase);
 }
 
 void launch_post(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
@@ -1745,9 +1959,20 @@ size_t sweep_lds_bytes(int max_levels, int gring, int ls, int slots, int es) {
 }
 
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
-                  int block, size_t lds_bytes, hipStream_t st) {
+                  int block, size_t lds_bytes, hipStream_t st, bool order2) {
     if (n <= 0) return;
     if (bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8) bpl = 1;
+    if (order2) {
+        auto go = [&](auto tag) {
+            using T = decltype(tag);
+            if (maxin <= 2) dispatch_sweep_so2<T, 2>(vs, wk, n, bpl, block, lds_bytes, st);
+            else if (maxin == 3) dispatch_sweep_so2<T, 3>(vs, wk, n, bpl, block, lds_bytes, st);
+            else dispatch_sweep_so2<T, 5>(vs, wk, n, bpl, block, lds_bytes, st);
+        };
+        if (fp32) go(float{});
+        else go(double{});
+        return;
+    }
     if (fp32) dispatch_sweep<float>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st);
     else dispatch_sweep<double>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st);
 }

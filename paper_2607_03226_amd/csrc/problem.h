@@ -74,6 +74,7 @@ class Runner {
         int maxin = 0, bpl = 1, block = 256, iters = 0;
         int mode = 0;   // sweep kernel mode (launch_sweep)
         bool one = false;   // one lane per cell
+        bool so2 = false;   // second-order sweep kernels
         size_t lds = 0;
     };
     void build();
@@ -151,6 +152,12 @@ struct nbte_problem {
     int acc_nblk = 1;
     int self_acc = 0, n_self_acc = 0;   // offsets in d_self_work: initial inflow state (face waves)
     int accel_m() const { return tuning.accel_depth; }
+    // second-order face values (opts.spatial_order = 2)
+    int order = 1;
+    bool lsq_up = false;
+    nbte::DevBuf d_lsq, d_Sv, d_xf, d_xc, d_bf_local, d_grad, d_corr, d_bdelta;
+    int so2_nblk = 1, so2_nblk_b = 1;   // workgroups of the gradient / correction and of the boundary launches
+    int self_so2 = 0;                    // offset in d_self_work: [grad items][corr items][boundary items]
     int64_t accel_rows() const;         // NR: ghost rows x bands
     int pcg_nblk = 1;
     int ell_w = 0;                   // ELL width of the correction's matrix
@@ -205,7 +212,7 @@ struct nbte_problem {
         build_host();
         upload_device();
     }
-    int64_t state_bytes(int prec) const;
+    int64_t state_bytes(int prec, int ord = 1) const;
     void allocate_state(int prec);
     int64_t device_bytes() const;
     void make_view();

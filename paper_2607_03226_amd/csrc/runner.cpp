@@ -18,7 +18,7 @@ namespace nbte {
 namespace {
 
 enum Kind { K_MARK, K_STAGE, K_SWEEP, K_POST, K_WALL, K_PCG_BLOCK, K_PCG_MULTI, K_UPDATE, K_FINISH, K_ACC_COLS,
-            K_ACC_SOLVE, K_ACC_MIX };
+            K_ACC_SOLVE, K_ACC_MIX, K_GRAD, K_RECON };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -118,14 +118,18 @@ void Runner::build() {
     mark(PH_SWEEP);
     {
         // group by kernel variant; inside a group, XCD-aware longest-first order
-        using Key = std::tuple<int, int, int, int, int, int>;   // fp32, maxin class, bpl, mode, block, one
+        // fp32, maxin class, bpl, mode, block, one lane per cell, second order
+        using Key = std::tuple<int, int, int, int, int, int, int>;
         std::map<Key, std::vector<int>> groups;
         for (int s = 0; s < M; ++s) {
             const nbte_problem &p = *members_[s];
             const int mi = p.prog.maxin <= 2 ? 2 : (p.prog.maxin == 3 ? 3 : 5);
             const bool spill = p.shape.slots == 0 || p.sched.spilled > 0;
-            const int mode = spill ? 2 : (p.prog.max_ghosts > p.shape.gcap ? 1 : 0);
-            groups[Key(p.fp32() ? 1 : 0, mi, p.shape.bpl, mode, p.shape.block, p.hv.lpc == 1 ? 1 : 0)].push_back(s);
+            const bool so2 = p.order == 2;   // second order: the general mode, several lanes per cell
+            const int mode = (spill || so2) ? 2 : (p.prog.max_ghosts > p.shape.gcap ? 1 : 0);
+            groups[Key(p.fp32() ? 1 : 0, mi, p.shape.bpl, mode, p.shape.block, (p.hv.lpc == 1 && !so2) ? 1 : 0,
+                       so2 ? 1 : 0)]
+                .push_back(s);
         }
         for (auto &kv : groups) {
             struct Unit {
@@ -171,6 +175,7 @@ void Runner::build() {
             L.bpl = std::get<2>(kv.first);
             L.mode = std::get<3>(kv.first);
             L.one = std::get<5>(kv.first) != 0;
+            L.so2 = std::get<6>(kv.first) != 0;
             L.block = std::get<4>(kv.first);
             L.lds = lds;
             L.off = (int)work.size();
@@ -183,6 +188,29 @@ void Runner::build() {
     }
 
     mark(PH_MOM);
+    // second order: gradients of the new distribution, the next sweep's
+    // correction and the outgoing increments the boundary flux needs
+    for (bool f : {true, false}) {
+        Launch G;
+        G.kind = K_GRAD;
+        G.fp32 = f;
+        G.off = (int)work.size();
+        each(f, [&](int s, nbte_problem &p) {
+            if (p.order != 2) return;
+            for (int b = 0; b < p.so2_nblk; ++b) work.push_back({s, 0, b, p.so2_nblk});
+        });
+        close(G);
+        Launch R;
+        R.kind = K_RECON;
+        R.fp32 = f;
+        R.off = (int)work.size();
+        each(f, [&](int s, nbte_problem &p) {
+            if (p.order != 2) return;
+            for (int b = 0; b < p.so2_nblk; ++b) work.push_back({s, 0, b, p.so2_nblk});
+            for (int b = 0; b < p.so2_nblk_b; ++b) work.push_back({s, 1, b, p.so2_nblk_b});
+        });
+        close(R);
+    }
     for (bool f : {true, false}) {
         // boundary flux (every scheme: the outgoing sums feed the next
         // diffuse inflow; the net flows are used by the synthetic correction
@@ -322,7 +350,8 @@ void Runner::enqueue_iteration(int slot) {
                 break;
             case K_STAGE: launch_stage(vs, wk + L.off, L.n, L.fp32, stream_); break;
             case K_SWEEP:
-                launch_sweep(vs, wk + L.off, L.n, L.fp32, L.maxin, L.bpl, L.one, L.mode, L.block, L.lds, stream_);
+                launch_sweep(vs, wk + L.off, L.n, L.fp32, L.maxin, L.bpl, L.one, L.mode, L.block, L.lds, stream_,
+                             L.so2);
                 break;
             case K_POST: launch_post(vs, wk + L.off, L.n, L.fp32, stream_); break;
             case K_WALL: launch_wall_rhs(vs, wk + L.off, L.n, stream_); break;
@@ -335,6 +364,8 @@ void Runner::enqueue_iteration(int slot) {
             case K_ACC_COLS: launch_accel_cols(vs, wk + L.off, L.n, L.fp32, stream_); break;
             case K_ACC_SOLVE: launch_accel_solve(vs, wk + L.off, L.n, stream_); break;
             case K_ACC_MIX: launch_accel_mix(vs, wk + L.off, L.n, L.fp32, stream_); break;
+            case K_GRAD: launch_grad(vs, wk + L.off, L.n, L.fp32, 0, stream_); break;
+            case K_RECON: launch_recon(vs, wk + L.off, L.n, L.fp32, 0, stream_); break;
         }
     }
     NBTE_HIP(hipGetLastError());

@@ -370,4 +370,89 @@ DiffusionOperator build_diffusion(const Mesh &m, const BandTable &b, const Quadr
     return op;
 }
 
+namespace {
+
+// eigenvalues of a symmetric d x d matrix (d <= 3) by cyclic Jacobi rotations
+void sym_eigenvalues(int d, double A[3][3], double ev[3]) {
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < d; ++p)
+            for (int q = p + 1; q < d; ++q) off += A[p][q] * A[p][q];
+        if (off < 1e-300) break;
+        for (int p = 0; p < d; ++p)
+            for (int q = p + 1; q < d; ++q) {
+                if (A[p][q] == 0.0) continue;
+                const double th = 0.5 * (A[q][q] - A[p][p]) / A[p][q];
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < d; ++k) {   // A <- J^T A J
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < d; ++k) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+            }
+    }
+    for (int k = 0; k < d; ++k) ev[k] = A[k][k];
+}
+
+}  // namespace
+
+std::vector<double> build_lsq_weights(const Mesh &m) {
+    const int64_t N = m.N;
+    const int F = m.F, d = m.dim;
+    std::vector<double> w((size_t)N * F * 3, 0.0);
+    for (int64_t c = 0; c < N; ++c) {
+        double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int f = 0; f < F; ++f) {
+            const int32_t n = m.nbr[c * F + f];
+            if (n < 0) continue;
+            double off[3];
+            for (int k = 0; k < 3; ++k) off[k] = m.xc[n * 3 + k] - m.xc[c * 3 + k];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) M[a][b] += off[a] * off[b];
+        }
+        double E[3][3], ev[3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) E[a][b] = M[a][b];
+        sym_eigenvalues(d, E, ev);
+        double lo = ev[0], hi = ev[0];
+        for (int k = 1; k < d; ++k) lo = std::min(lo, ev[k]), hi = std::max(hi, ev[k]);
+        if (!(hi > 0.0) || !(lo > 1e-8 * hi)) continue;   // no gradient: first-order faces
+        // inverse of the d x d block
+        double inv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        if (d == 2) {
+            const double det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+            inv[0][0] = M[1][1] / det, inv[0][1] = -M[0][1] / det;
+            inv[1][0] = -M[1][0] / det, inv[1][1] = M[0][0] / det;
+        } else {
+            const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                               M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                               M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    // cofactor (b, a) / det
+                    const int r0 = (b + 1) % 3, r1 = (b + 2) % 3, c0 = (a + 1) % 3, c1 = (a + 2) % 3;
+                    inv[a][b] = (M[r0][c0] * M[r1][c1] - M[r0][c1] * M[r1][c0]) / det;
+                }
+        }
+        for (int f = 0; f < F; ++f) {
+            const int32_t n = m.nbr[c * F + f];
+            if (n < 0) continue;
+            double off[3];
+            for (int k = 0; k < 3; ++k) off[k] = m.xc[n * 3 + k] - m.xc[c * 3 + k];
+            for (int a = 0; a < d; ++a) {
+                double x = 0.0;
+                for (int b = 0; b < d; ++b) x += inv[a][b] * off[b];
+                w[((size_t)c * F + f) * 3 + a] = x;
+            }
+        }
+    }
+    return w;
+}
+
 }  // namespace nbte

@@ -117,7 +117,7 @@ nbte_problem::Shape nbte_problem::resolve_shape() const {
     if (bpl > 8) throw Error(NBTE_ERR_INVALID_ARG, "bands_per_block too large for 8 bands per lane");
     int lanes = (bpb + bpl - 1) / bpl, lpc = 1;
     while (lpc < lanes) lpc <<= 1;
-    if (lpc > 1 && bpl > 4) {   // eight bands per lane only with one lane per cell
+    if ((lpc > 1 || order == 2) && bpl > 4) {   // eight bands per lane only with one lane per cell (first order)
         bpl = 4;
         lanes = (bpb + bpl - 1) / bpl;
         lpc = 1;
@@ -364,9 +364,12 @@ int64_t nbte_problem::accel_rows() const {
     return std::max<int64_t>(ghosts, 1) * bands.B;
 }
 
-int64_t nbte_problem::state_bytes(int prec) const {
+int64_t nbte_problem::state_bytes(int prec, int ord) const {
     const int64_t N = mesh->N, NBF = mesh->NBF, B = bands.B, D = quad.D;
     const int64_t es = prec == NBTE_PREC_MIXED ? 4 : 8;
+    int64_t so2 = 0;
+    if (ord == 2)   // gradient planes, correction, two boundary increment slots; weights and geometry
+        so2 = 4 * D * N * B * es + 2 * NBF * D * B * es + (int64_t)mesh->F * N * 9 * 8 + N * 3 * 8 + NBF * 4;
     const int64_t ghosts = prog_B > 0 ? (int64_t)prog.ghost_src.size() : NBF * D;   // incoming pairs
     int64_t acc = 0;
     if (accel_m() > 0) {
@@ -374,7 +377,7 @@ int64_t nbte_problem::state_bytes(int prec) const {
         acc = (2 * NR + 2 * NS) * 8 + 2 * (int64_t)accel_m() * NS * es + 1024 * 2 * kAccelMaxDepth * 8 + 1024;
     }
     return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + NBF * (B + 3) * 8 + N * 8 * 10 +
-           1024 + acc;
+           1024 + acc + so2;
 }
 
 void nbte_problem::allocate_state(int prec) {
@@ -413,6 +416,25 @@ void nbte_problem::allocate_state(int prec) {
     d_delta.alloc(N * 8);
     d_state.alloc(sizeof(SolveState));
     d_view.alloc(sizeof(DeviceView));
+    if (order == 2) {
+        if (!lsq_up) {
+            const Mesh &m = *mesh;
+            upload(d_lsq, build_lsq_weights(m), stream);
+            upload(d_Sv, m.S, stream);
+            upload(d_xf, m.xf, stream);
+            upload(d_xc, m.xc, stream);
+            upload(d_bf_local, m.bf_local, stream);
+            NBTE_HIP(hipStreamSynchronize(stream));   // the host copies go out of scope
+            lsq_up = true;
+        }
+        d_grad.alloc((size_t)3 * D * N * B * es);
+        d_corr.alloc((size_t)D * N * B * es);
+        d_bdelta.alloc((size_t)2 * std::max<int64_t>(NBF, 1) * D * B * es);
+        so2_nblk = (int)std::min<int64_t>(4096, cdiv(D * N * B, 256));
+        so2_nblk_b = (int)std::min<int64_t>(1024, cdiv(std::max<int64_t>(NBF, 1) * D * B, 256));
+    } else {
+        for (DevBuf *b : {&d_grad, &d_corr, &d_bdelta}) b->release();
+    }
     if (accel_m() > 0) {
         const int64_t NR = accel_rows(), NS = N + NR;
         d_acc_x.alloc(NR * 8);
@@ -437,7 +459,8 @@ int64_t nbte_problem::device_bytes() const {
           &d_mirror, &d_wall, &d_wall_ptr, &d_wslot, &d_wallJ, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_Ecol, &d_Eval, &d_g, &d_gval,
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work, &d_acc_x, &d_acc_G, &d_acc_fprev,
-          &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal})
+          &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal, &d_lsq, &d_Sv, &d_xf, &d_xc, &d_bf_local,
+          &d_grad, &d_corr, &d_bdelta})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -533,6 +556,15 @@ void nbte_problem::make_view() {
     a.dG = d_acc_dG.ptr;
     a.part = d_acc_part.as<double>();
     a.scal = d_acc_scal.as<double>();
+    v.order = order;
+    v.lsq = d_lsq.as<double>();
+    v.Sv = d_Sv.as<double>();
+    v.xf = d_xf.as<double>();
+    v.xc = d_xc.as<double>();
+    v.bf_local = d_bf_local.as<int32_t>();
+    v.grad = d_grad.ptr;
+    v.corr = d_corr.ptr;
+    v.bdelta = d_bdelta.ptr;
     hv = v;
 }
 
@@ -540,6 +572,9 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     if (batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member; remove it from the batch first");
     if (o.precision != NBTE_PREC_FP64 && o.precision != NBTE_PREC_MIXED) throw Error(NBTE_ERR_INVALID_ARG, "bad precision");
     if (o.scheme < 0 || o.scheme > 2) throw Error(NBTE_ERR_INVALID_ARG, "bad scheme");
+    if (o.spatial_order != 1 && o.spatial_order != 2) throw Error(NBTE_ERR_INVALID_ARG, "spatial_order must be 1 or 2");
+    if (o.spatial_order == 2 && accel_m() > 0)
+        throw Error(NBTE_ERR_INVALID_ARG, "the second-order scheme is not combined with Anderson acceleration");
     if (!std::isfinite(o.T_ref)) throw Error(NBTE_ERR_INVALID_ARG, "bad T_ref");
     if (o.T_ref != T_ref) {
         T_ref = o.T_ref;
@@ -563,6 +598,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     check_addressable(o.precision);
     prepared = false;
     precision = o.precision;   // the launch shape's LDS budget depends on it
+    order = o.spatial_order;   // so does its bands per lane
     ensure_setup();
     scheme = o.scheme;
     time_phases = o.time_phases;
@@ -585,6 +621,10 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
         self_acc = (int)wk.size();   // stage items of kind 3: the initial inflow state
         for (int b = 0; b < nf; ++b) wk.push_back({0, 3, b, nf});
         n_self_acc = nf;
+        self_so2 = (int)wk.size();   // second order: gradient items, then correction and boundary items
+        for (int b = 0; b < so2_nblk; ++b) wk.push_back({0, 0, b, so2_nblk});
+        for (int b = 0; b < so2_nblk; ++b) wk.push_back({0, 0, b, so2_nblk});
+        for (int b = 0; b < so2_nblk_b; ++b) wk.push_back({0, 1, b, so2_nblk_b});
         upload(d_self_work, wk, stream);
         NBTE_HIP(hipStreamSynchronize(stream));
     }
@@ -626,6 +666,13 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     NBTE_HIP(hipMemcpyAsync(d_theta[1].ptr, th0, m.N * 8, hipMemcpyDeviceToDevice, stream));
     launch_fill_zero(d_g.ptr, d_g.bytes, stream);
     launch_fill_zero(d_gval.ptr, d_gval.bytes, stream);
+    if (order == 2) {
+        // the initial distribution's gradients, the first sweep's correction and
+        // the increments of its outgoing boundary values (slot 0)
+        const WorkItem *w2 = d_self_work.as<WorkItem>() + self_so2;
+        launch_grad(d_view.as<DeviceView>(), w2, so2_nblk, fp32(), 1, stream);
+        launch_recon(d_view.as<DeviceView>(), w2 + so2_nblk, so2_nblk + so2_nblk_b, fp32(), 1, stream);
+    }
     // the first boundary stage's diffuse sums, from the initial distribution
     launch_flux(d_view.as<DeviceView>(), d_self_work.as<WorkItem>() + self_flux, n_self_flux, fp32(), 2, stream);
     if (accel_m() > 0) {
@@ -682,6 +729,13 @@ void nbte_problem::promote() {
     launch_gather((int64_t)quad.D * mesh->N, p_cell(), d_Q.as<double>(), t_row(2), false, stream);
     make_view();
     NBTE_HIP(hipMemcpyAsync(d_view.ptr, &hv, sizeof(DeviceView), hipMemcpyHostToDevice, stream));
+    if (order == 2) {
+        // the FP64 copies of the gradients, the next sweep's correction and the
+        // boundary increments of the distribution the next stage reads
+        const WorkItem *w2 = d_self_work.as<WorkItem>() + self_so2;
+        launch_grad(d_view.as<DeviceView>(), w2, so2_nblk, fp32(), 2, stream);
+        launch_recon(d_view.as<DeviceView>(), w2 + so2_nblk, so2_nblk + so2_nblk_b, fp32(), 2, stream);
+    }
     if (accel_m() > 0) {
         // the acceleration restarts, in FP64 columns, from the last plain image:
         // theta[cur] and the inflow of the last distribution
@@ -709,7 +763,7 @@ void nbte_problem::iterate(int n, bool check, double *res_out) {
     if (check) {
         solo->collect();
         if (hs.done == NBTE_DONE_DIVERGED)
-            throw Error(NBTE_ERR_DIVERGED, "iteration diverged (non-finite temperature)");
+            throw Error(NBTE_ERR_DIVERGED, "iteration diverged (non-finite or exploding temperature update)");
         if (res_out) *res_out = hs.residual;
     }
     stats.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -914,6 +968,7 @@ void nbte_solve_opts_default(nbte_solve_opts *o) {
     o->outputs_on_device = 0;
     o->time_phases = 0;
     o->refine = 1;
+    o->spatial_order = 1;
 }
 
 nbte_status nbte_prepare(nbte_problem *p, const double *Q_cell, const nbte_solve_opts *o) {
@@ -964,7 +1019,7 @@ nbte_status nbte_solve_steady(nbte_problem *p, const double *Q_cell, const nbte_
         }
         p->stats.ms_total += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (out) p->read_result(out);
-        if (p->hs.done == NBTE_DONE_DIVERGED) return fail(NBTE_ERR_DIVERGED, "iteration diverged (non-finite temperature)");
+        if (p->hs.done == NBTE_DONE_DIVERGED) return fail(NBTE_ERR_DIVERGED, "iteration diverged (non-finite or exploding temperature update)");
         if (p->hs.done == NBTE_DONE_STALLED)
             return fail(NBTE_ERR_NOT_CONVERGED, "the FP32 iteration stalled at residual " +
                                                     std::to_string(p->hs.residual) +

@@ -36,7 +36,8 @@ class Boundary(ct.Structure):
 class SolveOpts(ct.Structure):
     _fields_ = [("scheme", ct.c_int32), ("precision", ct.c_int32), ("T_ref", ct.c_double), ("tol", ct.c_double),
                 ("max_iter", ct.c_int32), ("check_every", ct.c_int32), ("T_init", _d),
-                ("outputs_on_device", ct.c_int32), ("time_phases", ct.c_int32), ("refine", ct.c_int32)]
+                ("outputs_on_device", ct.c_int32), ("time_phases", ct.c_int32), ("refine", ct.c_int32),
+                ("spatial_order", ct.c_int32)]
 
 
 class Result(ct.Structure):
@@ -243,7 +244,7 @@ def nbte_solve_opts_default():
 
 
 def make_opts(scheme="synthetic", precision="fp64", T_ref=300.0, tol=1e-8, max_iter=10000, check_every=8,
-              T_init=None, outputs_on_device=False, time_phases=False, refine=True):
+              T_init=None, outputs_on_device=False, time_phases=False, refine=True, order=1):
     o = nbte_solve_opts_default()
     o.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -251,6 +252,7 @@ def make_opts(scheme="synthetic", precision="fp64", T_ref=300.0, tol=1e-8, max_i
     o.outputs_on_device = int(bool(outputs_on_device))
     o.time_phases = int(bool(time_phases))
     o.refine = int(bool(refine))
+    o.spatial_order = int(order)
     o._keep = None
     if T_init is not None:
         t = _f64(T_init)
@@ -428,7 +430,7 @@ def build_problem(problem, stream=None):
 
 
 def solve(problem, precision=None, scheme=None, tol=1e-8, max_iter=10000, check_every=8, T_init=None,
-          stream=None, allow_not_converged=False, tuning=None, accel=None):
+          stream=None, allow_not_converged=False, tuning=None, accel=None, order=1):
     """tuning: None (library defaults), "auto" (autotuner cache, defaults if
     the workload was never tuned) or a dict of nbte_set_tuning arguments;
     accel: Anderson depth of the outer iteration (overrides the tuning's)."""
@@ -442,7 +444,8 @@ def solve(problem, precision=None, scheme=None, tol=1e-8, max_iter=10000, check_
     if tuning:
         nbte_set_tuning(p, **tuning)
     opts = make_opts(scheme=scheme or problem.scheme, precision=precision,
-                     T_ref=problem.T_ref, tol=tol, max_iter=max_iter, check_every=check_every, T_init=T_init)
+                     T_ref=problem.T_ref, tol=tol, max_iter=max_iter, check_every=check_every, T_init=T_init,
+                     order=order)
     out = nbte_solve_steady(p, problem.Q, opts, allow_not_converged=allow_not_converged)
     out["_handles"] = (mesh, p)
     return out
