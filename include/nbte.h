@@ -222,9 +222,23 @@ nbte_status nbte_get_distribution_noalloc(nbte_problem *p, int32_t band, int32_t
  * lvl_ptr[0..n_levels] (nullable; capacity cap_levels entries), such that
  * every interior upwind neighbour of a cell lies in an earlier level.  For
  * first-order upwind this order is the exact factorisation of the transport
- * matrix of Eq. (13).  Errors: NBTE_ERR_MESH if the upwind graph is cyclic. */
+ * matrix of Eq. (13).  Where the upwind graph of a direction is cyclic (a
+ * non-convex cell), the order releases the lowest unfinished cell whenever it
+ * stalls and lags that cell's upwind faces towards unfinished cells: those
+ * faces are excluded from the level constraint and take the upwind value of
+ * the previous iterate, like boundary inflow (nbte_get_lagged_faces).  The
+ * outer iteration then converges to the same fixed point. */
 nbte_status nbte_get_schedule(nbte_problem *p, int32_t dir, int32_t *perm, int32_t *lvl_ptr, int32_t cap_levels,
                               int32_t *n_levels);
+
+/* The lagged faces of direction dir's sweep (host data, no device needed):
+ * cells[k], faces[k] = cell and its local face index (the cell's face order of
+ * its type), k < min(n, cap); *n = their number (0 for an acyclic upwind
+ * graph).  cells/faces may be NULL to query *n.  A lagged face takes the
+ * upwind neighbour's value of the previous iterate.  Errors:
+ * NBTE_ERR_INVALID_ARG, NBTE_ERR_STATE (quadrature not set). */
+nbte_status nbte_get_lagged_faces(nbte_problem *p, int32_t dir, int32_t *cells, int32_t *faces, int32_t cap,
+                                  int32_t *n);
 
 typedef struct {
     int32_t iterations;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -117,6 +118,16 @@ struct Schedule {
     int64_t spilled = 0;             // consumed values that did not fit
     int max_ghosts = 0;              // most boundary inflow faces feeding one level
     int max_ghost_pair = 0;          // most inflow faces feeding two consecutive levels
+    // Cyclic upwind graphs: where the topological order stalls, the lowest
+    // unfinished cell is released and its upwind faces towards unfinished
+    // cells are lagged: they take the upwind value of the previous iterate
+    // (like boundary inflow), which keeps the fixed point.  Sorted keys
+    // (i N + c) F + f of the lagged faces.
+    std::vector<int64_t> lagged;
+    bool is_lagged(int64_t N, int F, int i, int64_t c, int f) const {
+        if (lagged.empty()) return false;
+        return std::binary_search(lagged.begin(), lagged.end(), ((int64_t)i * N + c) * F + f);
+    }
 };
 
 Schedule build_schedule(const Mesh &m, const Quadrature &q);
@@ -145,6 +156,7 @@ struct SweepProgram {
     std::vector<int64_t> ghost_src;
     std::vector<int32_t> in_row;            // NBF*D: ghost row of incoming (bf, i), -1 otherwise
     int max_ghosts = 0;                     // most ghosts of one level
+    std::vector<int32_t> lag;               // per lagged face (4 ints): ghost row, direction, cell, upwind cell
 };
 // record reference encoding (shared with the sweep kernel): >= 0 an element
 // offset in the workgroup's LDS (a staged value: ring_off + slot ls; a ghost

@@ -136,6 +136,10 @@ struct DeviceView {
     const int32_t NBTE_G *wall_cell, *wall_ptr, *wslot;
     int64_t n_wall;
     const int32_t NBTE_G *in_row;  // NBF*D: ghost row of an incoming (face, direction), -1 otherwise
+    // lagged faces of cyclic upwind graphs (ghost rows filled from the previous
+    // distribution): n_lag entries of (ghost row, direction, cell, upwind cell)
+    int64_t n_lag;
+    const int32_t NBTE_G *lag;
     const double NBTE_G *bf_thw, *bf_p, *sdotS, *win;
     // state
     void NBTE_G *g;                // D*N*B, FP32 or FP64: non-equilibrium part e - C theta/W
@@ -180,7 +184,8 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 // blocks of this (solve, kind)), 256 threads each.
 //   stage:   kind 0 = boundary inflow, one wave per boundary face;
 //            kind 1 = equilibrium-imbalance term D of every stream entry;
-//            kinds 2, 3 = the accelerated iteration's absolute inflow (below)
+//            kinds 2, 3 = the accelerated iteration's absolute inflow (below);
+//            kind 4 = the ghost rows of lagged faces (grid-stride over rows x bands)
 //   flux:    per-band outgoing sums and net flow, one wave per boundary face
 //            (items (solve, -, b, nblk): faces b*4 + wave, strided by 4 nblk)
 //   post:    kind 0 = flux mode 0 face groups (as above); kind 1 = band x

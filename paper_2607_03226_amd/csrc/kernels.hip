@@ -304,6 +304,20 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
         const int wv = threadIdx.x >> 6;
         for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4)
             bc_face<T>(v, bf, red + 64 * wv);
+    } else if (it.a == 4) {
+        // lagged faces: the upwind cell's value of the previous iterate, as the
+        // deviation from the downwind cell's equilibrium at the coming theta
+        const int B = v.B;
+        const int64_t N = v.N;
+        const T *g = static_cast<const T *>(v.g);
+        T *gv = static_cast<T *>(v.gval);
+        const double *thp = theta_prev(v), *thc = theta_cur(v);
+        for (int64_t t = (int64_t)it.b * blockDim.x + threadIdx.x; t < v.n_lag * B; t += (int64_t)it.c * blockDim.x) {
+            const int lam = (int)(t % B);
+            const int32_t *L = v.lag + 4 * (t / B);
+            const double e = ld(g, ((int64_t)L[1] * N + L[3]) * B + lam) + v.Cw[lam] * thp[L[3]];
+            gv[(int64_t)L[0] * B + lam] = static_cast<T>(e - v.Cw[lam] * thc[L[2]]);
+        }
     } else if (it.a >= 2) {
         double *dst = it.a == 2 ? v.acc.ain_G : v.acc.ain_x;
         const int wv = threadIdx.x >> 6;

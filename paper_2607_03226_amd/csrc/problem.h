@@ -125,7 +125,7 @@ struct nbte_problem {
 
     // device buffers
     nbte::DevBuf d_nbr, d_V;
-    nbte::DevBuf d_lvl_ptr, d_lvl_off, d_gptr, d_pupc, d_inrow;
+    nbte::DevBuf d_lvl_ptr, d_lvl_off, d_gptr, d_pupc, d_inrow, d_lag;
     // the sweep's streams, D*N entries per row, rows contiguous so the sweep
     // reads them through one buffer descriptor each:
     //   d_pint (int32):           cell | slot | maxin reference rows

@@ -111,6 +111,9 @@ void Runner::build() {
             const int64_t nb1 = std::min<int64_t>(cdiv((int64_t)p.quad.D * p.mesh->N, 256), 65536);
             for (int64_t b = 0; b < nb0; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb0});
             for (int64_t b = 0; b < nb1; ++b) work.push_back({s, 1, (int32_t)b, (int32_t)nb1});
+            const int64_t nlag = (int64_t)p.prog.lag.size() / 4;   // lagged faces of cyclic upwind graphs
+            const int64_t nb4 = std::min<int64_t>(cdiv(nlag * p.bands.B, 256), 1024);
+            for (int64_t b = 0; b < nb4; ++b) work.push_back({s, 4, (int32_t)b, (int32_t)nb4});
         });
         close(L);
     }

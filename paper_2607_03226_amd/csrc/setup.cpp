@@ -28,6 +28,7 @@ Schedule build_schedule(const Mesh &m, const Quadrature &q) {
     sc.perm.resize((size_t)q.D * N);
     sc.lvl_off.assign(q.D + 1, 0);
     std::vector<int32_t> indeg(N), frontier, next;
+    std::vector<uint8_t> placed(N);
     for (int i = 0; i < q.D; ++i) {
         const double *s = &q.s[3 * i];
         auto sdot = [&](int64_t c, int f) {
@@ -47,10 +48,30 @@ Schedule build_schedule(const Mesh &m, const Quadrature &q) {
         int64_t done = 0;
         int levels = 0;
         int prev_ghosts = 0;
+        std::fill(placed.begin(), placed.end(), 0);
+        int64_t scan = 0;   // cells below scan are placed (search start for a stalled order)
+        int lag_ghosts = 0; // lagged faces of the released cell: ghosts of its level
         sc.lvl_ptr.push_back(0);
-        while (!frontier.empty()) {
+        for (;;) {
+            if (frontier.empty()) {
+                if (done == N) break;
+                // a cycle: release the lowest unfinished cell, lagging its
+                // upwind faces towards unfinished cells
+                while (placed[scan]) ++scan;
+                const int64_t c = scan;
+                for (int f = 0; f < F; ++f) {
+                    const int32_t u = m.nbr[c * F + f];
+                    if (u >= 0 && sdot(c, f) < 0.0 && !placed[u]) {
+                        sc.lagged.push_back(((int64_t)i * N + c) * F + f);
+                        ++lag_ghosts;
+                    }
+                }
+                indeg[c] = 0;
+                frontier.push_back((int32_t)c);
+            }
             std::sort(frontier.begin(), frontier.end());
-            int ghosts = 0;
+            int ghosts = lag_ghosts;
+            lag_ghosts = 0;
             for (int32_t u : frontier)
                 for (int f = 0; f < F; ++f)
                     if (m.nbr[(int64_t)u * F + f] < 0 && sdot(u, f) < 0.0) ++ghosts;
@@ -58,6 +79,7 @@ Schedule build_schedule(const Mesh &m, const Quadrature &q) {
             sc.max_ghost_pair = std::max(sc.max_ghost_pair, prev_ghosts + ghosts);
             prev_ghosts = ghosts;
             std::copy(frontier.begin(), frontier.end(), perm + done);
+            for (int32_t u : frontier) placed[u] = 1;
             done += (int64_t)frontier.size();
             sc.lvl_ptr.push_back((int32_t)done);
             ++levels;
@@ -65,16 +87,15 @@ Schedule build_schedule(const Mesh &m, const Quadrature &q) {
             for (int32_t u : frontier)
                 for (int f = 0; f < F; ++f) {
                     int32_t d = m.nbr[(int64_t)u * F + f];
-                    if (d >= 0 && sdot(u, f) > 0.0 && --indeg[d] == 0) next.push_back(d);
+                    // a released cell's indegree is already 0 (goes negative, never queued twice)
+                    if (d >= 0 && sdot(u, f) > 0.0 && !placed[d] && --indeg[d] == 0) next.push_back(d);
                 }
             frontier.swap(next);
         }
-        if (done != N)
-            throw Error(NBTE_ERR_MESH, "upwind graph of direction " + std::to_string(i) +
-                                           " has a cycle; this mesh cannot be swept in one pass");
         sc.lvl_off[i + 1] = (int32_t)sc.lvl_ptr.size();
         sc.max_levels = std::max(sc.max_levels, levels);
     }
+    std::sort(sc.lagged.begin(), sc.lagged.end());
     return sc;
 }
 
@@ -106,7 +127,8 @@ void assign_slots(const Mesh &m, const Quadrature &q, Schedule &sc, int cap) {
                 const int32_t u = m.nbr[c * F + f];
                 if (u < 0) continue;
                 const double *S = &m.S[(c * F + f) * 3];
-                if (s[0] * S[0] + s[1] * S[1] + s[2] * S[2] < 0.0) last[u] = std::max(last[u], level[c]);
+                if (s[0] * S[0] + s[1] * S[1] + s[2] * S[2] < 0.0 && !sc.is_lagged(N, F, i, c, f))
+                    last[u] = std::max(last[u], level[c]);
             }
         release.assign(L + 1, {});
         free_slots.clear();
@@ -197,12 +219,18 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                         sout += a;
                     } else if (a < 0.0) {
                         const int32_t n = m.nbr[(int64_t)c * F + f];
+                        const bool lag = n >= 0 && sc.is_lagged(N, F, i, c, f);
                         int32_t r;
-                        if (n < 0) {                                   // boundary: a ghost of this level
-                            const int64_t bf = -(int64_t)n - 1;
+                        if (n < 0 || lag) {   // boundary inflow or a lagged face: a ghost of this level
                             const int64_t row = (int64_t)pg.ghost_src.size();
-                            pg.ghost_src.push_back((bf * D + i) * (int64_t)B);
-                            pg.in_row[bf * D + i] = (int32_t)row;
+                            if (n < 0) {
+                                const int64_t bf = -(int64_t)n - 1;
+                                pg.ghost_src.push_back((bf * D + i) * (int64_t)B);
+                                pg.in_row[bf * D + i] = (int32_t)row;
+                            } else {
+                                pg.ghost_src.push_back(-1);
+                                pg.lag.insert(pg.lag.end(), {(int32_t)row, i, c, n});
+                            }
                             r = rank < gcap ? lay.gbuf0 + ((gpos + rank) & (gring - 1)) * ls : -1 - (int32_t)row;
                             ++rank;
                         } else if (slot_i && slot_i[n] >= 0) {
@@ -211,7 +239,7 @@ SweepProgram build_program(const Mesh &m, const Quadrature &q, const Schedule &s
                             r = -(kSpillBase + 1) - pos[n];            // stored copy in HBM
                         }
                         pg.ref[(size_t)j * DN + at] = r;
-                        if (n >= 0) pg.upc[(size_t)j * DN + at] = n;
+                        if (n >= 0 && !lag) pg.upc[(size_t)j * DN + at] = n;   // ghosts are relative to the cell
                         pg.coef[(size_t)j * DN + at] = -a;
                         ++j;
                     }

@@ -267,6 +267,8 @@ void nbte_problem::upload_device() {
         coef_prec = -1;
         upload(d_gptr, prog.gptr, stream);
         upload(d_inrow, prog.in_row, stream);
+        upload(d_lag, prog.lag, stream);
+        NBTE_HIP(hipStreamSynchronize(stream));   // the program may be rebuilt (host copies replaced) after this
         sched_up = true;
     }
     if (!plan_up) {
@@ -455,7 +457,7 @@ void nbte_problem::allocate_state(int prec) {
 int64_t nbte_problem::device_bytes() const {
     int64_t s = 0;
     for (const DevBuf *b :
-         {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pint, &d_pupc, &d_tstream, &d_inrow, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
+         {&d_nbr, &d_V, &d_lvl_ptr, &d_lvl_off, &d_gptr, &d_pint, &d_pupc, &d_tstream, &d_inrow, &d_lag, &d_Cw, &d_src, &d_vel, &d_itau, &d_dirs, &d_w, &d_qbias, &d_bf_owner, &d_bf_kind,
           &d_mirror, &d_wall, &d_wall_ptr, &d_wslot, &d_wallJ, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_Ecol, &d_Eval, &d_g, &d_gval,
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work, &d_acc_x, &d_acc_G, &d_acc_fprev,
@@ -513,6 +515,8 @@ void nbte_problem::make_view() {
     v.wallJ = d_wallJ.as<double>();
     v.n_wall = n_wall;
     v.in_row = d_inrow.as<int32_t>();
+    v.n_lag = (int64_t)prog.lag.size() / 4;
+    v.lag = d_lag.as<int32_t>();
     v.bf_thw = d_bf_thw.as<double>();
     v.bf_p = d_bf_p.as<double>();
     v.sdotS = d_sdotS.as<double>();
@@ -600,6 +604,8 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     precision = o.precision;   // the launch shape's LDS budget depends on it
     order = o.spatial_order;   // so does its bands per lane
     ensure_setup();
+    if (!prog.lag.empty() && accel_m() > 0)
+        throw Error(NBTE_ERR_INVALID_ARG, "Anderson acceleration is not provided for meshes with lagged (cyclic) faces");
     scheme = o.scheme;
     time_phases = o.time_phases;
     allocate_state(precision);
@@ -1087,6 +1093,34 @@ nbte_status nbte_get_schedule(nbte_problem *p, int32_t dir, int32_t *perm, int32
             if (cap_levels < *n_levels + 1) throw Error(NBTE_ERR_INVALID_ARG, "lvl_ptr capacity too small");
             std::copy(&sc.lvl_ptr[b], &sc.lvl_ptr[e], lvl_ptr);
         }
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_get_lagged_faces(nbte_problem *p, int32_t dir, int32_t *cells, int32_t *faces, int32_t cap,
+                                  int32_t *n) {
+    return guarded([&] {
+        if (!p || !n || cap < 0) throw Error(NBTE_ERR_INVALID_ARG, "bad arguments");
+        if (!p->have_quad) throw Error(NBTE_ERR_STATE, "quadrature not set");
+        if (dir < 0 || dir >= p->quad.D) throw Error(NBTE_ERR_INVALID_ARG, "direction out of range");
+        if (!p->sched_ok) {
+            p->sched = build_schedule(*p->mesh, p->quad);
+            p->sched_ok = true;
+            p->sched_up = false;
+        }
+        const int64_t N = p->mesh->N;
+        const int F = p->mesh->F;
+        const auto &lg = p->sched.lagged;
+        const int64_t lo = (int64_t)dir * N * F, hi = (int64_t)(dir + 1) * N * F;
+        auto b = std::lower_bound(lg.begin(), lg.end(), lo), e = std::lower_bound(lg.begin(), lg.end(), hi);
+        int32_t k = 0;
+        for (auto it = b; it != e; ++it, ++k) {
+            if (k >= cap) continue;
+            const int64_t key = *it - lo;
+            if (cells) cells[k] = (int32_t)(key / F);
+            if (faces) faces[k] = (int32_t)(key % F);
+        }
+        *n = k;
         return NBTE_OK;
     });
 }

@@ -88,6 +88,7 @@ SIGNATURES = [
     ("nbte_read_result", ct.c_int32, [ct.c_void_p, ct.POINTER(Result)]),
     ("nbte_get_distribution", ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_int32, _d]),
     ("nbte_get_distribution_noalloc", ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_int32, _d]),
+    ("nbte_get_lagged_faces", ct.c_int32, [ct.c_void_p, ct.c_int32, _i32, _i32, ct.c_int32, _i32]),
     ("nbte_get_schedule", ct.c_int32, [ct.c_void_p, ct.c_int32, _i32, _i32, ct.c_int32, _i32]),
     ("nbte_get_stats", ct.c_int32, [ct.c_void_p, ct.POINTER(Stats)]),
     ("nbte_set_tuning", ct.c_int32, [ct.c_void_p, ct.POINTER(Tuning)]),
@@ -332,6 +333,16 @@ def nbte_get_schedule(p, direction):
     lvl = np.empty(n.value + 1, np.int32)
     _check(_lib.nbte_get_schedule(p.handle, int(direction), _ptr(perm, _i32), _ptr(lvl, _i32), len(lvl), ct.byref(n)))
     return perm, lvl
+
+
+def nbte_get_lagged_faces(p, direction):
+    n = ct.c_int32(0)
+    _check(_lib.nbte_get_lagged_faces(p.handle, int(direction), None, None, 0, ct.byref(n)))
+    cells = np.empty(n.value, np.int32)
+    faces = np.empty(n.value, np.int32)
+    _check(_lib.nbte_get_lagged_faces(p.handle, int(direction), _ptr(cells, _i32), _ptr(faces, _i32), n.value,
+                                      ct.byref(n)))
+    return cells, faces
 
 
 def nbte_get_stats(p):

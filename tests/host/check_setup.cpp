@@ -1,9 +1,10 @@
 // Host-side setup of the library under AddressSanitizer and
 // UndefinedBehaviorSanitizer: the mesh-to-CSR builder, the per-direction
 // level schedules, the LDS slot assignment, the sweep program, the boundary
-// plan and the diffusion operator, on small meshes of every cell type (with
-// jittered nodes, several slot budgets and ghost-ring sizes), plus the
-// rejection of a mesh whose upwind graph is cyclic.  No device code runs.
+// plan, the diffusion operator and the least-squares gradient weights, on
+// small meshes of every cell type (with jittered nodes, several slot budgets
+// and ghost-ring sizes), plus a mesh whose upwind graph is cyclic (scheduled
+// with lagged faces).  No device code runs.
 // Exit status 0 and no sanitizer report mean every access stayed in bounds.
 #include <algorithm>
 #include <cmath>
@@ -138,6 +139,8 @@ Quadrature quadrature(int dim, int D) {
     return q;
 }
 
+int64_t g_lagged = 0;   // lagged faces of the last exercised mesh
+
 int exercise(const RawMesh &rm, int D, int B) {
     const int nv = (int)(rm.type == NBTE_CELL_TRI3 ? 3 : rm.type == NBTE_CELL_HEX8 ? 8 : 4);
     const int nfv = rm.type == NBTE_CELL_TET4 ? 3 : (rm.type == NBTE_CELL_HEX8 ? 4 : 2);
@@ -159,6 +162,7 @@ int exercise(const RawMesh &rm, int D, int B) {
                                       {3, NBTE_BC_SPECULAR, 0.0, 0.0},
                                       {4, NBTE_BC_PARTIAL, 0.0, 0.4}};
     Schedule sc = build_schedule(*m, q);
+    g_lagged = (int64_t)sc.lagged.size();
     int checks = 0;
     for (int cap : {1, 7, 64, 1 << 20}) {
         assign_slots(*m, q, sc, cap);
@@ -178,6 +182,8 @@ int exercise(const RawMesh &rm, int D, int B) {
     BoundaryPlan bp = build_boundary_plan(*m, q, bcs, 300.0);
     DiffusionOperator op = build_diffusion(*m, bt, q, bp);
     checks += (int64_t)op.row_ptr.size() == m->N + 1 && !pg.cell.empty();
+    const std::vector<double> lsq = build_lsq_weights(*m);
+    checks += (int64_t)lsq.size() == m->N * m->F * 3;
     return checks;
 }
 
@@ -203,12 +209,7 @@ int main() {
     dart.cells = {0, 1, 4, 2, 0, 2, 5, 3, 0, 3, 6, 1};
     dart.bfaces = {1, 4, 4, 2, 2, 5, 5, 3, 3, 6, 6, 1};
     dart.tags = {2, 2, 2, 2, 1, 2};
-    bool rejected = false;
-    try {
-        exercise(dart, 8, 2);
-    } catch (const Error &e) {
-        rejected = e.code == NBTE_ERR_MESH;
-    }
+    const bool lagged = exercise(dart, 8, 2) == 34 && g_lagged > 0;
     // malformed input is rejected, not read out of bounds
     RawMesh bad = grid2d(3, 3, false, rng);
     bad.cells[5] = 1000;
@@ -218,6 +219,6 @@ int main() {
     } catch (const Error &e) {
         bad_rejected = e.code == NBTE_ERR_MESH;
     }
-    std::printf("checks %d cyclic_rejected %d bad_index_rejected %d\n", checks, (int)rejected, (int)bad_rejected);
-    return (checks == 4 * 33 && rejected && bad_rejected) ? 0 : 1;
+    std::printf("checks %d cyclic_lagged %d bad_index_rejected %d\n", checks, (int)lagged, (int)bad_rejected);
+    return (checks == 4 * 34 && lagged && bad_rejected) ? 0 : 1;
 }

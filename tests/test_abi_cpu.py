@@ -238,25 +238,39 @@ def test_counter_traffic_needs_same_source_and_shape(tmp_path, monkeypatch):
     assert bench.counter_traffic("configX", "mixed", shape) is None
 
 
-def test_cyclic_upwind_graph_is_reported_as_a_mesh_error():
+def test_cyclic_upwind_graph_is_ordered_with_lagged_faces():
     """A non-convex (dart) cell closes a cycle in the upwind graph of some
     directions (the mesh is built in the oracle pins, where the oracle's
-    direct-solve fallback is checked): the library's level schedule cannot
-    order it and says so."""
+    direct-solve fallback is checked).  The library's order then lags the
+    faces that close the cycles: acyclic directions have none, cyclic ones
+    have some, and every other interior upwind neighbour of a cell lies in an
+    earlier level."""
+    from oracle import geometry as geo
     from tests.test_oracle_pins import dart_mesh
     xyz, cells, bf, tags = dart_mesh()
     mesh = N.nbte_mesh_create(2, xyz, "quad4", cells, bf, tags)
     h = N.nbte_problem_create(mesh)
     s, w = inplane_quadrature(8)
-    # only the acyclic directions (22.5, 67.5, 202.5, 247.5 degrees): fine
-    N.nbte_set_quadrature(h, s[[0, 1, 4, 5]], w[[0, 1, 4, 5]])
-    for i in range(4):
+    N.nbte_set_quadrature(h, s, w)
+    g = geo.build(xyz, "quad4", cells, bf, tags)
+    phi = np.degrees(np.arctan2(s[:, 1], s[:, 0])) % 360
+    cyclic = ((phi > 110) & (phi < 190)) | (phi > 290)
+    for i in range(len(w)):
         perm, lvl = N.nbte_get_schedule(h, i)
         assert sorted(perm) == [0, 1, 2]
-    N.nbte_set_quadrature(h, s, w)
-    with pytest.raises(N.NbteError) as e:
-        N.nbte_get_schedule(h, 0)
-    assert e.value.status == N.ERR_MESH and "cycle" in e.value.message
+        level = np.empty(3, int)
+        for l in range(len(lvl) - 1):
+            level[perm[lvl[l]:lvl[l + 1]]] = l
+        lc, lf = N.nbte_get_lagged_faces(h, i)
+        assert (len(lc) > 0) == bool(cyclic[i]), (i, phi[i], lc)
+        lagged = set(zip(lc.tolist(), lf.tolist()))
+        for c in range(3):
+            for f in range(4):
+                n = g.nbr[c, f]
+                if n >= 0 and g.S[c, f] @ s[i] < 0 and (c, f) not in lagged:
+                    assert level[n] < level[c]
+        for c, f in lagged:
+            assert g.nbr[c, f] >= 0 and g.S[c, f] @ s[i] < 0
 
 
 def test_problem_too_large_for_32bit_offsets_is_refused_before_the_device():
