@@ -40,7 +40,7 @@ typedef int32_t nbte_status;
 #define NBTE_OK                 0
 #define NBTE_ERR_INVALID_ARG   -1  /* null pointer, size or enum out of range, NaN input */
 #define NBTE_ERR_MESH          -2  /* degenerate cell, non-manifold/non-conforming face, untagged boundary */
-#define NBTE_ERR_QUADRATURE    -3  /* |s| != 1, w <= 0, s_z != 0 in 2D, specular mirror not in the set */
+#define NBTE_ERR_QUADRATURE    -3  /* |s| != 1, w <= 0, specular mirror not in the set */
 #define NBTE_ERR_BOUNDARY      -4  /* tag without a condition, bad wall data */
 #define NBTE_ERR_ILL_POSED     -5  /* no thermalizing wall: the steady problem is singular */
 #define NBTE_ERR_OUT_OF_MEMORY -6  /* device allocation failed or batch budget exceeded */
@@ -98,6 +98,26 @@ nbte_status nbte_mesh_create(int32_t dim, int64_t n_nodes, const double *xyz,
                              nbte_mesh **out);
 void nbte_mesh_destroy(nbte_mesh *m);
 
+/* Read a Gmsh mesh file (MSH 4.1 or 2.2, ASCII; the mesh format of the
+ * paper's workflow).  The elements of the highest dimension are the cells (one
+ * type: 3-node triangles or 4-node quadrangles in 2D, 4-node tetrahedra or
+ * 8-node hexahedra in 3D); the elements one dimension lower that lie on the
+ * mesh boundary are the boundary faces, tagged with their physical group (0
+ * when they have none; lower-dimensional elements inside the domain, such as
+ * material interfaces, are skipped); each cell keeps its element's physical
+ * group as its region (nbte_mesh_get_regions), e.g. to place heat sources.
+ * Every boundary face of the cells must be present as an element.
+ * Coordinates are multiplied by scale (1e-9 for a file in nm).
+ * Errors: NBTE_ERR_INVALID_ARG (unreadable file, binary or unsupported format,
+ * unsupported element type, scale <= 0), NBTE_ERR_MESH (mixed cell types, as
+ * nbte_mesh_create). */
+nbte_status nbte_mesh_read_gmsh(const char *path, double scale, nbte_mesh **out);
+/* region[c] for every cell (n_cells entries): the physical group of its
+ * element in the mesh file, 0 for meshes built by nbte_mesh_create. */
+nbte_status nbte_mesh_get_regions(const nbte_mesh *m, int32_t *region);
+/* xc[3c..3c+2]: the centre (vertex average) of every cell, m (z = 0 in 2D). */
+nbte_status nbte_mesh_get_centroids(const nbte_mesh *m, double *xc);
+
 typedef struct {
     int32_t dim;
     int32_t faces_per_cell;
@@ -122,8 +142,11 @@ nbte_status nbte_set_bands(nbte_problem *p, int32_t n_bands, const double *C, co
                            const double *tau);
 
 /* Discrete-ordinates quadrature (Methods, Eqs. (4), (7), (11)): unit directions
- * s (n_dirs*3, row-major) and weights w > 0; W_Omega = sum w.  In 2D every
- * s_z must be 0 (in-plane directions).  Errors: NBTE_ERR_QUADRATURE. */
+ * s (n_dirs*3, row-major) and weights w > 0; W_Omega = sum w.  On a 2D mesh
+ * the directions may be in-plane (s_z = 0, a 2D material) or span the sphere
+ * (a 3D material over a domain that does not vary along z, as the paper's
+ * diamond film): the faces see the in-plane part of s, a direction along z
+ * carries nothing between cells.  Errors: NBTE_ERR_QUADRATURE. */
 nbte_status nbte_set_quadrature(nbte_problem *p, int32_t n_dirs, const double *s, const double *w);
 
 typedef struct {

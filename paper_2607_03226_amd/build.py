@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libnbte.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mesh.cpp", "setup.cpp", "solver.cpp", "runner.cpp", "batch.cpp", "kernels.hip"]
+SOURCES = ["mesh.cpp", "mesh_io.cpp", "setup.cpp", "solver.cpp", "runner.cpp", "batch.cpp", "kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]

@@ -77,11 +77,16 @@ struct Mesh {
     std::vector<int32_t> bf_tag;     // NBF
     double total_volume = 0.0;
     double max_closure = 0.0;
+    std::vector<int32_t> region;     // N physical group of each cell (mesh files), empty otherwise
 };
 
 std::shared_ptr<Mesh> build_mesh(int32_t dim, int64_t n_nodes, const double *xyz, int32_t cell_type,
                                  int64_t n_cells, const int64_t *cell_nodes, int64_t n_bfaces,
                                  const int64_t *bface_nodes, const int32_t *bface_tag);
+// Gmsh MSH 4.1 / 2.2 ASCII file -> mesh (cells: the highest-dimension
+// elements; boundary faces: the lower-dimension elements on the boundary,
+// tagged by physical group; regions: the cells' physical groups)
+std::shared_ptr<Mesh> read_gmsh(const std::string &path, double scale);
 
 // ---------------------------------------------------------------- tables
 struct BandTable {

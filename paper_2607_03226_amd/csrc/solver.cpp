@@ -861,6 +861,33 @@ nbte_status nbte_mesh_create(int32_t dim, int64_t n_nodes, const double *xyz, in
 
 void nbte_mesh_destroy(nbte_mesh *m) { delete m; }
 
+nbte_status nbte_mesh_read_gmsh(const char *path, double scale, nbte_mesh **out) {
+    return guarded([&] {
+        if (!path || !out) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        *out = nullptr;
+        auto m = read_gmsh(path, scale);
+        *out = new nbte_mesh{std::move(m)};
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_mesh_get_regions(const nbte_mesh *m, int32_t *region) {
+    return guarded([&] {
+        if (!m || !region) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        const Mesh &mm = *m->m;
+        for (int64_t c = 0; c < mm.N; ++c) region[c] = mm.region.empty() ? 0 : mm.region[c];
+        return NBTE_OK;
+    });
+}
+
+nbte_status nbte_mesh_get_centroids(const nbte_mesh *m, double *xc) {
+    return guarded([&] {
+        if (!m || !xc) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
+        std::copy(m->m->xc.begin(), m->m->xc.end(), xc);
+        return NBTE_OK;
+    });
+}
+
 nbte_status nbte_mesh_get_info(const nbte_mesh *m, nbte_mesh_info *info) {
     return guarded([&] {
         if (!m || !info) throw Error(NBTE_ERR_INVALID_ARG, "null argument");
@@ -926,8 +953,6 @@ nbte_status nbte_set_quadrature(nbte_problem *p, int32_t n_dirs, const double *s
             if (!std::isfinite(nrm) || std::fabs(nrm - 1.0) > 1e-12)
                 throw Error(NBTE_ERR_QUADRATURE, "direction " + std::to_string(i) + " is not a unit vector");
             if (!(std::isfinite(w[i]) && w[i] > 0)) throw Error(NBTE_ERR_QUADRATURE, "weights must be finite and > 0");
-            if (p->mesh->dim == 2 && s[3 * i + 2] != 0.0)
-                throw Error(NBTE_ERR_QUADRATURE, "2D mesh needs in-plane directions (s_z = 0)");
             q.W += w[i];
         }
         p->quad = std::move(q);

@@ -75,6 +75,9 @@ SIGNATURES = [
     ("nbte_mesh_create", ct.c_int32, [ct.c_int32, ct.c_int64, _d, ct.c_int32, ct.c_int64, _i64, ct.c_int64, _i64,
                                       _i32, ct.POINTER(ct.c_void_p)]),
     ("nbte_mesh_destroy", None, [ct.c_void_p]),
+    ("nbte_mesh_read_gmsh", ct.c_int32, [ct.c_char_p, ct.c_double, ct.POINTER(ct.c_void_p)]),
+    ("nbte_mesh_get_regions", ct.c_int32, [ct.c_void_p, _i32]),
+    ("nbte_mesh_get_centroids", ct.c_int32, [ct.c_void_p, _d]),
     ("nbte_mesh_get_info", ct.c_int32, [ct.c_void_p, ct.POINTER(MeshInfo)]),
     ("nbte_problem_create", ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.POINTER(ct.c_void_p)]),
     ("nbte_problem_destroy", None, [ct.c_void_p]),
@@ -206,6 +209,26 @@ def nbte_mesh_create(dim, xyz, cell_type, cells, bfaces, bface_tag):
     _check(_lib.nbte_mesh_create(int(dim), xyz.shape[0], _ptr(xyz), ct_code, cells.shape[0], _ptr(cells, _i64),
                                  bfaces.shape[0], _ptr(bfaces, _i64), _ptr(tags, _i32), ct.byref(h)))
     return Mesh(h)
+
+
+def nbte_mesh_read_gmsh(path, scale=1.0):
+    h = ct.c_void_p()
+    _check(_lib.nbte_mesh_read_gmsh(os.fsencode(path), float(scale), ct.byref(h)))
+    return Mesh(h)
+
+
+def nbte_mesh_get_regions(mesh):
+    n = nbte_mesh_get_info(mesh)["n_cells"]
+    out = np.empty(n, np.int32)
+    _check(_lib.nbte_mesh_get_regions(mesh.handle, _ptr(out, _i32)))
+    return out
+
+
+def nbte_mesh_get_centroids(mesh):
+    n = nbte_mesh_get_info(mesh)["n_cells"]
+    out = np.empty((n, 3))
+    _check(_lib.nbte_mesh_get_centroids(mesh.handle, _ptr(out)))
+    return out
 
 
 def nbte_mesh_get_info(mesh):
@@ -427,12 +450,14 @@ def nbte_batch_get_info(b):
 
 # --- convenience: a whole problem description in one call -------------------
 
-def build_problem(problem, stream=None):
+def build_problem(problem, stream=None, mesh=None):
     """problem: any object with the attributes of a steady-solve request
-    (dim, xyz, cell_type, cells, bfaces, bface_tag, boundaries, C, v, tau, s, w).
-    Returns (mesh, problem handle)."""
-    mesh = nbte_mesh_create(problem.dim, problem.xyz, problem.cell_type, problem.cells, problem.bfaces,
-                            problem.bface_tag)
+    (dim, xyz, cell_type, cells, bfaces, bface_tag, boundaries, C, v, tau, s, w);
+    mesh: an existing mesh handle (e.g. nbte_mesh_read_gmsh) to use instead of
+    the problem's arrays.  Returns (mesh, problem handle)."""
+    if mesh is None:
+        mesh = nbte_mesh_create(problem.dim, problem.xyz, problem.cell_type, problem.cells, problem.bfaces,
+                                problem.bface_tag)
     p = nbte_problem_create(mesh, stream)
     nbte_set_bands(p, problem.C, problem.v, problem.tau)
     nbte_set_quadrature(p, problem.s, problem.w)
