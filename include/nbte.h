@@ -311,6 +311,16 @@ typedef struct {
                                  plain iteration.  Holds about (2 accel_depth + 4) state vectors of
                                  n_cells + n_rows x n_bands values on the device (counted by
                                  nbte_problem_footprint). */
+    int32_t inner_solver;     /* transport solve of each (band, direction) system in an iteration:
+                                 0 (default) the exact upwind sweep in level order; 1 matrix-free
+                                 BiCGSTAB with the Jacobi (diagonal) preconditioner (the paper's
+                                 optional iterative inner solver), one workgroup per system, every
+                                 interior face coupled implicitly (cyclic upwind graphs included),
+                                 started from the previous distribution.  Meant for small meshes: a
+                                 system's iterations run in one workgroup.  First-order face values
+                                 only (NBTE_ERR_INVALID_ARG with spatial_order 2). */
+    int32_t inner_max_iter;   /* BiCGSTAB iterations per system and outer iteration (0 = 500) */
+    double inner_rtol;        /* BiCGSTAB stop: ||r|| <= inner_rtol ||b|| (0 = 1e-13) */
 } nbte_tuning;
 nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t);
 nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t);

@@ -167,6 +167,12 @@ struct DeviceView {
     void NBTE_G *corr;             // D*N*B in stream order: -v sum_f a delta_f of the coming sweep
     void NBTE_G *bdelta;           // 2 slots of NBF*D*B: increments of the outgoing face values;
                                    // slot m & 1 belongs to the distribution of sweep m - 1
+    // Jacobi-BiCGSTAB inner solver: 9 vectors of D*B*N FP64 values, system
+    // (i B + l) at offset (i B + l) N of each; iteration cap and tolerance
+    double NBTE_G *bicg;
+    int32_t bicg_max_iter;
+    double bicg_rtol;
+    const double NBTE_G *Qc;       // N heat source per cell
 };
 
 // One workgroup's share of a launch: the solve (index into the descriptor
@@ -234,6 +240,9 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
 // (bpl = bands per block, up to 8); otherwise bpl is 1, 2 or 4.
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
                   int block, size_t lds_bytes, hipStream_t st, bool order2 = false);
+// The transport solve of every (band, direction) system by Jacobi-BiCGSTAB:
+// items (solve, direction, band, -), one 1024-thread workgroup per system.
+void launch_bicgstab(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
 size_t sweep_lds_bytes(int max_levels, int gring, int lstride, int slots, int elem_bytes);
 
 // Dynamic LDS of a sweep workgroup, in elements of the storage type (es

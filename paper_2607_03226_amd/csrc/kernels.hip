@@ -1007,6 +1007,142 @@ __global__ void __launch_bounds__(256) k_recon(const DeviceView *__restrict__ vs
 }
 
 // --------------------------------------------------------------------------
+// Jacobi-preconditioned BiCGSTAB of one (band, direction) system, the
+// paper's optional iterative inner solver; one workgroup per system:
+//   A g = b,   (A g)_c = d_c g_c - v sum_{a_cf < 0, interior} |a_cf| g_n,
+//   d_c = 1/tau + v sum_{a_cf > 0} a_cf,
+//   b_c = Qdot_c S_l + v sum_{a_cf < 0, boundary} |a_cf| ghost + v (C_l/W) D_c,
+// the deviation form of the sweep with every interior face implicit (also
+// the faces a cyclic order lags).  Right preconditioning by diag(d), started
+// from the stored distribution; stops at ||r|| <= rtol ||b||, the cap, or a
+// breakdown.  Work vectors (system-major, FP64): r, r0, p, v, s, t, p/d,
+// s/d, d.  Reductions are workgroup sums in a fixed order.
+// --------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(1024) k_bicgstab(const DeviceView *__restrict__ vs,
+                                                   const WorkItem *__restrict__ wk) {
+    __shared__ double red[32];
+    const WorkItem it = wk[blockIdx.x];
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    const int i = it.a, lam = it.b;
+    const int64_t N = v.N;
+    const int B = v.B, F = v.F, D = v.D;
+    const double *sd = v.dirs + 3 * i;
+    const double vel = v.vel[lam], itau = v.inv_tau[lam], cw = v.Cw[lam], src = v.src[lam];
+    T *x = static_cast<T *>(v.g) + (int64_t)i * N * B + lam;   // the system's values, stride B
+    const T *gv = static_cast<const T *>(v.gval);
+    const double *th = theta_cur(v);
+    const int64_t sys = (int64_t)i * B + lam, DBN = (int64_t)D * B * N;
+    double *r = v.bicg + sys * N, *r0 = r + DBN, *p = r + 2 * DBN, *vv = r + 3 * DBN, *sv = r + 4 * DBN,
+           *t = r + 5 * DBN, *ph = r + 6 * DBN, *sh = r + 7 * DBN, *d = r + 8 * DBN;
+    const int nt = blockDim.x;
+    auto coef = [&](int64_t c, int f) {
+        const double *S = v.Sv + (c * F + f) * 3;
+        return (sd[0] * S[0] + sd[1] * S[1] + sd[2] * S[2]) / v.V[c];
+    };
+    // A y for a vector y given by its values at cells (y(n))
+    auto apply = [&](int64_t c, auto &&y) {
+        double acc = d[c] * y(c);
+        for (int f = 0; f < F; ++f) {
+            const int32_t n = v.nbr[c * F + f];
+            if (n < 0) continue;
+            const double a = coef(c, f);
+            if (a < 0.0) acc += vel * a * y(n);
+        }
+        return acc;
+    };
+    double bb = 0.0, rr = 0.0;
+    for (int64_t c = threadIdx.x; c < N; c += nt) {
+        double dd = itau, b = v.Qc[c] * src, dsum = 0.0;
+        for (int f = 0; f < F; ++f) {
+            const double a = coef(c, f);
+            const int32_t n = v.nbr[c * F + f];
+            if (a > 0.0) {
+                dd += vel * a;
+            } else if (a < 0.0) {
+                if (n >= 0) {
+                    dsum += -a * (th[n] - th[c]);
+                } else {
+                    const int32_t row = v.in_row[(int64_t)(-n - 1) * D + i];
+                    b += vel * -a * ld(gv, (int64_t)row * B + lam);
+                }
+            }
+        }
+        b += vel * cw * dsum;
+        d[c] = dd;
+        sv[c] = b;   // b, until the residual is formed
+        bb += b * b;
+    }
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < N; c += nt) {
+        const double rc = sv[c] - apply(c, [&](int64_t n) { return ld(x, n * B); });
+        r[c] = rc;
+        r0[c] = rc;
+        p[c] = 0.0;
+        vv[c] = 0.0;
+        rr += rc * rc;
+    }
+    const double bn = sqrt(block_sum(bb, red));
+    const double tol2 = v.bicg_rtol * v.bicg_rtol * (bn > 0.0 ? bn * bn : 1.0);
+    if (!(block_sum(rr, red) > tol2)) return;
+    double rho = 1.0, alpha = 1.0, omega = 1.0;
+    for (int k = 0; k < v.bicg_max_iter; ++k) {
+        double acc = 0.0;
+        for (int64_t c = threadIdx.x; c < N; c += nt) acc += r0[c] * r[c];
+        const double rho_n = block_sum(acc, red);
+        if (rho_n == 0.0 || !isfinite(rho_n)) break;
+        const double beta = (rho_n / rho) * (alpha / omega);
+        for (int64_t c = threadIdx.x; c < N; c += nt) {
+            const double pc = r[c] + beta * (p[c] - omega * vv[c]);
+            p[c] = pc;
+            ph[c] = pc / d[c];
+        }
+        __syncthreads();
+        acc = 0.0;
+        for (int64_t c = threadIdx.x; c < N; c += nt) {
+            const double vc = apply(c, [&](int64_t n) { return ph[n]; });
+            vv[c] = vc;
+            acc += r0[c] * vc;
+        }
+        const double r0v = block_sum(acc, red);
+        if (r0v == 0.0 || !isfinite(r0v)) break;
+        alpha = rho_n / r0v;
+        acc = 0.0;
+        for (int64_t c = threadIdx.x; c < N; c += nt) {
+            const double sc = r[c] - alpha * vv[c];
+            sv[c] = sc;
+            sh[c] = sc / d[c];
+            acc += sc * sc;
+        }
+        if (!(block_sum(acc, red) > tol2)) {   // block_sum synchronises: sh is complete
+            for (int64_t c = threadIdx.x; c < N; c += nt) x[c * B] = static_cast<T>(ld(x, c * B) + alpha * ph[c]);
+            break;
+        }
+        double ts = 0.0, tt = 0.0;
+        for (int64_t c = threadIdx.x; c < N; c += nt) {
+            const double tc = apply(c, [&](int64_t n) { return sh[n]; });
+            t[c] = tc;
+            ts += tc * sv[c];
+            tt += tc * tc;
+        }
+        ts = block_sum(ts, red);
+        tt = block_sum(tt, red);
+        if (tt == 0.0 || !isfinite(tt)) break;
+        omega = ts / tt;
+        acc = 0.0;
+        for (int64_t c = threadIdx.x; c < N; c += nt) {
+            x[c * B] = static_cast<T>(ld(x, c * B) + alpha * ph[c] + omega * sh[c]);
+            const double rc = sv[c] - omega * t[c];
+            r[c] = rc;
+            acc += rc * rc;
+        }
+        rho = rho_n;
+        if (!(block_sum(acc, red) > tol2) || omega == 0.0) break;
+    }
+}
+
+// --------------------------------------------------------------------------
 // net heat flow through each boundary face: one wave per face
 //   J_f = sum_l v_l sum_i w_i (s_i . S_f) e
 // with e the owner's value for outgoing and the inflow for incoming directions
@@ -1926,6 +2062,12 @@ void launch_recon(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, in
     if (n <= 0) return;
     if (fp32) hipLaunchKernelGGL(k_recon<float>, dim3(n), dim3(256), 0, st, vs, wk, phase);
     else hipLaunchKernelGGL(k_recon<double>, dim3(n), dim3(256), 0, st, vs, wk, phase);
+}
+
+void launch_bicgstab(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_bicgstab<float>, dim3(n), dim3(1024), 0, st, vs, wk);
+    else hipLaunchKernelGGL(k_bicgstab<double>, dim3(n), dim3(1024), 0, st, vs, wk);
 }
 
 void launch_post(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {

@@ -152,6 +152,10 @@ struct nbte_problem {
     int acc_nblk = 1;
     int self_acc = 0, n_self_acc = 0;   // offsets in d_self_work: initial inflow state (face waves)
     int accel_m() const { return tuning.accel_depth; }
+    // Jacobi-BiCGSTAB inner solver (tuning.inner_solver = 1): eight work
+    // vectors per (band, direction) system, system-major
+    bool bicg() const { return tuning.inner_solver == 1; }
+    nbte::DevBuf d_bicg;
     // second-order face values (opts.spatial_order = 2)
     int order = 1;
     bool lsq_up = false;
@@ -169,7 +173,7 @@ struct nbte_problem {
     } shape;
     int slots_for_cap = -2;   // slot budget the current slot table was built for
     int prog_B = -1, prog_gcap = -1, prog_gring = -1, prog_ls = -1, prog_es = -1;
-    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0, 0};
+    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0.0};
 
     // iteration state
     bool prepared = false;

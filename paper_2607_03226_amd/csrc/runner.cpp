@@ -18,7 +18,7 @@ namespace nbte {
 namespace {
 
 enum Kind { K_MARK, K_STAGE, K_SWEEP, K_POST, K_WALL, K_PCG_BLOCK, K_PCG_MULTI, K_UPDATE, K_FINISH, K_ACC_COLS,
-            K_ACC_SOLVE, K_ACC_MIX, K_GRAD, K_RECON };
+            K_ACC_SOLVE, K_ACC_MIX, K_GRAD, K_RECON, K_BICG };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -126,6 +126,7 @@ void Runner::build() {
         std::map<Key, std::vector<int>> groups;
         for (int s = 0; s < M; ++s) {
             const nbte_problem &p = *members_[s];
+            if (p.bicg()) continue;   // transport solved by BiCGSTAB below
             const int mi = p.prog.maxin <= 2 ? 2 : (p.prog.maxin == 3 ? 3 : 5);
             const bool spill = p.shape.slots == 0 || p.sched.spilled > 0;
             const bool so2 = p.order == 2;   // second order: the general mode, several lanes per cell
@@ -188,6 +189,20 @@ void Runner::build() {
             while ((int)work.size() > L.off && work.back().solve < 0) work.pop_back();
             close(L);
         }
+    }
+
+    // members with the BiCGSTAB inner solver: one workgroup per system
+    for (bool f : {true, false}) {
+        Launch L;
+        L.kind = K_BICG;
+        L.fp32 = f;
+        L.off = (int)work.size();
+        each(f, [&](int s, nbte_problem &p) {
+            if (!p.bicg()) return;
+            for (int i = 0; i < p.quad.D; ++i)
+                for (int b = 0; b < p.bands.B; ++b) work.push_back({s, i, b, 0});
+        });
+        close(L);
     }
 
     mark(PH_MOM);
@@ -369,6 +384,7 @@ void Runner::enqueue_iteration(int slot) {
             case K_ACC_MIX: launch_accel_mix(vs, wk + L.off, L.n, L.fp32, stream_); break;
             case K_GRAD: launch_grad(vs, wk + L.off, L.n, L.fp32, 0, stream_); break;
             case K_RECON: launch_recon(vs, wk + L.off, L.n, L.fp32, 0, stream_); break;
+            case K_BICG: launch_bicgstab(vs, wk + L.off, L.n, L.fp32, stream_); break;
         }
     }
     NBTE_HIP(hipGetLastError());

@@ -372,6 +372,8 @@ int64_t nbte_problem::state_bytes(int prec, int ord) const {
     int64_t so2 = 0;
     if (ord == 2)   // gradient planes, correction, two boundary increment slots; weights and geometry
         so2 = 4 * D * N * B * es + 2 * NBF * D * B * es + (int64_t)mesh->F * N * 9 * 8 + N * 3 * 8 + NBF * 4;
+    if (bicg())     // BiCGSTAB work vectors and the geometry it reads
+        so2 += 9 * D * B * N * 8 + (ord == 2 ? 0 : (int64_t)mesh->F * N * 9 * 8 + N * 3 * 8 + NBF * 4);
     const int64_t ghosts = prog_B > 0 ? (int64_t)prog.ghost_src.size() : NBF * D;   // incoming pairs
     int64_t acc = 0;
     if (accel_m() > 0) {
@@ -418,7 +420,9 @@ void nbte_problem::allocate_state(int prec) {
     d_delta.alloc(N * 8);
     d_state.alloc(sizeof(SolveState));
     d_view.alloc(sizeof(DeviceView));
-    if (order == 2) {
+    if (bicg()) d_bicg.alloc((size_t)9 * D * B * N * 8);
+    else d_bicg.release();
+    if (order == 2 || bicg()) {
         if (!lsq_up) {
             const Mesh &m = *mesh;
             upload(d_lsq, build_lsq_weights(m), stream);
@@ -429,6 +433,8 @@ void nbte_problem::allocate_state(int prec) {
             NBTE_HIP(hipStreamSynchronize(stream));   // the host copies go out of scope
             lsq_up = true;
         }
+    }
+    if (order == 2) {
         d_grad.alloc((size_t)3 * D * N * B * es);
         d_corr.alloc((size_t)D * N * B * es);
         d_bdelta.alloc((size_t)2 * std::max<int64_t>(NBF, 1) * D * B * es);
@@ -462,7 +468,7 @@ int64_t nbte_problem::device_bytes() const {
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work, &d_acc_x, &d_acc_G, &d_acc_fprev,
           &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal, &d_lsq, &d_Sv, &d_xf, &d_xc, &d_bf_local,
-          &d_grad, &d_corr, &d_bdelta})
+          &d_grad, &d_corr, &d_bdelta, &d_bicg})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -569,6 +575,10 @@ void nbte_problem::make_view() {
     v.grad = d_grad.ptr;
     v.corr = d_corr.ptr;
     v.bdelta = d_bdelta.ptr;
+    v.bicg = d_bicg.as<double>();
+    v.bicg_max_iter = tuning.inner_max_iter > 0 ? tuning.inner_max_iter : 500;
+    v.bicg_rtol = tuning.inner_rtol > 0 ? tuning.inner_rtol : 1e-13;
+    v.Qc = d_Q.as<double>();
     hv = v;
 }
 
@@ -579,6 +589,8 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     if (o.spatial_order != 1 && o.spatial_order != 2) throw Error(NBTE_ERR_INVALID_ARG, "spatial_order must be 1 or 2");
     if (o.spatial_order == 2 && accel_m() > 0)
         throw Error(NBTE_ERR_INVALID_ARG, "the second-order scheme is not combined with Anderson acceleration");
+    if (o.spatial_order == 2 && bicg())
+        throw Error(NBTE_ERR_INVALID_ARG, "the BiCGSTAB inner solver solves the first-order systems only");
     if (!std::isfinite(o.T_ref)) throw Error(NBTE_ERR_INVALID_ARG, "bad T_ref");
     if (o.T_ref != T_ref) {
         T_ref = o.T_ref;
@@ -1173,6 +1185,8 @@ nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t) {
         if (t->cg_max_iter < 0 || !(t->cg_rtol >= 0)) throw Error(NBTE_ERR_INVALID_ARG, "bad CG settings");
         if (t->accel_depth < 0 || t->accel_depth > kAccelMaxDepth)
             throw Error(NBTE_ERR_INVALID_ARG, "accel_depth must be in [0, 8]");
+        if (t->inner_solver < 0 || t->inner_solver > 1 || t->inner_max_iter < 0 || !(t->inner_rtol >= 0))
+            throw Error(NBTE_ERR_INVALID_ARG, "bad inner solver settings");
         if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member");
         p->tuning = *t;
         p->prepared = false;   // launch shape and slot table are rebuilt by the next prepare
