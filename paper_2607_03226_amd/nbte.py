@@ -476,7 +476,7 @@ def solve(problem, precision=None, scheme=None, tol=1e-8, max_iter=10000, check_
     precision = precision or problem.precision
     if tuning == "auto":
         from . import tune
-        tuning = tune.lookup(problem, precision)
+        tuning = tune.settings(problem, precision, p)
     if accel is not None:
         tuning = dict(tuning or {}, accel_depth=int(accel))
     if tuning:

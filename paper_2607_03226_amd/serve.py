@@ -35,6 +35,7 @@ class Served:
     iterations: int = 0
     residual: float = float("nan")
     converged: bool = False
+    updates: int = 0            # cell x band x direction updates of its iterations
     result: dict = field(default=None, repr=False)
 
     @property
@@ -50,7 +51,8 @@ def percentile(x, q):
 
 
 def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_iter=20000, step=8,
-          keep_results=False, tuning=None, clock=time.perf_counter, log=None, lookahead=4):
+          keep_results=False, tuning=None, clock=time.perf_counter, log=None, lookahead=4, progress=0,
+          progress_log=print):
     """Run the request stream.
 
     requests  list of problem descriptions (see nbte.build_problem)
@@ -59,11 +61,15 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
               may hold together (0: no limit)
     tuning    None, "auto" (autotuner cache) or a dict of launch-shape settings
     lookahead waiting requests whose setup runs ahead on host threads
+    progress  report every `progress` finished requests through progress_log
+    requests may be a sequence that builds requests on demand and has
+    release(j) (workloads.configs.RequestStream): served ones are released.
     Returns (list of Served, summary dict).
     """
     n = len(requests)
     batch = N.nbte_batch_create(budget_bytes)
-    served = [Served(j, requests[j].name, float(arrivals[j])) for j in range(n)]
+    served = [Served(j, "", float(arrivals[j])) for j in range(n)]
+    release = getattr(requests, "release", None)   # streams generated on demand drop served requests
     queue = collections.deque()
     handles = {}                # handle value -> (index, mesh, problem handle)
     next_arrival = 0
@@ -88,10 +94,11 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
 
     def host_part(j):
         p = requests[j]
+        served[j].name = p.name
         mesh, h = N.build_problem(p)
         if tuning == "auto":
             from . import tune
-            shape = tune.lookup(p, precision)
+            shape = tune.settings(p, precision, h)
             if shape:
                 N.nbte_set_tuning(h, **shape)
         elif tuning:
@@ -174,6 +181,7 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
             s = served[j]
             s.finished = now()
             s.iterations = out["iterations"]
+            s.updates = requests[j].updates_per_sweep * s.iterations
             s.residual = out["residual"]
             s.converged = bool(out["residual"] <= tol)
             if keep_results:
@@ -183,6 +191,10 @@ def serve(requests, arrivals, budget_bytes, precision="mixed", tol=1e-8, max_ite
                 log(f"serve: t={s.finished:.3f} s finished {j} {s.name} in {s.iterations} iterations, "
                     f"latency {s.latency:.3f} s")
             del mesh, hh
+            if release:
+                release(j)
+            if progress and done_count % progress == 0:
+                progress_log(f"serve: {done_count}/{n} finished at t={now():.1f} s")
     pool.shutdown(wait=True)
     lat = [s.latency for s in served]
     span = max(s.finished for s in served) - min(s.arrival for s in served)

@@ -1,9 +1,10 @@
-"""Autotuner of the sweep launch shape and the correction's CG cap.
+"""Autotuner of the sweep launch shape and the iteration settings.
 
 For a problem it times candidate shapes (bands per workgroup, bands per lane,
 workgroup size, LDS budget) through the C ABI's HIP-event phase timers and
-keeps the fastest; for the synthetic schemes it then picks the CG iteration
-cap of the diffusion correction by time-to-converge.  Results are cached in tune_cache.json next to this file,
+keeps the fastest; it then picks the CG iteration cap of the diffusion
+correction (synthetic schemes) and the Anderson depth of the outer iteration
+together, by time-to-converge.  Results are cached in tune_cache.json next to this file,
 keyed by (cell type, cell-count bucket, bands, directions, precision), and
 looked up by nbte.solve(..., tuning="auto").
 """
@@ -41,6 +42,18 @@ def save_cache(cache):
 
 def lookup(problem, precision):
     return load_cache().get(key(problem, precision), {}).get("shape")
+
+
+def settings(problem, precision, h):
+    """The cached settings to run a built problem with (None if its workload
+    class was never tuned).  A cached Anderson depth is dropped when the
+    problem's upwind graphs have lagged (cyclic) faces: the library does not
+    accelerate those, and the cache entry is shared by every mesh of the class."""
+    shape = lookup(problem, precision)
+    if shape and shape.get("accel_depth", 0) > 0:
+        if any(len(N.nbte_get_lagged_faces(h, d)[0]) for d in range(problem.n_dirs)):
+            shape = dict(shape, accel_depth=0)
+    return shape
 
 
 WHOLE_CU_LDS = 163840   # a CU's LDS: one sweep workgroup per CU, every value staged where it fits
@@ -91,11 +104,35 @@ def time_to_converge(h, problem, precision, shape, tol=1e-8, max_iter=20000, rep
     return best, iters
 
 
+def tune_convergence(h, problem, precision, shape, cg_choices=(4, 8, 16, 32), accel_choices=(0, 5, 8),
+                     verbose=True):
+    """The iteration settings by time-to-converge on a fixed launch shape: the
+    correction's CG iteration cap (synthetic schemes; fewer CG launches per
+    iteration against more outer iterations) jointly with the Anderson depth
+    of the outer iteration (0 = plain).  Returns the shape with both set."""
+    caps = cg_choices if problem.scheme != "sequential" and cg_choices else (shape.get("cg_max_iter", 0),)
+    conv = []
+    for acc in accel_choices:
+        for cg in caps:
+            trial = dict(shape, cg_max_iter=cg, accel_depth=acc)
+            try:
+                sec, it = time_to_converge(h, problem, precision, trial)
+            except N.NbteError as e:      # e.g. acceleration on a mesh with lagged faces
+                if verbose:
+                    print(f"tune: {problem.name} {precision} accel {acc} cg {cg}: {e}", flush=True)
+                continue
+            conv.append((sec, acc, cg))
+            if verbose:
+                print(f"tune: {problem.name} {precision} accel_depth {acc} cg_max_iter {cg}: converged in {it} "
+                      f"iterations, {sec:.4f} s", flush=True)
+    sec, acc, cg = min(conv)
+    return dict(shape, cg_max_iter=cg, accel_depth=acc)
+
+
 def tune(problem, precision="mixed", shapes=None, iters=4, verbose=True, write=True,
-         cg_choices=(4, 6, 8, 12, 16, 24, 32)):
-    """Fastest sweep shape by sweep time; then, for the synthetic schemes, the
-    correction's CG iteration cap by time-to-converge (fewer CG launches per
-    iteration against more outer iterations)."""
+         cg_choices=(4, 8, 16, 32), accel_choices=(0, 5, 8)):
+    """Fastest sweep shape by sweep time; then the correction's CG iteration
+    cap and the outer Anderson depth by time-to-converge (tune_convergence)."""
     mesh, h = N.build_problem(problem)
     table = []
     t0 = time.time()
@@ -112,16 +149,7 @@ def tune(problem, precision="mixed", shapes=None, iters=4, verbose=True, write=T
             print(f"tune: {problem.name} {precision} {shape} sweep {ms:.4f} ms ({ups:.3e} updates/s)", flush=True)
     table.sort(key=lambda t: t[0])
     best_ms, best = table[0]
-    best = dict(best)
-    if problem.scheme != "sequential" and cg_choices:
-        conv = []
-        for cg in cg_choices:
-            sec, it = time_to_converge(h, problem, precision, dict(best, cg_max_iter=cg))
-            conv.append((sec, cg))
-            if verbose:
-                print(f"tune: {problem.name} {precision} cg_max_iter {cg}: converged in {it} iterations, {sec:.4f} s",
-                      flush=True)
-        best["cg_max_iter"] = min(conv)[1]
+    best = tune_convergence(h, problem, precision, dict(best), cg_choices, accel_choices, verbose)
     if write:
         cache = load_cache()
         cache[key(problem, precision)] = {"shape": best, "sweep_ms": best_ms, "workload": problem.name,
@@ -131,10 +159,32 @@ def tune(problem, precision="mixed", shapes=None, iters=4, verbose=True, write=T
     return best, best_ms, table
 
 
+def retune_convergence(problem, precision="mixed", verbose=True, **kw):
+    """Redo only the iteration settings of a cached entry (its launch shape kept)."""
+    cache = load_cache()
+    k = key(problem, precision)
+    if k not in cache:
+        return tune(problem, precision, verbose=verbose)[0]
+    mesh, h = N.build_problem(problem)
+    shape = {a: b for a, b in cache[k]["shape"].items() if a not in ("cg_max_iter", "accel_depth")}
+    best = tune_convergence(h, problem, precision, shape, verbose=verbose, **kw)
+    cache = load_cache()
+    cache[k]["shape"] = best
+    cache[k]["converge_tuned_at"] = time.strftime("%Y-%m-%d %H:%M:%S")
+    save_cache(cache)
+    return best
+
+
 if __name__ == "__main__":
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from workloads import configs as C
+    if sys.argv[1:2] == ["--converge"]:
+        for name in sys.argv[2:]:
+            p = {"config1": C.config1, "config2": C.config2, "config3": C.config3}[name]()
+            for prec in ("mixed", "fp64"):
+                print(f"tune: BEST {name} {prec} {retune_convergence(p, prec)}", flush=True)
+        sys.exit(0)
     names = sys.argv[1:] or ["config2"]
     for name in names:
         if name == "config4":

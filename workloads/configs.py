@@ -229,6 +229,60 @@ def serving_request(seed, families=("rect2d", "box3d", "finfet"), size_scale=1.0
                    meta={"config": 5, "family": kind, "seed": seed})
 
 
+class RequestStream:
+    """The requests serving_request(first + j), j < n, generated ahead of use
+    on a background thread (at most `ahead` beyond the highest index asked
+    for) and dropped with release(j), so a long stream never holds all its
+    meshes.  Indexing blocks until the request exists."""
+
+    def __init__(self, first, n, ahead=48, **kw):
+        import threading
+        self.first, self.n, self.ahead, self.kw = first, n, ahead, kw
+        self.items = {}
+        self.want = 0
+        self.next = 0
+        self.cv = threading.Condition()
+        self.stop = False
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
+
+    def _run(self):
+        while True:
+            with self.cv:
+                while not self.stop and (self.next >= self.n or self.next > self.want + self.ahead):
+                    self.cv.wait()
+                if self.stop:
+                    return
+                j = self.next
+            p = serving_request(self.first + j, **self.kw)
+            with self.cv:
+                self.items[j] = p
+                self.next = j + 1
+                self.cv.notify_all()
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, j):
+        with self.cv:
+            self.want = max(self.want, j)
+            self.cv.notify_all()
+            while j not in self.items:
+                if j < self.next:
+                    raise KeyError(f"request {j} was released")
+                self.cv.wait()
+            return self.items[j]
+
+    def release(self, j):
+        with self.cv:
+            self.items.pop(j, None)
+
+    def close(self):
+        with self.cv:
+            self.stop = True
+            self.cv.notify_all()
+
+
 def poisson_arrivals(n, rate, seed=5):
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, n))
