@@ -321,6 +321,13 @@ typedef struct {
                                  only (NBTE_ERR_INVALID_ARG with spatial_order 2). */
     int32_t inner_max_iter;   /* BiCGSTAB iterations per system and outer iteration (0 = 500) */
     double inner_rtol;        /* BiCGSTAB stop: ||r|| <= inner_rtol ||b|| (0 = 1e-13) */
+    int32_t layout;           /* distribution layout in device memory: 1 cell-major (the bands of a
+                                 (direction, cell) contiguous); 2 per direction in planes of the
+                                 sweep's band blocks in upwind (level) order, so the sweep stores
+                                 whole lines, at the price of a permuting reduction pass and a
+                                 cell-major copy of the boundary cells' values; 0 (default) = 2 for
+                                 n_cells x n_dirs x n_bands >= 2^26, else 1.  Results agree to
+                                 rounding (summation order of the reductions). */
 } nbte_tuning;
 nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t);
 nbte_status nbte_get_tuning(const nbte_problem *p, nbte_tuning *t);

@@ -87,6 +87,15 @@ struct AccelWork {
     double NBTE_G *scal;         // [0] steps done; [1..m*m] Gram matrix dF_i . dF_j; then m gammas
 };
 
+// The reductions' first stage per (direction, cell): band sums of the
+// distribution weighted by 1/tau, 1 and the group velocity, accumulated and
+// kept in FP64 on both paths (the moments are small differences of the
+// directions' sums; FP32 roundings of the sums measurably moved the mixed
+// path's heat flux).
+struct Mom3 {
+    double a, w, u;
+};
+
 // Everything the kernels read and write of one solve, as raw device pointers.
 struct DeviceView {
     int64_t N;       // cells
@@ -96,7 +105,8 @@ struct DeviceView {
     int32_t fp32;    // g stored in FP32 (else FP64)
     int64_t NBF;     // boundary faces
     int32_t scheme;  // NBTE_SCHEME_*
-    int32_t mom_lpc; // lanes per cell of the reductions
+    int32_t mom_lpc; // lanes per cell of the cell-major reductions
+    int32_t planes;  // distribution layout: 0 cell-major, 1 band-block planes in stream order
     // mesh
     const int32_t NBTE_G *nbr;     // N*F
     const double NBTE_G *V;        // N
@@ -142,7 +152,25 @@ struct DeviceView {
     const int32_t NBTE_G *lag;
     const double NBTE_G *bf_thw, *bf_p, *sdotS, *win;
     // state
-    void NBTE_G *g;                // D*N*B, FP32 or FP64: non-equilibrium part e - C theta/W
+    // g: D*N*B, FP32 or FP64: non-equilibrium part e - C theta/W.
+    // Cell-major layout: (i, c, l) at (i N + c) B + l.  Plane layout: per
+    // direction in band-block planes (bpb bands; the last block may be
+    // narrower), each plane in the direction's stream order: (i, c, l) at
+    //   i N B + k N bpb + pos[i N + c] w_k + (l - k bpb),
+    //   k = l / bpb,  w_k = min(bpb, B - k bpb)
+    // so a sweep workgroup (direction, band block) writes one contiguous run
+    // per pass
+    void NBTE_G *g;
+    const int32_t NBTE_G *pos;     // D*N: stream position of cell c in direction i (at i N + c)
+    // plane layout only: boundary rows, the distribution of every cell that
+    // owns a boundary face, all directions and bands, row (bown[c] D + i) of
+    // B values in the storage type, copied from the planes by the
+    // reductions' first stage and read by the boundary inflow and flux; and
+    // the first stage's per (direction, cell) band sums
+    const int32_t NBTE_G *bown;    // N: the cell's index among the boundary-owner cells, -1 if none
+    const int32_t NBTE_G *bf_brow; // NBF: the boundary row of the face's owner (bown of the owner)
+    void NBTE_G *brow;             // n_bown D B values
+    void NBTE_G *mom;              // D*N Mom3 triples: band sums of g weighted by 1/tau, 1 and v
     void NBTE_G *gval;             // n_ghost*B boundary inflow in sweep (ghost) order, type T, as the
                                    // deviation from equilibrium at the sweep's theta of the owner cell
     double NBTE_G *Jw;             // NBF: net flux through each boundary face
@@ -194,8 +222,16 @@ void launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 //            kind 4 = the ghost rows of lagged faces (grid-stride over rows x bands)
 //   flux:    per-band outgoing sums and net flow, one wave per boundary face
 //            (items (solve, -, b, nblk): faces b*4 + wave, strided by 4 nblk)
-//   post:    kind 0 = flux mode 0 face groups (as above); kind 1 = band x
-//            direction reductions, mom_lpc lanes per cell, item b = block b
+//   post:    cell-major layout: kind 0 = flux mode 0 face groups (as above),
+//            kind 1 = band x direction reductions, mom_lpc lanes per cell,
+//            item b = block b; plane layout: kind 2 = first stage of the
+//            reductions, the band sums of one stream position per thread and
+//            the boundary rows, item (solve, 2, chunk of 256 positions,
+//            direction); solve < 0 pads
+//   reduce:  plane layout: kind 0 = flux mode 0 face groups; kind 1 = second
+//            stage of the reductions, the direction sums of every cell, the
+//            moments and the correction's right-hand side (grid-stride over
+//            the cells, kReduceLanes lanes per cell)
 //   wall rhs: the reflective faces' net flows into the correction's
 //            right-hand side (grid-stride over the cells that own one)
 //   update:  theta update and residual maxima (grid-stride over the cells)
@@ -215,6 +251,9 @@ void launch_post(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hip
 // outgoing increments of the boundary faces (items (solve, 1, b, nblk)).
 void launch_grad(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int phase, hipStream_t st);
 void launch_recon(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int phase, hipStream_t st);
+void launch_reduce(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
+constexpr int kReduceLanes = 4;   // lanes per cell of reduction stage 2 (a power of two)
+constexpr int64_t kPlanesMinValues = int64_t(1) << 26;   // auto layout: planes from 2^26 distribution values
 void launch_wall_rhs(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 void launch_update(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st);
 // Anderson step after an iteration's finish (solves with acc.m > 0; each
@@ -239,7 +278,7 @@ void launch_finish(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t 
 // values spilled to HBM (LDS budget too small).  one: one lane per cell
 // (bpl = bands per block, up to 8); otherwise bpl is 1, 2 or 4.
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
-                  int block, size_t lds_bytes, hipStream_t st, bool order2 = false);
+                  int block, size_t lds_bytes, hipStream_t st, bool order2, bool planes);
 // The transport solve of every (band, direction) system by Jacobi-BiCGSTAB:
 // items (solve, direction, band, -), one 1024-thread workgroup per system.
 void launch_bicgstab(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st);
@@ -289,8 +328,11 @@ constexpr int64_t kPcgBlockMaxRows = 8192;   // larger systems use the multi-wor
 void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, int patience, hipStream_t st);
 void launch_collect_states(const DeviceView *vs, int n, SolveState *out, hipStream_t st);
 
+// the FP32 distribution in planes of bpb_in bands into the FP64 one in planes
+// of bpb_out bands (D directions of N cells, B bands)
+void launch_widen(int64_t D, int64_t N, int B, const float *in, int bpb_in, double *out, int bpb_out, hipStream_t st);
 // out[k] = in[k] widened to FP64
-void launch_widen(int64_t n, const float *in, double *out, hipStream_t st);
+void launch_widen_flat(int64_t n, const float *in, double *out, hipStream_t st);
 
 // Single-solve helpers (outside the iteration).
 // out[k] = offset + scale * in[k]

@@ -44,6 +44,56 @@ __device__ __forceinline__ double NBTE_G *theta_spare(const DeviceView &v) {
     return theta_at(v, (th_cur(v.state) + 2) % 3);
 }
 
+// Distribution layout: per direction, band-block planes of the sweep's bands
+// per workgroup, each in the direction's stream (level) order.  Band l lies
+// in plane k = l / bpb at offset k N bpb + (l - k bpb); the plane's rows are
+// w_k = min(bpb, B - k bpb) values wide (one row per stream position).
+struct GPlane {
+    int64_t off;   // offset of band l within a direction's N B values, at position 0
+    int w;         // row width of its plane
+};
+__device__ __forceinline__ GPlane gplane(const DeviceView &v, int lam) {
+    const int k = lam / v.bpb;
+    GPlane p;
+    p.off = (int64_t)k * v.N * v.bpb + (lam - k * v.bpb);
+    p.w = min(v.bpb, v.B - k * v.bpb);
+    return p;
+}
+// element of band p at stream position t of direction i
+__device__ __forceinline__ int64_t gat_pos(const DeviceView &v, const GPlane &p, int64_t i, int64_t t) {
+    return i * v.N * v.B + p.off + t * p.w;
+}
+// element of band p at cell c of direction i
+__device__ __forceinline__ int64_t gat_cell(const DeviceView &v, const GPlane &p, int64_t i, int64_t c) {
+    return gat_pos(v, p, i, v.pos[i * v.N + c]);
+}
+
+// element of (direction i, cell c, band lam) in the solve's layout
+__device__ __forceinline__ int64_t g_elem(const DeviceView &v, int64_t i, int64_t c, int lam) {
+    return v.planes ? gat_cell(v, gplane(v, lam), i, c) : (i * v.N + c) * v.B + lam;
+}
+
+// The distribution of a boundary face's owner: value (i, lam) at
+// p[i * stride + lam] (cell-major: the distribution itself; plane layout:
+// the owner's boundary row)
+template <class T>
+struct OwnerRows {
+    const T *p;
+    int64_t stride;
+};
+template <class T>
+__device__ __forceinline__ OwnerRows<T> owner_rows(const DeviceView &v, int64_t bf) {
+    OwnerRows<T> o;
+    if (v.planes) {
+        o.p = static_cast<const T *>(v.brow) + (int64_t)v.bf_brow[bf] * v.D * v.B;
+        o.stride = v.B;
+    } else {
+        o.p = static_cast<const T *>(v.g) + (int64_t)v.bf_owner[bf] * v.B;
+        o.stride = v.N * v.B;
+    }
+    return o;
+}
+
 // bit pattern of a non-negative double: ordered like the values (atomic maxima)
 __device__ __forceinline__ unsigned long long dbits(double x) {
     return static_cast<unsigned long long>(__double_as_longlong(x));
@@ -148,7 +198,7 @@ __device__ void bc_face_abs(const DeviceView &v, int64_t bf, double *dst) {
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
-    const T *g = static_cast<const T *>(v.g);
+    const OwnerRows<T> og = owner_rows<T>(v, bf);   // the owner's distribution
     const int32_t *row = v.in_row + bf * D;
     const int BL = B < 64 ? B : 64;
     const int JG = 64 / BL;
@@ -179,7 +229,7 @@ __device__ void bc_face_abs(const DeviceView &v, int64_t bf, double *dst) {
             const int r = row[i];
             if (r < 0) continue;
             double t = (1.0 - p) * diff;
-            if (p > 0.0) t += p * (ld(g, ((int64_t)mir[i] * N + c) * B + lam) / cw + thp);
+            if (p > 0.0) t += p * (ld(og.p, (int64_t)mir[i] * og.stride + lam) / cw + thp);
             dst[(int64_t)r * B + lam] = t;
         }
     }
@@ -195,7 +245,6 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
     const int D = v.D, B = v.B;
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
-    const T *g = static_cast<const T *>(v.g);
     T *gv = static_cast<T *>(v.gval);
     const double *sd = v.sdotS + bf * D;
     const int32_t *row = v.in_row + bf * D;
@@ -221,6 +270,7 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
     const double p = v.bf_p[bf];
     const double iw = 1.0 / v.win[bf];
     const int32_t *mir = v.mirror + bf * D;
+    const OwnerRows<T> og = owner_rows<T>(v, bf);   // the owner's distribution
     // second order: the owner's outgoing face values carry their increments
     // (slot of the distribution this stage reads)
     const T *bd = v.order == 2 ? static_cast<const T *>(v.bdelta) + (int64_t)(v.state->iterations & 1) * v.NBF * D * B +
@@ -240,7 +290,7 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
             for (int i = jg; i < D; i += JG) {
                 const int r = row[i];
                 const int mi = mir[i] >= 0 ? mir[i] : 0;   // outgoing directions have no mirror entry
-                const double em = ld(g, ((int64_t)mi * N + c) * B + lam) + eq + (bd ? ld(bd, (int64_t)mi * B + lam) : 0.0);
+                const double em = ld(og.p, (int64_t)mi * og.stride + lam) + eq + (bd ? ld(bd, (int64_t)mi * B + lam) : 0.0);
                 const double e = (1.0 - p) * diff + p * em;
                 if (r >= 0) {
                     gv[(int64_t)r * B + lam] = static_cast<T>(e - eqc);
@@ -315,7 +365,7 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
         for (int64_t t = (int64_t)it.b * blockDim.x + threadIdx.x; t < v.n_lag * B; t += (int64_t)it.c * blockDim.x) {
             const int lam = (int)(t % B);
             const int32_t *L = v.lag + 4 * (t / B);
-            const double e = ld(g, ((int64_t)L[1] * N + L[3]) * B + lam) + v.Cw[lam] * thp[L[3]];
+            const double e = ld(g, g_elem(v, L[1], L[3], lam)) + v.Cw[lam] * thp[L[3]];
             gv[(int64_t)L[0] * B + lam] = static_cast<T>(e - v.Cw[lam] * thc[L[2]]);
         }
     } else if (it.a >= 2) {
@@ -447,7 +497,7 @@ __device__ __forceinline__ SweepStreams sweep_streams(const DeviceView &v, int64
     return S;
 }
 
-template <class T, int MI>
+template <class T, int MI, bool PL>
 __device__ __forceinline__ void load_rec(SweepRec<T, MI> &r, const SweepStreams &S, int k, int kend) {
     // the loads are issued on every path (a past-the-end record reads stream
     // position 0 of the direction), so the number of loads in flight is the
@@ -456,7 +506,7 @@ __device__ __forceinline__ void load_rec(SweepRec<T, MI> &r, const SweepStreams 
     r.ok = k < kend;
     const uint32_t at = (uint32_t)(r.ok ? k : 0);
     const uint32_t o4 = at * 4u, oT = at * (uint32_t)sizeof(T);
-    r.c = bload<int>(S.ints, o4, 0);
+    if constexpr (!PL) r.c = bload<int>(S.ints, o4, 0);   // the plane layout stores by stream position
     r.mine = bload<int>(S.ints, o4, S.row4);
     r.sout = bload<T>(S.reals, oT, 0);
     r.dc = bload<T>(S.reals, oT, S.rowT);
@@ -561,9 +611,9 @@ struct CorrVals {
 template <class T, int BPL>
 struct CorrVals<T, BPL, false> {};
 
-template <class T, int MI, int BPL, bool SO2 = false>
+template <class T, int MI, int BPL, bool SO2, bool PL>
 __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const DeviceView &v, const BandConst<T, BPL> &bc,
-                                           T NBTE_G *gi, int64_t base, int b0, int lane, int nb_here,
+                                           T NBTE_G *gi, uint32_t row, int64_t base, int b0, int lane, int nb_here,
                                            const CorrVals<T, BPL, SO2> &cv = CorrVals<T, BPL, SO2>{}) {
     const int B = v.B;
     const T NBTE_G *gval = static_cast<const T NBTE_G *>(v.gval);
@@ -571,7 +621,8 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
     // padding bands read valid rows (band clamped) and are never stored
     const int lofs = lane * BPL;
     const int nv = max(0, min(BPL, nb_here - lofs));
-    const bool vst = (B % BPL) == 0 && (b0 % BPL) == 0 && nv == BPL;   // whole-lane stores are aligned
+    // whole-lane stores are aligned (cell-major rows of B values, plane rows of nb_here)
+    const bool vst = (B % BPL) == 0 && (b0 % BPL) == 0 && (nb_here % BPL) == 0 && nv == BPL;
     T out[BPL];
 #pragma unroll
     for (int jb = 0; jb < BPL; ++jb) {
@@ -588,10 +639,12 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
             } else if (rf >= -kSpill) {
                 up = gval[(int64_t)(-1 - rf) * B + lam];   // ghost beyond the LDS capacity
             } else {
-                // value without an LDS slot: its stored copy, located through
-                // the neighbour's position in this direction's streams
-                const int n = v.p_cell[base + (-(kSpill + 1) - rf)];
-                up = gi[(int64_t)n * B + lam];
+                // value without an LDS slot: its stored copy at the
+                // neighbour's position (plane layout: that row of this band
+                // block's plane; cell-major: the neighbour cell's row)
+                const int64_t at = -(kSpill + 1) - rf;
+                if constexpr (PL) up = gi[at * nb_here + min(lb, nb_here - 1)];
+                else up = gi[(int64_t)v.p_cell[base + at] * B + lam];
             }
             gain += r.cf[j] * up;
         }
@@ -602,7 +655,7 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
     }
     // one LDS access and one store per 16 bytes, as in the LDS-only path
     lds_write_bands<T, BPL>(r.mine + lofs, out);   // own slot, or the scratch block
-    const uint32_t gc = (uint32_t)r.c * (uint32_t)B + (uint32_t)(b0 + lofs);
+    const uint32_t gc = row + (uint32_t)lofs;
     if (vst) {
         gstore_bands<T, BPL>(gi, gc, out);
     } else {
@@ -620,7 +673,7 @@ __device__ __forceinline__ void sweep_cell(const SweepRec<T, MI> &r, const Devic
 // is past the end), and stores to HBM only for live records.
 template <class T, int MI, int BPL>
 __device__ __forceinline__ void sweep_cell_lds(const SweepRec<T, MI> &r, const BandConst<T, BPL> &bc, T NBTE_G *gi,
-                                               int B, int b0, int lofs, int nv, bool vst, int trash) {
+                                               uint32_t row, int lofs, int nv, bool vst, int trash) {
     T up[MI][BPL];
 #pragma unroll
     for (int j = 0; j < MI; ++j) lds_read_bands<T, BPL>(r.ref[j] + lofs, up[j]);
@@ -635,7 +688,7 @@ __device__ __forceinline__ void sweep_cell_lds(const SweepRec<T, MI> &r, const B
     }
     lds_write_bands<T, BPL>((r.ok ? r.mine : trash) + lofs, out);
     if (r.ok) {
-        const uint32_t gc = (uint32_t)r.c * (uint32_t)B + (uint32_t)(b0 + lofs);   // within one direction's slice
+        const uint32_t gc = row + (uint32_t)lofs;
         if (vst) {
             gstore_bands<T, BPL>(gi, gc, out);
         } else {
@@ -685,7 +738,7 @@ struct LevelWindow {
 // keeps its registers while its loads are in flight (moving it would force
 // the wait).
 // --------------------------------------------------------------------------
-template <class T, int MI, int BPL, int MODE, bool ONE, bool SO2 = false>
+template <class T, int MI, int BPL, int MODE, bool ONE, bool SO2, bool PL>
 __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs,
                                                 const WorkItem *__restrict__ wk) {
     // ONE: one lane per cell (it sweeps all BPL bands of the block), so the
@@ -705,7 +758,9 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     const int nslots = ONE ? (int)blockDim.x : (int)blockDim.x / lpc;
     const int64_t N = v.N;
     const int B = v.B;
-    T NBTE_G *gi = static_cast<T NBTE_G *>(v.g) + (int64_t)i * N * B;
+    // direction i's distribution: cell-major rows of B values, or (plane
+    // layout) this band block's plane, one row of nb_here values per stream position
+    T NBTE_G *gi = static_cast<T NBTE_G *>(v.g) + (int64_t)i * N * B + (PL ? (int64_t)b0 * N : 0);
     const int64_t base = (int64_t)i * N;
     const int nlev = v.lvl_off[i + 1] - v.lvl_off[i] - 1;
     if (nlev <= 0) return;
@@ -730,7 +785,8 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     // this lane's bands: [lofs, lofs + BPL) of the block, nv of them real
     const int lofs = lane * BPL;
     const int nv = max(0, min(BPL, nb_here - lofs));
-    const bool vst = (B % BPL) == 0 && (b0 % BPL) == 0 && nv == BPL;   // whole-lane stores are aligned
+    // whole-lane stores are aligned (cell-major rows of B values, plane rows of nb_here)
+    const bool vst = (B % BPL) == 0 && (b0 % BPL) == 0 && (nb_here % BPL) == 0 && nv == BPL;
     BandConst<T, BPL> bc;
 #pragma unroll
     for (int jb = 0; jb < BPL; ++jb) {
@@ -822,7 +878,7 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     int lc = 0, kc = kf, kendc = kendf, g0c = g0f, gnc = gnf, gposc = 0;
     auto fetch = [&](Set &st) {
         const bool live = lf < nlev;
-        load_rec(st.r, S, kf + slot, live ? kendf : 0);
+        load_rec<T, MI, PL>(st.r, S, kf + slot, live ? kendf : 0);
         if constexpr (SO2) {
             // past-the-end records read position 0, like their stream loads
             const uint32_t at = (live && kf + slot < kendf) ? (uint32_t)(kf + slot) : 0u;
@@ -856,10 +912,14 @@ __global__ void __launch_bounds__(512) k_sweep(const DeviceView *__restrict__ vs
     // be the ones computed next, draining the prefetches once per turn.
     auto step = [&](Set &cur, Set &nxt, const Set &after) {
         fetch(nxt);
+        // the record's first element in gi: its stream position's row in the
+        // band block's plane, or its cell's row (band b0) in the cell-major layout
+        const uint32_t row = PL ? (uint32_t)(kc + slot) * (uint32_t)nb_here
+                                : (uint32_t)cur.r.c * (uint32_t)B + (uint32_t)b0;
         if constexpr (MODE == kModeLds)
-            sweep_cell_lds<T, MI, BPL>(cur.r, bc, gi, B, b0, lofs, nv, vst, lay.trash_off);
+            sweep_cell_lds<T, MI, BPL>(cur.r, bc, gi, row, lofs, nv, vst, lay.trash_off);
         else if (cur.r.ok)
-            sweep_cell<T, MI, BPL, SO2>(cur.r, v, bc, gi, base, b0, lane, nb_here, cur.cv);
+            sweep_cell<T, MI, BPL, SO2, PL>(cur.r, v, bc, gi, row, base, b0, lane, nb_here, cur.cv);
         kc += nslots;
         if (lc < nlev && kc >= kendc) {   // level done
             ++lc;
@@ -930,12 +990,12 @@ __global__ void __launch_bounds__(256) k_grad(const DeviceView *__restrict__ vs,
         const int64_t ic = t / B;
         const int64_t c = ic % N, i = ic / N;
         const double cw = v.Cw[lam];
-        const double gc = ld(g, t), thc = th[c];
+        const double gc = ld(g, g_elem(v, i, c, lam)), thc = th[c];
         double gx = 0.0, gy = 0.0, gz = 0.0;
         for (int f = 0; f < F; ++f) {
             const int32_t n = v.nbr[c * F + f];
             if (n < 0) continue;
-            const double d = (ld(g, (i * N + n) * B + lam) - gc) + cw * (th[n] - thc);
+            const double d = (ld(g, g_elem(v, i, n, lam)) - gc) + cw * (th[n] - thc);
             const double *w = v.lsq + (c * F + f) * 3;
             gx += w[0] * d;
             gy += w[1] * d;
@@ -1030,7 +1090,13 @@ __global__ void __launch_bounds__(1024) k_bicgstab(const DeviceView *__restrict_
     const int B = v.B, F = v.F, D = v.D;
     const double *sd = v.dirs + 3 * i;
     const double vel = v.vel[lam], itau = v.inv_tau[lam], cw = v.Cw[lam], src = v.src[lam];
-    T *x = static_cast<T *>(v.g) + (int64_t)i * N * B + lam;   // the system's values, stride B
+    // the system's values: cell-major (stride B), or band lam's plane of
+    // direction i (cell c at row pos_i(c))
+    const GPlane pl = gplane(v, lam);
+    T *xb = static_cast<T *>(v.g) + (int64_t)i * N * B + (v.planes ? pl.off : lam);
+    const int32_t *pi = v.pos + (int64_t)i * N;
+    const bool planes = v.planes != 0;
+    auto xat = [&](int64_t c) -> T & { return planes ? xb[(int64_t)pi[c] * pl.w] : xb[c * B]; };
     const T *gv = static_cast<const T *>(v.gval);
     const double *th = theta_cur(v);
     const int64_t sys = (int64_t)i * B + lam, DBN = (int64_t)D * B * N;
@@ -1076,7 +1142,7 @@ __global__ void __launch_bounds__(1024) k_bicgstab(const DeviceView *__restrict_
     }
     __syncthreads();
     for (int64_t c = threadIdx.x; c < N; c += nt) {
-        const double rc = sv[c] - apply(c, [&](int64_t n) { return ld(x, n * B); });
+        const double rc = sv[c] - apply(c, [&](int64_t n) { return static_cast<double>(xat(n)); });
         r[c] = rc;
         r0[c] = rc;
         p[c] = 0.0;
@@ -1116,7 +1182,7 @@ __global__ void __launch_bounds__(1024) k_bicgstab(const DeviceView *__restrict_
             acc += sc * sc;
         }
         if (!(block_sum(acc, red) > tol2)) {   // block_sum synchronises: sh is complete
-            for (int64_t c = threadIdx.x; c < N; c += nt) x[c * B] = static_cast<T>(ld(x, c * B) + alpha * ph[c]);
+            for (int64_t c = threadIdx.x; c < N; c += nt) xat(c) = static_cast<T>(static_cast<double>(xat(c)) + alpha * ph[c]);
             break;
         }
         double ts = 0.0, tt = 0.0;
@@ -1132,7 +1198,7 @@ __global__ void __launch_bounds__(1024) k_bicgstab(const DeviceView *__restrict_
         omega = ts / tt;
         acc = 0.0;
         for (int64_t c = threadIdx.x; c < N; c += nt) {
-            x[c * B] = static_cast<T>(ld(x, c * B) + alpha * ph[c] + omega * sh[c]);
+            xat(c) = static_cast<T>(static_cast<double>(xat(c)) + alpha * ph[c] + omega * sh[c]);
             const double rc = sv[c] - omega * t[c];
             r[c] = rc;
             acc += rc * rc;
@@ -1166,7 +1232,7 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
     const int64_t N = v.N;
     const int c = v.bf_owner[bf];
     const double th = (mode == 0 ? theta_cur(v) : theta_prev(v))[c];
-    const T *g = static_cast<const T *>(v.g);
+    const OwnerRows<T> og = owner_rows<T>(v, bf);   // the owner's distribution
     const T *gv = static_cast<const T *>(v.gval);
     const double *sd = v.sdotS + bf * D;
     // second order: increments of the outgoing face values.  The net flow
@@ -1201,7 +1267,7 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
                 // owner's value otherwise (s.S = 0 contributes exactly zero)
                 for (int i = jg; i < D; i += JG) {
                     const int32_t row = v.in_row[bf * D + i];
-                    const T *src = row >= 0 ? gv + (int64_t)row * B : g + ((int64_t)i * N + c) * B;
+                    const T *src = row >= 0 ? gv + (int64_t)row * B : og.p + (int64_t)i * og.stride;
                     double e = ld(src, lc) + cwt;
                     if (bj && row < 0) e += ld(bj, (int64_t)i * B + lc);
                     sum += (row >= 0 || sd[i] > 0.0) ? v.w[i] * sd[i] * e : 0.0;
@@ -1209,7 +1275,7 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
                 sumj = sum;
             } else if (v.order == 2) {
                 for (int i = jg; i < D; i += JG) {
-                    const double e = ld(g, ((int64_t)i * N + c) * B + lc) + cwt;
+                    const double e = ld(og.p, (int64_t)i * og.stride + lc) + cwt;
                     const double wsd = sd[i] > 0.0 ? v.w[i] * sd[i] : 0.0;
                     sum += wsd * (e + (bs ? ld(bs, (int64_t)i * B + lc) : 0.0));
                     sumj += wsd * (e + (bj ? ld(bj, (int64_t)i * B + lc) : 0.0));
@@ -1219,7 +1285,7 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
                 // direction (independent loads) and weighted by s.S > 0
 #pragma unroll 8
                 for (int i = jg; i < D; i += JG) {
-                    const double e = ld(g, ((int64_t)i * N + c) * B + lc) + cwt;
+                    const double e = ld(og.p, (int64_t)i * og.stride + lc) + cwt;
                     sum += sd[i] > 0.0 ? v.w[i] * sd[i] * e : 0.0;
                 }
                 sumj = sum;
@@ -1255,8 +1321,9 @@ __global__ void __launch_bounds__(256) k_flux(const DeviceView *__restrict__ vs,
 }
 
 // --------------------------------------------------------------------------
-// band x direction reductions (Methods, Eqs. (5), (7); T = energy temperature)
-// mom_lpc lanes per cell, FP64 accumulation, shuffle reduction over the lanes.
+// band x direction reductions, cell-major layout (Methods, Eqs. (5), (7);
+// T = energy temperature): mom_lpc lanes per cell, FP64 accumulation, shuffle
+// reduction over the lanes.
 // Synthetic schemes also get the collision part V beta (theta_seq - theta) of
 // the correction's right-hand side; the reflective walls' net flows are added
 // by k_wall_rhs once the flux is known.
@@ -1318,21 +1385,158 @@ __device__ __forceinline__ void moments_block(const DeviceView &v, int64_t blk) 
     }
 }
 
-// The work after a sweep that reads its distribution, in one launch: items
-// (solve, 0, b, nblk) are boundary-face flux (k_flux's mode 0 face groups),
-// items (solve, 1, b, -) moment blocks.  The two read the same distribution
-// and depend on nothing of each other, so the latency-bound face waves run
-// beside the bandwidth-bound moment blocks.
+// --------------------------------------------------------------------------
+// band x direction reductions, plane layout (Methods, Eqs. (5), (7)), in two
+// stages.  Stage 1 (in k_post): one thread per stream position t of a
+// direction i reads the cell's row in each band-block plane (consecutive
+// threads, consecutive rows) and forms the band sums
+//   A = sum_l g_l / tau_l,   W = sum_l g_l,   U = sum_l v_l g_l
+// with FP64 accumulation in band order, kept in FP64 at (i, c).
+// Stage 2 (k_reduce): four lanes per cell sum w_i A, w_i W and w_i s_i U over
+// the directions (FP64, lanes combined in a fixed order):
+//   theta_seq = theta + sum_i w_i A_i / beta,   T = theta + sum_i w_i W_i / C,
+//   q = sum_i w_i s_i U_i + theta q_bias,
+// and the collision part V beta (theta_seq - theta) of the correction's
+// right-hand side (the reflective faces' net flows follow in k_wall_rhs).
+// --------------------------------------------------------------------------
+// W > 0: every plane W bands wide with 16-byte aligned rows (vector loads);
+// W = 0: any plane widths (one load per band).  A cell that owns a boundary
+// face also gets its values copied into its boundary row.
+// The band constants (1/tau, v, C/W) are read through the constant address
+// space: the band index is uniform, so they become scalar loads that do not
+// wait behind the distribution loads (vector loads would be waited on band by
+// band).  Nothing writes them during the launch.
+#define NBTE_C __attribute__((address_space(4)))
+template <class T, int W>
+__device__ __forceinline__ void band_sums(const DeviceView &v, int64_t i, int64_t t0) {
+    // the descriptor's fields in registers: the stores below could otherwise
+    // alias the descriptor in memory and force a reload of every pointer
+    const int64_t N = v.N;
+    const int B = v.B, bpb = v.bpb, D = v.D;
+    const bool so2 = v.order == 2;
+    const double NBTE_C *itau = (const double NBTE_C *)v.inv_tau;
+    const double NBTE_C *vel = (const double NBTE_C *)v.vel;
+    const double NBTE_C *cwv = (const double NBTE_C *)v.Cw;
+    const T NBTE_G *g = static_cast<const T NBTE_G *>(v.g) + i * N * B;
+    const int64_t t = t0 + threadIdx.x;
+    if (t >= N && !so2) return;
+    const bool live = t < N;
+    const int c = live ? v.p_cell[i * N + t] : 0;
+    double a = 0.0, w = 0.0, u = 0.0;
+    double gmax = 0.0;   // second order: largest |g| W / C, the divergence watch of the deferred correction
+    auto add = [&](double x, int l) {
+        a += x * itau[l];
+        w += x;
+        u += x * vel[l];
+        if (so2) gmax = fmax(gmax, fabs(x) / cwv[l]);
+    };
+    if (live) {
+        const int bo = v.bown[c];   // the cell's boundary row, if it owns a boundary face
+        T NBTE_G *br = bo >= 0 ? static_cast<T NBTE_G *>(v.brow) + ((int64_t)bo * D + i) * B : nullptr;
+        // rows (W > 0) or bands (W = 0) requested before the first is used: 128 bytes per thread
+        constexpr int G = W > 0 ? (128 / (W * (int)sizeof(T)) > 0 ? 128 / (W * (int)sizeof(T)) : 1) : 8;
+        if constexpr (W > 0) {
+            using V = typename VecOf<T, W>::type;
+            for (int k0 = 0; k0 < B; k0 += G * W) {
+                V x[G];
+#pragma unroll
+                for (int q = 0; q < G; ++q) {   // branch-free: rows past the end reread the last row
+                    const int kq = min(k0 + q * W, B - W);
+                    x[q] = __builtin_nontemporal_load(reinterpret_cast<const V NBTE_G *>(g + (int64_t)kq * N + t * W));
+                }
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (k0 + q * W >= B) break;
+                    if (br) *reinterpret_cast<V NBTE_G *>(br + k0 + q * W) = x[q];   // rows of B values: aligned
+#pragma unroll
+                    for (int j = 0; j < W; ++j) add(static_cast<double>(x[q][j]), k0 + q * W + j);
+                }
+            }
+        } else {
+            // band l of plane k = l / bpb
+            for (int l0 = 0; l0 < B; l0 += G) {
+                T x[G];
+#pragma unroll
+                for (int q = 0; q < G; ++q) {   // branch-free: bands past the end reread the last band
+                    const int l = min(l0 + q, B - 1);
+                    const int kb = (l / bpb) * bpb;
+                    x[q] = g[(int64_t)kb * N + t * min(bpb, B - kb) + (l - kb)];
+                }
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if (l0 + q >= B) break;
+                    if (br) br[l0 + q] = x[q];
+                    add(static_cast<double>(x[q]), l0 + q);
+                }
+            }
+        }
+        Mom3 m;
+        m.a = a;
+        m.w = w;
+        m.u = u;
+        static_cast<Mom3 NBTE_G *>(v.mom)[i * N + c] = m;
+    }
+    if (so2) {
+        if (!(gmax <= 1e300)) gmax = INFINITY;
+        for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(&v.state->maxbuf[2], dbits(gmax));
+    }
+}
+
+// Reduction stage 2 (item kind 1, grid-stride over the cells), beside the
+// boundary-face flux (kind 0: k_flux's mode 0 face groups, which read the
+// boundary rows stage 1 wrote): both only read what k_post wrote and need
+// nothing of each other.
 template <class T>
-__global__ void __launch_bounds__(256) k_post(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+__global__ void __launch_bounds__(256) k_reduce(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
     const WorkItem it = wk[blockIdx.x];
     const DeviceView &v = vs[it.solve];
     if (v.state->done) return;
     if (it.a == 0) {
         const int wv = threadIdx.x >> 6;
         for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4) flux_face<T>(v, bf, 0);
-    } else {
-        moments_block<T>(v, it.b);
+        return;
+    }
+    // kReduceLanes lanes per cell, lane j taking directions j, j + kReduceLanes,
+    // ...; the lanes' sums are combined by shuffles in a fixed order
+    const int64_t N = v.N;
+    const int D = v.D;
+    const Mom3 *m = static_cast<const Mom3 *>(v.mom);
+    const double *th = theta_cur(v);
+    const int lane = threadIdx.x % kReduceLanes;
+    const int64_t nthr = (int64_t)it.c * blockDim.x;
+    const int64_t span = (N * kReduceLanes + nthr - 1) / nthr * nthr;   // whole waves run every pass
+    for (int64_t k = (int64_t)it.b * blockDim.x + threadIdx.x; k < span; k += nthr) {
+        const int64_t c = k / kReduceLanes;
+        double a_tau = 0, a_w = 0, qx = 0, qy = 0, qz = 0;
+        if (c < N) {
+#pragma unroll 4
+            for (int i = lane; i < D; i += kReduceLanes) {
+                const Mom3 x = m[(int64_t)i * N + c];
+                const double wi = v.w[i];
+                a_tau += wi * x.a;
+                a_w += wi * x.w;
+                const double wu = wi * x.u;
+                qx += wu * v.dirs[3 * i];
+                qy += wu * v.dirs[3 * i + 1];
+                qz += wu * v.dirs[3 * i + 2];
+            }
+        }
+        for (int off = 1; off < kReduceLanes; off <<= 1) {
+            a_tau += __shfl_xor(a_tau, off);
+            a_w += __shfl_xor(a_w, off);
+            qx += __shfl_xor(qx, off);
+            qy += __shfl_xor(qy, off);
+            qz += __shfl_xor(qz, off);
+        }
+        if (c >= N || lane != 0) continue;
+        const double t = th[c];
+        v.theta_seq[c] = t + a_tau / v.beta;
+        v.thetaE[c] = t + a_w / v.C_tot;
+        v.q[3 * c] = qx + t * v.qbias[0];
+        v.q[3 * c + 1] = qy + t * v.qbias[1];
+        v.q[3 * c + 2] = qz + t * v.qbias[2];
+        if (v.scheme != NBTE_SCHEME_SEQUENTIAL) v.rhs[c] = v.V[c] * a_tau;
     }
 }
 
@@ -1356,6 +1560,33 @@ __global__ void __launch_bounds__(256) k_wall_rhs(const DeviceView *__restrict__
     }
 }
 
+// The work after a sweep that reads its distribution, in one launch.
+// Cell-major layout: items (solve, 0, b, nblk) boundary-face flux (k_flux's
+// mode 0 face groups) and (solve, 1, b, -) moment blocks; the two read the
+// same distribution and need nothing of each other, so the latency-bound face
+// waves run beside the bandwidth-bound moment blocks.  Plane layout: items
+// (solve, 2, b, i) reduction stage 1 over positions [256 b, + 256) of
+// direction i (the face flux follows in k_reduce, from the boundary rows
+// this stage writes).  solve < 0 pads.
+template <class T>
+__global__ void __launch_bounds__(256) k_post(const DeviceView *__restrict__ vs, const WorkItem *__restrict__ wk) {
+    const WorkItem it = wk[blockIdx.x];
+    if (it.solve < 0) return;
+    const DeviceView &v = vs[it.solve];
+    if (v.state->done) return;
+    if (it.a == 0) {
+        const int wv = threadIdx.x >> 6;
+        for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4) flux_face<T>(v, bf, 0);
+    } else if (it.a == 1) {
+        moments_block<T>(v, it.b);
+    } else {
+        const int64_t i = it.c, t0 = (int64_t)it.b * blockDim.x;
+        const bool full = v.B % v.bpb == 0;
+        if (full && v.bpb * (int)sizeof(T) == 16) band_sums<T, 16 / sizeof(T)>(v, i, t0);
+        else if (full && v.bpb * (int)sizeof(T) == 32) band_sums<T, 32 / sizeof(T)>(v, i, t0);
+        else band_sums<T, 0>(v, i, t0);
+    }
+}
 
 // theta_new = base + delta: sequential base = theta_seq (Eq. (5)); synthetic
 // base = theta_seq + correction (Eq. (12)); the literal variant adds the
@@ -1643,9 +1874,18 @@ __global__ void k_set_controls(SolveState *s, int stop, double tol, int max_iter
 }
 
 // FP32 distribution -> FP64 (switch of a solve to FP64 sweeps)
-__global__ void k_widen(int64_t n, const float *in, double *out) {
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-        out[k] = static_cast<double>(in[k]);
+// element of band l at stream position t in a direction's planes of bpb bands
+__device__ __forceinline__ int64_t plane_elem(int64_t N, int B, int bpb, int64_t t, int l) {
+    const int k = l / bpb;
+    return (int64_t)k * N * bpb + t * min(bpb, B - k * bpb) + (l - k * bpb);
+}
+__global__ void k_widen(int64_t D, int64_t N, int B, const float *in, int bpb_in, double *out, int bpb_out) {
+    const int64_t n = D * N * B;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(k % B);
+        const int64_t it = k / B, t = it % N, base = (it / N) * N * B;
+        out[base + plane_elem(N, B, bpb_out, t, l)] = static_cast<double>(in[base + plane_elem(N, B, bpb_in, t, l)]);
+    }
 }
 
 __global__ void k_collect_states(const DeviceView *__restrict__ vs, int n, SolveState *out) {
@@ -1671,7 +1911,7 @@ __global__ void k_distribution(const DeviceView *__restrict__ vp, int band, int 
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= v.N) return;
     const T *g = static_cast<const T *>(v.g);
-    out[c] = ld(g, ((int64_t)dir * v.N + c) * v.B + band) + v.Cw[band] * theta_prev(v)[c];
+    out[c] = ld(g, g_elem(v, dir, c, band)) + v.Cw[band] * theta_prev(v)[c];
 }
 
 // --------------------------------------------------------------------------
@@ -1982,53 +2222,59 @@ __global__ void __launch_bounds__(256) k_cg1_iter(const DeviceView *__restrict__
     }
 }
 
-template <class T, int MI, int MODE>
+template <class T, int MI, int MODE, bool PL>
 void dispatch_sweep_bpl(const DeviceView *vs, const WorkItem *wk, int n, int bpl, bool one, int block, size_t lds,
                         hipStream_t st) {
     dim3 grid(n);
     if (one) {
         switch (bpl) {
-            case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, MODE, true>), grid, dim3(block), lds, st, vs, wk); break;
-            case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, MODE, true>), grid, dim3(block), lds, st, vs, wk); break;
-            case 4: hipLaunchKernelGGL((k_sweep<T, MI, 4, MODE, true>), grid, dim3(block), lds, st, vs, wk); break;
-            default: hipLaunchKernelGGL((k_sweep<T, MI, 8, MODE, true>), grid, dim3(block), lds, st, vs, wk); break;
+            case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, MODE, true, false, PL>), grid, dim3(block), lds, st, vs, wk); break;
+            case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, MODE, true, false, PL>), grid, dim3(block), lds, st, vs, wk); break;
+            case 4: hipLaunchKernelGGL((k_sweep<T, MI, 4, MODE, true, false, PL>), grid, dim3(block), lds, st, vs, wk); break;
+            default: hipLaunchKernelGGL((k_sweep<T, MI, 8, MODE, true, false, PL>), grid, dim3(block), lds, st, vs, wk); break;
         }
         return;
     }
     switch (bpl) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, MODE, false>), grid, dim3(block), lds, st, vs, wk); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, MODE, false>), grid, dim3(block), lds, st, vs, wk); break;
-        default: hipLaunchKernelGGL((k_sweep<T, MI, 4, MODE, false>), grid, dim3(block), lds, st, vs, wk); break;
+        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, MODE, false, false, PL>), grid, dim3(block), lds, st, vs, wk); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, MODE, false, false, PL>), grid, dim3(block), lds, st, vs, wk); break;
+        default: hipLaunchKernelGGL((k_sweep<T, MI, 4, MODE, false, false, PL>), grid, dim3(block), lds, st, vs, wk); break;
     }
 }
 
-template <class T, int MODE>
+template <class T, int MODE, bool PL>
 void dispatch_sweep_mi(const DeviceView *vs, const WorkItem *wk, int n, int maxin, int bpl, bool one, int block,
                        size_t lds, hipStream_t st) {
-    if (maxin <= 2) dispatch_sweep_bpl<T, 2, MODE>(vs, wk, n, bpl, one, block, lds, st);
-    else if (maxin == 3) dispatch_sweep_bpl<T, 3, MODE>(vs, wk, n, bpl, one, block, lds, st);
-    else dispatch_sweep_bpl<T, 5, MODE>(vs, wk, n, bpl, one, block, lds, st);
+    if (maxin <= 2) dispatch_sweep_bpl<T, 2, MODE, PL>(vs, wk, n, bpl, one, block, lds, st);
+    else if (maxin == 3) dispatch_sweep_bpl<T, 3, MODE, PL>(vs, wk, n, bpl, one, block, lds, st);
+    else dispatch_sweep_bpl<T, 5, MODE, PL>(vs, wk, n, bpl, one, block, lds, st);
 }
 
 // second-order kernels: the general mode (LDS, ghosts and spilled values
 // from HBM) with several lanes per cell, up to four bands per lane
-template <class T, int MI>
+template <class T, int MI, bool PL>
 void dispatch_sweep_so2(const DeviceView *vs, const WorkItem *wk, int n, int bpl, int block, size_t lds,
                         hipStream_t st) {
     dim3 grid(n);
     switch (bpl) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, kModeSpill, false, true>), grid, dim3(block), lds, st, vs, wk); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, kModeSpill, false, true>), grid, dim3(block), lds, st, vs, wk); break;
-        default: hipLaunchKernelGGL((k_sweep<T, MI, 4, kModeSpill, false, true>), grid, dim3(block), lds, st, vs, wk); break;
+        case 1: hipLaunchKernelGGL((k_sweep<T, MI, 1, kModeSpill, false, true, PL>), grid, dim3(block), lds, st, vs, wk); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, MI, 2, kModeSpill, false, true, PL>), grid, dim3(block), lds, st, vs, wk); break;
+        default: hipLaunchKernelGGL((k_sweep<T, MI, 4, kModeSpill, false, true, PL>), grid, dim3(block), lds, st, vs, wk); break;
     }
 }
 
-template <class T>
+template <class T, bool PL>
 void dispatch_sweep(const DeviceView *vs, const WorkItem *wk, int n, int maxin, int bpl, bool one, int mode,
-                    int block, size_t lds, hipStream_t st) {
-    if (mode == kModeLds) dispatch_sweep_mi<T, kModeLds>(vs, wk, n, maxin, bpl, one, block, lds, st);
-    else if (mode == kModeHbmGhost) dispatch_sweep_mi<T, kModeHbmGhost>(vs, wk, n, maxin, bpl, one, block, lds, st);
-    else dispatch_sweep_mi<T, kModeSpill>(vs, wk, n, maxin, bpl, one, block, lds, st);
+                    int block, size_t lds, hipStream_t st, bool order2) {
+    if (order2) {
+        if (maxin <= 2) dispatch_sweep_so2<T, 2, PL>(vs, wk, n, bpl, block, lds, st);
+        else if (maxin == 3) dispatch_sweep_so2<T, 3, PL>(vs, wk, n, bpl, block, lds, st);
+        else dispatch_sweep_so2<T, 5, PL>(vs, wk, n, bpl, block, lds, st);
+        return;
+    }
+    if (mode == kModeLds) dispatch_sweep_mi<T, kModeLds, PL>(vs, wk, n, maxin, bpl, one, block, lds, st);
+    else if (mode == kModeHbmGhost) dispatch_sweep_mi<T, kModeHbmGhost, PL>(vs, wk, n, maxin, bpl, one, block, lds, st);
+    else dispatch_sweep_mi<T, kModeSpill, PL>(vs, wk, n, maxin, bpl, one, block, lds, st);
 }
 
 }  // namespace
@@ -2076,6 +2322,12 @@ void launch_post(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hip
     else hipLaunchKernelGGL(k_post<double>, dim3(n), dim3(256), 0, st, vs, wk);
 }
 
+void launch_reduce(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, hipStream_t st) {
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_reduce<float>, dim3(n), dim3(256), 0, st, vs, wk);
+    else hipLaunchKernelGGL(k_reduce<double>, dim3(n), dim3(256), 0, st, vs, wk);
+}
+
 void launch_wall_rhs(const DeviceView *vs, const WorkItem *wk, int n, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_wall_rhs, dim3(n), dim3(256), 0, st, vs, wk);
@@ -2115,22 +2367,16 @@ size_t sweep_lds_bytes(int max_levels, int gring, int ls, int slots, int es) {
 }
 
 void launch_sweep(const DeviceView *vs, const WorkItem *wk, int n, bool fp32, int maxin, int bpl, bool one, int mode,
-                  int block, size_t lds_bytes, hipStream_t st, bool order2) {
+                  int block, size_t lds_bytes, hipStream_t st, bool order2, bool planes) {
     if (n <= 0) return;
     if (bpl != 1 && bpl != 2 && bpl != 4 && bpl != 8) bpl = 1;
-    if (order2) {
-        auto go = [&](auto tag) {
-            using T = decltype(tag);
-            if (maxin <= 2) dispatch_sweep_so2<T, 2>(vs, wk, n, bpl, block, lds_bytes, st);
-            else if (maxin == 3) dispatch_sweep_so2<T, 3>(vs, wk, n, bpl, block, lds_bytes, st);
-            else dispatch_sweep_so2<T, 5>(vs, wk, n, bpl, block, lds_bytes, st);
-        };
-        if (fp32) go(float{});
-        else go(double{});
-        return;
+    if (fp32) {
+        if (planes) dispatch_sweep<float, true>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st, order2);
+        else dispatch_sweep<float, false>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st, order2);
+    } else {
+        if (planes) dispatch_sweep<double, true>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st, order2);
+        else dispatch_sweep<double, false>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st, order2);
     }
-    if (fp32) dispatch_sweep<float>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st);
-    else dispatch_sweep<double>(vs, wk, n, maxin, bpl, one, mode, block, lds_bytes, st);
 }
 
 void launch_pcg_block(const DeviceView *vs, const WorkItem *wk, int n, int mode, hipStream_t st) {
@@ -2154,10 +2400,22 @@ void launch_set_controls(SolveState *s, int stop, double tol, int max_iter, int 
     hipLaunchKernelGGL(k_set_controls, dim3(1), dim3(64), 0, st, s, stop, tol, max_iter, patience);
 }
 
-void launch_widen(int64_t n, const float *in, double *out, hipStream_t st) {
+__global__ void k_widen_flat(int64_t n, const float *in, double *out) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = static_cast<double>(in[k]);
+}
+
+void launch_widen_flat(int64_t n, const float *in, double *out, hipStream_t st) {
     if (n <= 0) return;
     const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_widen, dim3(grid), dim3(256), 0, st, n, in, out);
+    hipLaunchKernelGGL(k_widen_flat, dim3(grid), dim3(256), 0, st, n, in, out);
+}
+
+void launch_widen(int64_t D, int64_t N, int B, const float *in, int bpb_in, double *out, int bpb_out, hipStream_t st) {
+    const int64_t n = D * N * B;
+    if (n <= 0) return;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_widen, dim3(grid), dim3(256), 0, st, D, N, B, in, bpb_in, out, bpb_out);
 }
 
 void launch_collect_states(const DeviceView *vs, int n, SolveState *out, hipStream_t st) {

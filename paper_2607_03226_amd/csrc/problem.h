@@ -75,6 +75,7 @@ class Runner {
         int mode = 0;   // sweep kernel mode (launch_sweep)
         bool one = false;   // one lane per cell
         bool so2 = false;   // second-order sweep kernels
+        bool planes = false;   // plane layout of the distribution (sweep kernels)
         size_t lds = 0;
     };
     void build();
@@ -144,6 +145,16 @@ struct nbte_problem {
     nbte::DevBuf d_Ecol, d_Eval;     // ELL copy (A D^-1) for the multi-workgroup CG
     nbte::DevBuf d_Jin, d_bsum;      // boundary faces: incoming flow, per-band outgoing sums
     nbte::DevBuf d_g, d_gval, d_Jw, d_Q;
+    // the distribution's row index: stream position of each cell per direction
+    // (D*N); each cell's index among the boundary-owner cells (N) and their
+    // boundary rows (storage type); per (direction, cell) band sums of the
+    // reductions' first stage (storage type)
+    nbte::DevBuf d_pos, d_bown, d_bf_brow, d_brow, d_mom;
+    int64_t boundary_owners() const;
+    // distribution layout: band-block planes in stream order (large problems,
+    // where the sweep's stores dominate) or cell-major (tuning.layout)
+    bool planes() const;
+    int mom_lpc() const;
     nbte::DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta;
     nbte::DevBuf d_pcg_vec, d_pcg_part, d_pcg_scal;
     nbte::DevBuf d_view, d_state, d_self_work;
@@ -173,7 +184,7 @@ struct nbte_problem {
     } shape;
     int slots_for_cap = -2;   // slot budget the current slot table was built for
     int prog_B = -1, prog_gcap = -1, prog_gring = -1, prog_ls = -1, prog_es = -1;
-    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0.0};
+    nbte_tuning tuning{0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0.0, 0};
 
     // iteration state
     bool prepared = false;
@@ -208,7 +219,6 @@ struct nbte_problem {
     double cg_rtol() const { return tuning.cg_rtol > 0 ? tuning.cg_rtol : 1e-3; }
     bool fp32() const { return precision == NBTE_PREC_MIXED; }
     bool synthetic() const { return scheme != NBTE_SCHEME_SEQUENTIAL; }
-    int mom_lpc() const;
 
     void build_host();
     void upload_device();

@@ -17,7 +17,7 @@ namespace nbte {
 
 namespace {
 
-enum Kind { K_MARK, K_STAGE, K_SWEEP, K_POST, K_WALL, K_PCG_BLOCK, K_PCG_MULTI, K_UPDATE, K_FINISH, K_ACC_COLS,
+enum Kind { K_MARK, K_STAGE, K_SWEEP, K_POST, K_REDUCE, K_WALL, K_PCG_BLOCK, K_PCG_MULTI, K_UPDATE, K_FINISH, K_ACC_COLS,
             K_ACC_SOLVE, K_ACC_MIX, K_GRAD, K_RECON, K_BICG };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -121,8 +121,8 @@ void Runner::build() {
     mark(PH_SWEEP);
     {
         // group by kernel variant; inside a group, XCD-aware longest-first order
-        // fp32, maxin class, bpl, mode, block, one lane per cell, second order
-        using Key = std::tuple<int, int, int, int, int, int, int>;
+        // fp32, maxin class, bpl, mode, block, one lane per cell, second order, plane layout
+        using Key = std::tuple<int, int, int, int, int, int, int, int>;
         std::map<Key, std::vector<int>> groups;
         for (int s = 0; s < M; ++s) {
             const nbte_problem &p = *members_[s];
@@ -132,7 +132,7 @@ void Runner::build() {
             const bool so2 = p.order == 2;   // second order: the general mode, several lanes per cell
             const int mode = (spill || so2) ? 2 : (p.prog.max_ghosts > p.shape.gcap ? 1 : 0);
             groups[Key(p.fp32() ? 1 : 0, mi, p.shape.bpl, mode, p.shape.block, (p.hv.lpc == 1 && !so2) ? 1 : 0,
-                       so2 ? 1 : 0)]
+                       so2 ? 1 : 0, p.hv.planes ? 1 : 0)]
                 .push_back(s);
         }
         for (auto &kv : groups) {
@@ -180,6 +180,7 @@ void Runner::build() {
             L.mode = std::get<3>(kv.first);
             L.one = std::get<5>(kv.first) != 0;
             L.so2 = std::get<6>(kv.first) != 0;
+            L.planes = std::get<7>(kv.first) != 0;
             L.block = std::get<4>(kv.first);
             L.lds = lds;
             L.off = (int)work.size();
@@ -230,19 +231,66 @@ void Runner::build() {
         close(R);
     }
     for (bool f : {true, false}) {
-        // boundary flux (every scheme: the outgoing sums feed the next
-        // diffuse inflow; the net flows are used by the synthetic correction
-        // only) first, the moment blocks after it, in one launch
+        // cell-major members: boundary flux (every scheme: the outgoing sums
+        // feed the next diffuse inflow; the net flows are used by the
+        // synthetic correction only) first, the moment blocks after it.
+        // Plane members: reduction stage 1, item (s, 2, chunk, direction)
+        // covering positions [256 chunk, + 256) of a direction.  Workgroup k
+        // of a launch runs on XCD k mod 8: the stage-1 items start at a
+        // multiple of 8 and each XCD takes whole directions one after the
+        // other (chunks in order), so the scattered (direction, cell) sums of
+        // the one or two directions it works on at a time stay in its L2.
         Launch L;
         L.kind = K_POST;
         L.fp32 = f;
         L.off = (int)work.size();
         each(f, [&](int s, nbte_problem &p) {
+            if (p.hv.planes) return;
             const int64_t nb = cdiv(p.mesh->NBF, 4);   // a wave per face
             for (int64_t b = 0; b < nb; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb});
         });
         each(f, [&](int s, nbte_problem &p) {
+            if (p.hv.planes) return;
             const int64_t nb = cdiv(p.mesh->N * p.hv.mom_lpc, 256);
+            for (int64_t b = 0; b < nb; ++b) work.push_back({s, 1, (int32_t)b, (int32_t)nb});
+        });
+        std::vector<WorkItem> q[8];
+        int64_t load[8] = {0};
+        each(f, [&](int s, nbte_problem &p) {
+            if (!p.hv.planes) return;
+            const int64_t nc = cdiv(p.mesh->N, 256);
+            for (int i = 0; i < p.quad.D; ++i) {
+                int x = 0;
+                for (int y = 1; y < 8; ++y)
+                    if (load[y] < load[x]) x = y;
+                for (int64_t b = 0; b < nc; ++b) q[x].push_back({s, 2, (int32_t)b, i});
+                load[x] += nc;
+            }
+        });
+        size_t len = 0;
+        for (auto &qq : q) len = std::max(len, qq.size());
+        if (len > 0)
+            while ((work.size() - L.off) % 8) work.push_back({-1, 0, 0, 0});
+        for (size_t k = 0; k < len; ++k)
+            for (int x = 0; x < 8; ++x) work.push_back(k < q[x].size() ? q[x][k] : WorkItem{-1, 0, 0, 0});
+        while ((int)work.size() > L.off && work.back().solve < 0) work.pop_back();
+        close(L);
+    }
+    for (bool f : {true, false}) {
+        // plane members: boundary flux from the boundary rows first, then
+        // stage 2 of the reductions
+        Launch L;
+        L.kind = K_REDUCE;
+        L.fp32 = f;
+        L.off = (int)work.size();
+        each(f, [&](int s, nbte_problem &p) {
+            if (!p.hv.planes) return;
+            const int64_t nb = cdiv(p.mesh->NBF, 4);   // a wave per face
+            for (int64_t b = 0; b < nb; ++b) work.push_back({s, 0, (int32_t)b, (int32_t)nb});
+        });
+        each(f, [&](int s, nbte_problem &p) {
+            if (!p.hv.planes) return;
+            const int64_t nb = std::min<int64_t>(cdiv(p.mesh->N * kReduceLanes, 256), 8192);
             for (int64_t b = 0; b < nb; ++b) work.push_back({s, 1, (int32_t)b, (int32_t)nb});
         });
         close(L);
@@ -369,9 +417,10 @@ void Runner::enqueue_iteration(int slot) {
             case K_STAGE: launch_stage(vs, wk + L.off, L.n, L.fp32, stream_); break;
             case K_SWEEP:
                 launch_sweep(vs, wk + L.off, L.n, L.fp32, L.maxin, L.bpl, L.one, L.mode, L.block, L.lds, stream_,
-                             L.so2);
+                             L.so2, L.planes);
                 break;
             case K_POST: launch_post(vs, wk + L.off, L.n, L.fp32, stream_); break;
+            case K_REDUCE: launch_reduce(vs, wk + L.off, L.n, L.fp32, stream_); break;
             case K_WALL: launch_wall_rhs(vs, wk + L.off, L.n, stream_); break;
             case K_PCG_BLOCK: launch_pcg_block(vs, wk + L.off, L.n, 0, stream_); break;
             case K_PCG_MULTI:

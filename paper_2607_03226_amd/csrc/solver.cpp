@@ -89,13 +89,34 @@ void *nbte_problem::t_row(int r) const {
     return static_cast<char *>(d_tstream.ptr) + (size_t)r * stream_DN() * (fp32() ? 4 : 8);
 }
 
-// lanes per cell of the reductions: a power of two >= B, at most 64 (one
-// band per lane; measured: splitting the directions of a cell over more
-// lanes breaks the coalesced band rows and is slower)
+// lanes per cell of the cell-major reductions: a power of two >= B, at most
+// 64 (one band per lane; measured: splitting the directions of a cell over
+// more lanes breaks the coalesced band rows and is slower, and so did 16-byte
+// loads of four bands per lane)
 int nbte_problem::mom_lpc() const {
     int lpc = 1;
     while (lpc < bands.B && lpc < 64) lpc <<= 1;
     return lpc;
+}
+
+// The plane layout pays where the distribution is far larger than the
+// caches: its sweep stores whole lines, but the reductions and boundary
+// kernels then permute (measured: config 3, 444M values, 5 % faster per
+// iteration; config 2, 28M values, cache resident, 30 % slower).  Chosen by
+// the element count, so the layout does not change with the precision.
+bool nbte_problem::planes() const {
+    if (tuning.layout != 0) return tuning.layout == 2;
+    return (int64_t)mesh->N * quad.D * bands.B >= kPlanesMinValues;
+}
+
+// cells that own at least one boundary face (rows of the boundary copy)
+int64_t nbte_problem::boundary_owners() const {
+    const Mesh &m = *mesh;
+    std::vector<char> own(m.N, 0);
+    for (int64_t bf = 0; bf < m.NBF; ++bf) own[m.bf_owner[bf]] = 1;
+    int64_t n = 0;
+    for (char x : own) n += x;
+    return n;
 }
 
 // Resolve the tuning into one sweep launch shape.  Defaults aim at two
@@ -252,6 +273,17 @@ void nbte_problem::upload_device() {
         upload(d_nbr, m.nbr, stream);
         upload(d_V, m.V, stream);
         upload(d_bf_owner, m.bf_owner, stream);
+        // the boundary-owner cells in ascending order (their boundary rows)
+        std::vector<int32_t> bown(m.N, -1);
+        for (int64_t bf = 0; bf < m.NBF; ++bf) bown[m.bf_owner[bf]] = 0;
+        int32_t k = 0;
+        for (int64_t c = 0; c < m.N; ++c)
+            if (bown[c] == 0) bown[c] = k++;
+        std::vector<int32_t> bf_brow(std::max<int64_t>(m.NBF, 1), 0);
+        for (int64_t bf = 0; bf < m.NBF; ++bf) bf_brow[bf] = bown[m.bf_owner[bf]];
+        upload(d_bown, bown, stream);
+        upload(d_bf_brow, bf_brow, stream);
+        NBTE_HIP(hipStreamSynchronize(stream));   // the host copy goes out of scope
         geom_ok = true;
     }
     if (!sched_up) {
@@ -268,6 +300,13 @@ void nbte_problem::upload_device() {
         upload(d_gptr, prog.gptr, stream);
         upload(d_inrow, prog.in_row, stream);
         upload(d_lag, prog.lag, stream);
+        {
+            // stream position of every cell in each direction (the distribution's row index)
+            std::vector<int32_t> pos((size_t)DN);
+            for (int64_t at = 0; at < DN; ++at) pos[(size_t)((at / m.N) * m.N + sched.perm[at])] = (int32_t)(at % m.N);
+            upload(d_pos, pos, stream);
+            NBTE_HIP(hipStreamSynchronize(stream));   // the host copy goes out of scope
+        }
         NBTE_HIP(hipStreamSynchronize(stream));   // the program may be rebuilt (host copies replaced) after this
         sched_up = true;
     }
@@ -300,6 +339,7 @@ void nbte_problem::upload_device() {
         upload(d_wslot, wslot, stream);
         plan_up = true;
     }
+
     if (!tables_ok) {
         const int B = bands.B, D = quad.D;
         std::vector<double> Cw(B), src(B), itau(B);
@@ -380,8 +420,10 @@ int64_t nbte_problem::state_bytes(int prec, int ord) const {
         const int64_t NR = accel_rows(), NS = N + NR;
         acc = (2 * NR + 2 * NS) * 8 + 2 * (int64_t)accel_m() * NS * es + 1024 * 2 * kAccelMaxDepth * 8 + 1024;
     }
-    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + NBF * (B + 3) * 8 + N * 8 * 10 +
-           1024 + acc + so2;
+    // plane layout: the reductions' band sums and the boundary rows
+    const int64_t pl = planes() ? D * N * 24 + std::max<int64_t>(boundary_owners(), 1) * D * B * es : 0;
+    return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + pl + NBF * (B + 3) * 8 +
+           N * 8 * 10 + 1024 + acc + so2;
 }
 
 void nbte_problem::allocate_state(int prec) {
@@ -418,6 +460,13 @@ void nbte_problem::allocate_state(int prec) {
     d_q.alloc(3 * N * 8);
     d_rhs.alloc(N * 8);
     d_delta.alloc(N * 8);
+    if (planes()) {
+        d_mom.alloc((size_t)D * N * sizeof(Mom3));
+        d_brow.alloc((size_t)std::max<int64_t>(boundary_owners(), 1) * D * B * es);
+    } else {
+        d_mom.release();
+        d_brow.release();
+    }
     d_state.alloc(sizeof(SolveState));
     d_view.alloc(sizeof(DeviceView));
     if (bicg()) d_bicg.alloc((size_t)9 * D * B * N * 8);
@@ -468,7 +517,7 @@ int64_t nbte_problem::device_bytes() const {
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work, &d_acc_x, &d_acc_G, &d_acc_fprev,
           &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal, &d_lsq, &d_Sv, &d_xf, &d_xc, &d_bf_local,
-          &d_grad, &d_corr, &d_bdelta, &d_bicg})
+          &d_grad, &d_corr, &d_bdelta, &d_bicg, &d_pos, &d_bown, &d_bf_brow, &d_brow, &d_mom})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -483,6 +532,7 @@ void nbte_problem::make_view() {
     v.NBF = mesh->NBF;
     v.scheme = scheme;
     v.mom_lpc = mom_lpc();
+    v.planes = planes() ? 1 : 0;
     v.nbr = d_nbr.as<int32_t>();
     v.V = d_V.as<double>();
     v.maxin = prog.maxin;
@@ -528,6 +578,11 @@ void nbte_problem::make_view() {
     v.sdotS = d_sdotS.as<double>();
     v.win = d_win.as<double>();
     v.g = d_g.ptr;
+    v.pos = d_pos.as<int32_t>();
+    v.bown = d_bown.as<int32_t>();
+    v.brow = d_brow.ptr;
+    v.mom = d_mom.ptr;
+    v.bf_brow = d_bf_brow.as<int32_t>();
     v.gval = d_gval.ptr;
     v.Jw = d_Jw.as<double>();
     v.Jin = d_Jin.as<double>();
@@ -683,6 +738,7 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     // g = 0 is equilibrium at theta^0; the stored g is relative to theta[prev]
     NBTE_HIP(hipMemcpyAsync(d_theta[1].ptr, th0, m.N * 8, hipMemcpyDeviceToDevice, stream));
     launch_fill_zero(d_g.ptr, d_g.bytes, stream);
+    launch_fill_zero(d_brow.ptr, d_brow.bytes, stream);
     launch_fill_zero(d_gval.ptr, d_gval.bytes, stream);
     if (order == 2) {
         // the initial distribution's gradients, the first sweep's correction and
@@ -736,14 +792,21 @@ void nbte_problem::promote() {
                                                 e.what());
     }
     NBTE_HIP(hipStreamSynchronize(stream));
-    const int64_t n = mesh->N * (int64_t)bands.B * quad.D;
-    DevBuf old_g;   // the FP32 distribution, widened into the new FP64 one below
+    DevBuf old_g, old_brow;   // the FP32 distribution (and boundary rows), widened into the new FP64 ones below
     std::swap(old_g.ptr, d_g.ptr);
     std::swap(old_g.bytes, d_g.bytes);
+    std::swap(old_brow.ptr, d_brow.ptr);
+    std::swap(old_brow.bytes, d_brow.bytes);
+    const int bpb_fp32 = shape.bpb;   // its band-block planes (plane layout)
     precision = NBTE_PREC_FP64;
     ensure_setup();   // launch shape and slot table for FP64 staged values
     allocate_state(precision);
-    launch_widen(n, old_g.as<float>(), d_g.as<double>(), stream);
+    if (planes()) {   // the planes of the FP64 launch shape, and the boundary rows
+        launch_widen(quad.D, mesh->N, bands.B, old_g.as<float>(), bpb_fp32, d_g.as<double>(), shape.bpb, stream);
+        launch_widen_flat((int64_t)old_brow.bytes / 4, old_brow.as<float>(), d_brow.as<double>(), stream);
+    } else {
+        launch_widen_flat((int64_t)old_g.bytes / 4, old_g.as<float>(), d_g.as<double>(), stream);
+    }
     launch_gather((int64_t)quad.D * mesh->N, p_cell(), d_Q.as<double>(), t_row(2), false, stream);
     make_view();
     NBTE_HIP(hipMemcpyAsync(d_view.ptr, &hv, sizeof(DeviceView), hipMemcpyHostToDevice, stream));
@@ -1187,6 +1250,7 @@ nbte_status nbte_set_tuning(nbte_problem *p, const nbte_tuning *t) {
             throw Error(NBTE_ERR_INVALID_ARG, "accel_depth must be in [0, 8]");
         if (t->inner_solver < 0 || t->inner_solver > 1 || t->inner_max_iter < 0 || !(t->inner_rtol >= 0))
             throw Error(NBTE_ERR_INVALID_ARG, "bad inner solver settings");
+        if (t->layout < 0 || t->layout > 2) throw Error(NBTE_ERR_INVALID_ARG, "layout must be 0, 1 or 2");
         if (p->batch) throw Error(NBTE_ERR_STATE, "the problem is a batch member");
         p->tuning = *t;
         p->prepared = false;   // launch shape and slot table are rebuilt by the next prepare
@@ -1231,8 +1295,9 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
         // level tables (at most one level per cell); streams cell, slot, refs, upwind cells, coefficients
         // and outflow sums (storage type); inflow rows
         const int64_t es = precision == NBTE_PREC_MIXED ? 4 : 8;
-        const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * (8 + es) + es) + NBF * D * 4;
-        const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * 3 * 4 + 8 + NBF * D * (8 + 4);   // + wall cells, slots
+        const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * (8 + es) + es) + NBF * D * 4 + D * N * 4;
+        // + wall cells, slots; the boundary-owner index of every cell
+        const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * 3 * 4 + 8 + NBF * D * (8 + 4) + N * 4 + NBF * 4;
         const int64_t lh = 2 * N * (F + 1) * 12 + N * 8 * 8 + 256 * 4 * 8;   // CSR and ELL copies, vectors
         *bytes = geo + sched + plan + lh + p->state_bytes(precision);
         return NBTE_OK;

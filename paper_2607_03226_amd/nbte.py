@@ -68,7 +68,7 @@ class Tuning(ct.Structure):
     _fields_ = [("bands_per_block", ct.c_int32), ("bands_per_lane", ct.c_int32), ("block_size", ct.c_int32),
                 ("lds_bytes", ct.c_int32), ("cg_max_iter", ct.c_int32), ("cg_rtol", ct.c_double),
                 ("no_graphs", ct.c_int32), ("accel_depth", ct.c_int32), ("inner_solver", ct.c_int32),
-                ("inner_max_iter", ct.c_int32), ("inner_rtol", ct.c_double)]
+                ("inner_max_iter", ct.c_int32), ("inner_rtol", ct.c_double), ("layout", ct.c_int32)]
 
 
 # (name, restype, argtypes) of every exported symbol declared in include/nbte.h
@@ -376,10 +376,10 @@ def nbte_get_stats(p):
 
 
 def nbte_set_tuning(p, bands_per_block=0, bands_per_lane=0, block_size=0, lds_bytes=0, cg_max_iter=0, cg_rtol=0.0,
-                    no_graphs=0, accel_depth=0, inner_solver=0, inner_max_iter=0, inner_rtol=0.0):
+                    no_graphs=0, accel_depth=0, inner_solver=0, inner_max_iter=0, inner_rtol=0.0, layout=0):
     t = Tuning(int(bands_per_block), int(bands_per_lane), int(block_size), int(lds_bytes), int(cg_max_iter),
                float(cg_rtol), int(no_graphs), int(accel_depth), int(inner_solver), int(inner_max_iter),
-               float(inner_rtol))
+               float(inner_rtol), int(layout))
     _check(_lib.nbte_set_tuning(p.handle, ct.byref(t)))
 
 
