@@ -161,19 +161,24 @@ def method_bytes_per_update(p, precision):
     return 2 * es + F * es / p.n_bands + (16 * F + 48) / (p.n_bands * p.n_dirs)
 
 
+PLANES_MIN_VALUES = 1 << 26   # the library's automatic layout choice (plane layout from 2^26 values)
+
+
 def sweep_algorithmic_bytes(p, precision):
     """Compulsory HBM bytes of one launch of this library's sweep: every distribution value
     written once; the level-ordered streams of every (direction, cell) read
-    once (cell, slot, up to F-1 upwind references, their coefficients, the
-    outflow sum, the imbalance term D and the source, the real-valued ones in
-    the storage type); the boundary inflow of every incoming (face, direction)
-    read once.  Returns (bytes per launch, bytes per update)."""
+    once (cell (cell-major layout only), slot, up to F-1 upwind references,
+    their coefficients, the outflow sum, the imbalance term D and the source,
+    the real-valued ones in the storage type); the boundary inflow of every
+    incoming (face, direction) read once.  Returns (bytes per launch, bytes
+    per update)."""
     es = 4 if precision == "mixed" else 8
     N, B, D = p.n_cells, p.n_bands, p.n_dirs
     F = {"tri3": 3, "quad4": 4, "tet4": 4, "hex8": 6}[p.cell_type]
     mi = {"tri3": 2, "quad4": 2, "tet4": 3, "hex8": 3}[p.cell_type]   # most upwind faces of one cell
     dist = N * B * D * es
-    streams = D * N * (4 + 4 + 4 * mi + es * (mi + 3))
+    cell = 0 if N * B * D >= PLANES_MIN_VALUES else 4
+    streams = D * N * (cell + 4 + 4 * mi + es * (mi + 3))
     inflow = len(p.bfaces) * (D // 2) * B * es             # incoming half of the directions
     total = dist + streams + inflow
     return total, total / (N * B * D)
