@@ -129,11 +129,13 @@ def bench_serving(args, N):
     # released once served (a 2000-request stream never holds all its meshes)
     reqs = C.RequestStream(5000, args.requests)
     cal = [C.serving_request(9000 + j) for j in range(args.calibration_requests)]   # all arrive at t = 0
-    budget = int(0.5 * torch.cuda.get_device_properties(0).total_memory)
+    # admission budget: 70 % of the device memory (the rest for the setup of
+    # waiting requests, torch and the runtime)
+    budget = int(0.7 * torch.cuda.get_device_properties(0).total_memory)
     sat = serve.calibrate(cal, budget, tol=1e-8, tuning="auto")
-    rate = 0.8 * sat
+    rate = args.load * sat
     arrivals = C.poisson_arrivals(len(reqs), rate, seed=5)
-    log(f"bench: serving {len(reqs)} requests at {rate:.3f} /s (0.8 x saturated {sat:.3f} /s over "
+    log(f"bench: serving {len(reqs)} requests at {rate:.3f} /s ({args.load} x saturated {sat:.3f} /s over "
         f"{args.calibration_requests} requests), budget {budget / 2**30:.0f} GiB")
     ups = {}
 
@@ -143,6 +145,7 @@ def bench_serving(args, N):
     served, summary = serve.serve(reqs, arrivals, budget, tol=1e-8, tuning="auto", progress=50, progress_log=note)
     reqs.close()
     summary["arrival_rate_per_s"] = rate
+    summary["load_factor"] = args.load
     summary["saturated_solves_per_s"] = sat
     summary["calibration_requests"] = args.calibration_requests
     summary["updates"] = sum(s.updates for s in served)
@@ -349,8 +352,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="config3", choices=["config1", "config2", "config3", "config4", "config5"])
     ap.add_argument("--requests", type=int, default=2000, help="config5: number of requests")
-    ap.add_argument("--calibration-requests", type=int, default=32,
+    ap.add_argument("--calibration-requests", type=int, default=64,
                     help="config5: requests of the saturated-rate calibration (all arriving at once)")
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="config5: arrival rate as a fraction of the calibrated saturated rate")
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--cpu-iters", type=int, default=40, help="most oracle iterations of the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU baseline sample length (about)")

@@ -1401,7 +1401,8 @@ __device__ __forceinline__ void moments_block(const DeviceView &v, int64_t blk) 
 // --------------------------------------------------------------------------
 // W > 0: every plane W bands wide with 16-byte aligned rows (vector loads);
 // W = 0: any plane widths (one load per band).  A cell that owns a boundary
-// face also gets its values copied into its boundary row.
+// face also gets its values copied into its boundary row, for the directions
+// that leave through one of its boundary faces.
 // The band constants (1/tau, v, C/W) are read through the constant address
 // space: the band index is uniform, so they become scalar loads that do not
 // wait behind the distribution loads (vector loads would be waited on band by
@@ -1431,8 +1432,9 @@ __device__ __forceinline__ void band_sums(const DeviceView &v, int64_t i, int64_
         if (so2) gmax = fmax(gmax, fabs(x) / cwv[l]);
     };
     if (live) {
-        const int bo = v.bown[c];   // the cell's boundary row, if it owns a boundary face
-        T NBTE_G *br = bo >= 0 ? static_cast<T NBTE_G *>(v.brow) + ((int64_t)bo * D + i) * B : nullptr;
+        // the boundary row of this (cell, direction), if the boundary kernels read it
+        const int rb = v.p_brow[i * N + t];
+        T NBTE_G *br = rb >= 0 ? static_cast<T NBTE_G *>(v.brow) + (int64_t)rb * B : nullptr;
         // rows (W > 0) or bands (W = 0) requested before the first is used: 128 bytes per thread
         constexpr int G = W > 0 ? (128 / (W * (int)sizeof(T)) > 0 ? 128 / (W * (int)sizeof(T)) : 1) : 8;
         if constexpr (W > 0) {

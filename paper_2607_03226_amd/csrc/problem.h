@@ -149,7 +149,8 @@ struct nbte_problem {
     // (D*N); each cell's index among the boundary-owner cells (N) and their
     // boundary rows (storage type); per (direction, cell) band sums of the
     // reductions' first stage (storage type)
-    nbte::DevBuf d_pos, d_bown, d_bf_brow, d_brow, d_mom;
+    nbte::DevBuf d_pos, d_bown, d_bf_brow, d_brow, d_mom, d_pbrow;
+    bool pbrow_ok = false;   // d_pbrow holds the current schedule's positions
     int64_t boundary_owners() const;
     // distribution layout: band-block planes in stream order (large problems,
     // where the sweep's stores dominate) or cell-major (tuning.layout)

@@ -309,6 +309,7 @@ void nbte_problem::upload_device() {
         }
         NBTE_HIP(hipStreamSynchronize(stream));   // the program may be rebuilt (host copies replaced) after this
         sched_up = true;
+        pbrow_ok = false;
     }
     if (!plan_up) {
         upload(d_bf_kind, plan.kind, stream);
@@ -421,7 +422,7 @@ int64_t nbte_problem::state_bytes(int prec, int ord) const {
         acc = (2 * NR + 2 * NS) * 8 + 2 * (int64_t)accel_m() * NS * es + 1024 * 2 * kAccelMaxDepth * 8 + 1024;
     }
     // plane layout: the reductions' band sums and the boundary rows
-    const int64_t pl = planes() ? D * N * 24 + std::max<int64_t>(boundary_owners(), 1) * D * B * es : 0;
+    const int64_t pl = planes() ? D * N * (24 + 4) + std::max<int64_t>(boundary_owners(), 1) * D * B * es : 0;
     return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + pl + NBF * (B + 3) * 8 +
            N * 8 * 10 + 1024 + acc + so2;
 }
@@ -463,9 +464,37 @@ void nbte_problem::allocate_state(int prec) {
     if (planes()) {
         d_mom.alloc((size_t)D * N * sizeof(Mom3));
         d_brow.alloc((size_t)std::max<int64_t>(boundary_owners(), 1) * D * B * es);
+        if (!pbrow_ok) {
+            // the boundary row each stream position copies its values into:
+            // the row (owner, i) of a cell that owns a boundary face through
+            // which direction i leaves (the only directions the boundary
+            // kernels read), -1 elsewhere
+            const Mesh &m = *mesh;
+            std::vector<int32_t> bown(m.N, -1), pb((size_t)D * N, -1);
+            int32_t k = 0;
+            for (int64_t bf = 0; bf < m.NBF; ++bf) bown[m.bf_owner[bf]] = 0;
+            for (int64_t c = 0; c < N; ++c)
+                if (bown[c] == 0) bown[c] = k++;
+            std::vector<int32_t> pos((size_t)D * N);
+            for (int64_t at = 0; at < D * N; ++at) pos[(size_t)((at / N) * N + sched.perm[at])] = (int32_t)(at % N);
+            for (int64_t bf = 0; bf < m.NBF; ++bf) {
+                const int64_t c = m.bf_owner[bf];
+                const double *S = &m.S[((int64_t)c * m.F + m.bf_local[bf]) * 3];
+                for (int64_t i = 0; i < D; ++i) {
+                    const double *si = &quad.s[3 * i];
+                    if (si[0] * S[0] + si[1] * S[1] + si[2] * S[2] > 0.0)
+                        pb[(size_t)(i * N + pos[(size_t)(i * N + c)])] = (int32_t)(bown[c] * D + i);
+                }
+            }
+            upload(d_pbrow, pb, stream);
+            NBTE_HIP(hipStreamSynchronize(stream));   // the host copy goes out of scope
+            pbrow_ok = true;
+        }
     } else {
         d_mom.release();
         d_brow.release();
+        d_pbrow.release();
+        pbrow_ok = false;
     }
     d_state.alloc(sizeof(SolveState));
     d_view.alloc(sizeof(DeviceView));
@@ -517,7 +546,7 @@ int64_t nbte_problem::device_bytes() const {
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work, &d_acc_x, &d_acc_G, &d_acc_fprev,
           &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal, &d_lsq, &d_Sv, &d_xf, &d_xc, &d_bf_local,
-          &d_grad, &d_corr, &d_bdelta, &d_bicg, &d_pos, &d_bown, &d_bf_brow, &d_brow, &d_mom})
+          &d_grad, &d_corr, &d_bdelta, &d_bicg, &d_pos, &d_bown, &d_bf_brow, &d_brow, &d_mom, &d_pbrow})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -580,6 +609,7 @@ void nbte_problem::make_view() {
     v.g = d_g.ptr;
     v.pos = d_pos.as<int32_t>();
     v.bown = d_bown.as<int32_t>();
+    v.p_brow = d_pbrow.as<int32_t>();
     v.brow = d_brow.ptr;
     v.mom = d_mom.ptr;
     v.bf_brow = d_bf_brow.as<int32_t>();

@@ -254,3 +254,33 @@ def test_setup_on_several_threads_then_admission_equals_alone():
     res = _drain(N, batch, [h for _, h in built])
     for (mesh, h), a in zip(built, alone):
         _same(res[h.handle.value], a)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_batch_mixing_layouts(precision, tol):
+    """Members of both distribution layouts in one batch (the post-sweep
+    launch holds the cell-major members' flux and moment blocks, then the
+    plane members' stage-1 items from an XCD-aligned offset; the stage-2
+    launch only plane members): each member equals its stand-alone solve
+    with the same layout bitwise, and the oracle's solution within the bar."""
+    N = _N()
+    probs = C.config4_small()[:3] + [C.config3_small(), C.config2_small()]
+    layouts = [2, 1, 2, 2, 1]
+    alone = [N.solve(p, precision=precision, scheme=p.scheme, tol=tol, max_iter=4000, tuning={"layout": lay})
+             for p, lay in zip(probs, layouts)]
+    batch = N.nbte_batch_create()
+    handles, keep = [], []
+    for p, lay in zip(probs, layouts):
+        mesh, h = N.build_problem(p)
+        N.nbte_set_tuning(h, layout=lay)
+        keep.append(mesh)
+        N.nbte_batch_admit(batch, h, p.Q, N.make_opts(scheme=p.scheme, precision=precision, T_ref=p.T_ref,
+                                                       tol=tol, max_iter=4000))
+        handles.append(h)
+    res = _drain(N, batch, handles)
+    bar = 1e-9 if precision == "fp64" else 1e-6
+    for h, a, p, lay in zip(handles, alone, probs, layouts):
+        _same(res[h.handle.value], a)
+        err = _vs_oracle(res[h.handle.value], p)
+        print(p.name, precision, lay, json.dumps(err), flush=True)
+        assert max(err.values()) < bar, (p.name, lay, err)
