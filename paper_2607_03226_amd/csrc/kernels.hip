@@ -3,9 +3,12 @@
 // Storage convention: for every (direction i, cell c, band l) the library
 // keeps g = e - C_l theta(c) / W, the part of the energy density that is not
 // in equilibrium at the lattice temperature the sweep used (Methods, Eq. (11)
-// gives the equilibrium C T_L / W).  Layout g[(i*N + c)*B + l]: the bands of
-// one (direction, cell) are contiguous, so the lanes that share a cell read
-// and write one contiguous run.  g is stored in FP64 or FP32; the sweep runs
+// gives the equilibrium C T_L / W).  Two layouts (DeviceView::planes):
+// cell-major g[(i*N + c)*B + l], the bands of one (direction, cell)
+// contiguous; or, for large problems, per direction in band-block planes in
+// the sweep's stream order, so that a sweep pass stores one contiguous run
+// (the reductions and the boundary kernels then permute, see below).  g is
+// stored in FP64 or FP32; the sweep runs
 // in the storage type's arithmetic (FP32 for the mixed path), while the
 // equilibrium-imbalance differences, the band x direction reductions, the
 // diffusion correction and the residual accumulate in FP64.
