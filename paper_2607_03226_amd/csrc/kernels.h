@@ -163,15 +163,15 @@ struct DeviceView {
     void NBTE_G *g;
     const int32_t NBTE_G *pos;     // D*N: stream position of cell c in direction i (at i N + c)
     // plane layout only: boundary rows, the distribution of every cell that
-    // owns a boundary face, row (bown[c] D + i) of B values in the storage
+    // owns a boundary face, row (k D + i) of B values in the storage
     // type, copied from the planes by the reductions' first stage for the
     // directions that leave through one of the cell's boundary faces (the
     // only ones the boundary inflow and flux read; the other rows keep
     // finite stale values or zeros, which those kernels select away); and
     // the first stage's per (direction, cell) band sums
-    const int32_t NBTE_G *bown;    // N: the cell's index among the boundary-owner cells, -1 if none
-    const int32_t NBTE_G *bf_brow; // NBF: the boundary row of the face's owner (bown of the owner)
-    const int32_t NBTE_G *p_brow;  // D*N per stream position: the row bown D + i its values are copied
+    // (k: the cell's index among the cells that own a boundary face, in cell order)
+    const int32_t NBTE_G *bf_brow; // NBF: k of the face's owner
+    const int32_t NBTE_G *p_brow;  // D*N per stream position: the row k D + i its values are copied
                                    // into (the cell owns a boundary face direction i leaves through), or -1
     void NBTE_G *brow;             // n_bown D B values
     void NBTE_G *mom;              // D*N Mom3 triples: band sums of g weighted by 1/tau, 1 and v

@@ -146,10 +146,11 @@ struct nbte_problem {
     nbte::DevBuf d_Jin, d_bsum;      // boundary faces: incoming flow, per-band outgoing sums
     nbte::DevBuf d_g, d_gval, d_Jw, d_Q;
     // the distribution's row index: stream position of each cell per direction
-    // (D*N); each cell's index among the boundary-owner cells (N) and their
-    // boundary rows (storage type); per (direction, cell) band sums of the
-    // reductions' first stage (storage type)
-    nbte::DevBuf d_pos, d_bown, d_bf_brow, d_brow, d_mom, d_pbrow;
+    // (D*N); plane layout: the boundary row of each face's owner (NBF), the
+    // boundary rows (storage type), per (direction, cell) band sums of the
+    // reductions' first stage (FP64 triples) and the boundary row each stream
+    // position copies into (D*N)
+    nbte::DevBuf d_pos, d_bf_brow, d_brow, d_mom, d_pbrow;
     bool pbrow_ok = false;   // d_pbrow holds the current schedule's positions
     int64_t boundary_owners() const;
     // distribution layout: band-block planes in stream order (large problems,

@@ -281,7 +281,6 @@ void nbte_problem::upload_device() {
             if (bown[c] == 0) bown[c] = k++;
         std::vector<int32_t> bf_brow(std::max<int64_t>(m.NBF, 1), 0);
         for (int64_t bf = 0; bf < m.NBF; ++bf) bf_brow[bf] = bown[m.bf_owner[bf]];
-        upload(d_bown, bown, stream);
         upload(d_bf_brow, bf_brow, stream);
         NBTE_HIP(hipStreamSynchronize(stream));   // the host copy goes out of scope
         geom_ok = true;
@@ -546,7 +545,7 @@ int64_t nbte_problem::device_bytes() const {
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work, &d_acc_x, &d_acc_G, &d_acc_fprev,
           &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal, &d_lsq, &d_Sv, &d_xf, &d_xc, &d_bf_local,
-          &d_grad, &d_corr, &d_bdelta, &d_bicg, &d_pos, &d_bown, &d_bf_brow, &d_brow, &d_mom, &d_pbrow})
+          &d_grad, &d_corr, &d_bdelta, &d_bicg, &d_pos, &d_bf_brow, &d_brow, &d_mom, &d_pbrow})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -608,7 +607,6 @@ void nbte_problem::make_view() {
     v.win = d_win.as<double>();
     v.g = d_g.ptr;
     v.pos = d_pos.as<int32_t>();
-    v.bown = d_bown.as<int32_t>();
     v.p_brow = d_pbrow.as<int32_t>();
     v.brow = d_brow.ptr;
     v.mom = d_mom.ptr;
@@ -1326,8 +1324,8 @@ nbte_status nbte_problem_footprint(const nbte_problem *p, int32_t precision, int
         // and outflow sums (storage type); inflow rows
         const int64_t es = precision == NBTE_PREC_MIXED ? 4 : 8;
         const int64_t sched = 3 * D * (N + 1) * 4 + D * N * (4 + 4 + mi * (8 + es) + es) + NBF * D * 4 + D * N * 4;
-        // + wall cells, slots; the boundary-owner index of every cell
-        const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * 3 * 4 + 8 + NBF * D * (8 + 4) + N * 4 + NBF * 4;
+        // + wall cells, slots; the boundary row of each face's owner
+        const int64_t plan = NBF * (4 + 8 + 8 + 8) + NBF * 3 * 4 + 8 + NBF * D * (8 + 4) + NBF * 4;
         const int64_t lh = 2 * N * (F + 1) * 12 + N * 8 * 8 + 256 * 4 * 8;   // CSR and ELL copies, vectors
         *bytes = geo + sched + plan + lh + p->state_bytes(precision);
         return NBTE_OK;
