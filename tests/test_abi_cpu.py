@@ -177,6 +177,32 @@ def test_footprint_scales_with_precision():
     assert halved < f64 - f32 <= halved + ndn * (6 + 3) * 4 + 2 * p.n_bands * len(p.bfaces) * p.n_dirs * 4
 
 
+def test_plane_layout_footprint():
+    """The plane layout holds, beyond the cell-major layout's state, the
+    reductions' FP64 band sums per (direction, cell) (24 bytes), the boundary
+    row index per stream position (4 bytes) and the boundary owners' rows (at
+    most one owner per boundary face, D B values each), and the same in both
+    precisions but for the rows' storage type; layout 1 forces cell-major."""
+    p = C.config2_small()
+    mesh, h = _handles(p)
+    N.nbte_set_bands(h, p.C, p.v, p.tau)
+    N.nbte_set_quadrature(h, p.s, p.w)
+    ndn = p.n_cells * p.n_dirs
+    rows = len(p.bfaces) * p.n_dirs * p.n_bands
+    cell = {}
+    for prec, es in (("mixed", 4), ("fp64", 8)):
+        N.nbte_set_tuning(h, layout=1)
+        cell[prec] = N.nbte_problem_footprint(h, prec)
+        N.nbte_set_tuning(h, layout=2)
+        planes = N.nbte_problem_footprint(h, prec)
+        assert ndn * 28 < planes - cell[prec] <= ndn * 28 + rows * es, (prec, planes - cell[prec])
+    N.nbte_set_tuning(h, layout=0)   # auto: a problem this small stays cell-major
+    assert N.nbte_problem_footprint(h, "mixed") == cell["mixed"]
+    with pytest.raises(N.NbteError) as e:
+        N.nbte_set_tuning(h, layout=3)
+    assert e.value.status == N.ERR_INVALID_ARG
+
+
 def test_tuning_validation():
     p = C.config1()
     mesh, h = _handles(p)
