@@ -159,6 +159,9 @@ struct nbte_problem {
     int mom_lpc() const;
     nbte::DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta;
     nbte::DevBuf d_pcg_vec, d_pcg_part, d_pcg_scal;
+    // the initial guess's CG: pinned converged flags of two chunks in flight, their events
+    double *h_pcg_flag = nullptr;
+    hipEvent_t pcg_ev[2] = {nullptr, nullptr};
     nbte::DevBuf d_view, d_state, d_self_work;
     // Anderson acceleration of the outer iteration (tuning.accel_depth > 0)
     nbte::DevBuf d_acc_x, d_acc_G, d_acc_fprev, d_acc_Gprev, d_acc_dF, d_acc_dG, d_acc_part, d_acc_scal;

@@ -65,6 +65,10 @@ nbte_problem::~nbte_problem() {
     if (batch) batch_forget(batch, this);
     solo.reset();
     if (stream) (void)hipStreamSynchronize(stream);
+    if (h_pcg_flag) {
+        (void)hipHostFree(h_pcg_flag);
+        for (auto e : pcg_ev) (void)hipEventDestroy(e);
+    }
     if (own_stream) (void)hipStreamDestroy(own_stream);
 }
 
@@ -751,15 +755,23 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
         else {
             // in chunks, stopping once the sticky converged flag is set (the
             // launches after convergence would return at once but still cost
-            // their launch time)
+            // their launch time).  A chunk's flag is read while the next chunk
+            // runs, so the device never waits for the host between chunks; at
+            // most one chunk of such early-returning launches follows.
             const int limit = std::max(1000, (int)std::sqrt((double)m.N) * 20), chunk = 64;
-            for (int k0 = 0; k0 < limit; k0 += chunk) {
+            if (!h_pcg_flag) {
+                NBTE_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_pcg_flag), 2 * sizeof(double), hipHostMallocDefault));
+                for (auto &e : pcg_ev) NBTE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            }
+            for (int k0 = 0, c = 0; k0 < limit; k0 += chunk, ++c) {
                 launch_pcg_multi(vp, wk + self_pcg, n_self_pcg, 1, std::min(chunk, limit - k0), stream, k0, k0 == 0);
-                double flag = 0.0;
-                NBTE_HIP(hipMemcpyAsync(&flag, d_pcg_scal.as<double>() + 4, sizeof(double), hipMemcpyDeviceToHost,
-                                        stream));
-                NBTE_HIP(hipStreamSynchronize(stream));
-                if (flag != 0.0) break;
+                NBTE_HIP(hipMemcpyAsync(h_pcg_flag + (c & 1), d_pcg_scal.as<double>() + 4, sizeof(double),
+                                        hipMemcpyDeviceToHost, stream));
+                NBTE_HIP(hipEventRecord(pcg_ev[c & 1], stream));
+                if (c > 0) {
+                    NBTE_HIP(hipEventSynchronize(pcg_ev[(c - 1) & 1]));
+                    if (h_pcg_flag[(c - 1) & 1] != 0.0) break;
+                }
             }
         }
     }
