@@ -80,7 +80,7 @@ struct AccelWork {
     int64_t NR;                  // inflow entries: ghost rows x bands
     double NBTE_G *ain_x;        // NR: inflow of the current iterate x (temperature units)
     double NBTE_G *ain_G;        // NR: inflow of its image G(x)
-    double NBTE_G *fprev;        // N + NR: f of the previous step
+    void NBTE_G *fprev;          // N + NR: f of the previous step, in the storage type (a residual: no cancellation)
     double NBTE_G *Gprev;        // N + NR: G of the previous step (then of this step)
     void NBTE_G *dF, *dG;        // m (N + NR) each, in the storage type: column j at j (N + NR)
     double NBTE_G *part;         // nblk x 2m partial sums of a step

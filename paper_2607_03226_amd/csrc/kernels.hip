@@ -1663,8 +1663,11 @@ __global__ void k_finish(const DeviceView *__restrict__ vs, const WorkItem *__re
 // image, ain_x / ain_G the inflow parts.  Step k (k = steps done before it):
 // k = 0 keeps f and G only (x_next = G); k >= 1 writes the newest columns
 // into slot (k - 1) mod m and the partial sums a_j = dF_new . dF_j and
-// b_j = dF_j . f of the w = min(k, m) columns in the window.  The columns are
-// stored in the storage type; the sums use the stored values.
+// b_j = dF_j . f of the w = min(k, m) columns in the window.  The columns
+// and the previous step's f are stored in the storage type (f and its
+// differences are residuals, not temperatures, so FP32 storage loses nothing
+// to cancellation); G, whose differences are taken, stays in FP64.  The sums
+// use the stored values.
 // --------------------------------------------------------------------------
 template <class T, int W>
 __device__ __forceinline__ void accel_cols_rows(const DeviceView &v, const WorkItem &it, int k, int c, double *sa,
@@ -1677,7 +1680,7 @@ __device__ __forceinline__ void accel_cols_rows(const DeviceView &v, const WorkI
     for (int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x; s < NS; s += (int64_t)it.c * blockDim.x) {
         const double xv = s < N ? tx[s] : a.ain_x[s - N];
         const double gv = s < N ? tg[s] : a.ain_G[s - N];
-        const double fp = a.fprev[s], gp = a.Gprev[s];
+        const double fp = static_cast<double>(static_cast<const T *>(a.fprev)[s]), gp = a.Gprev[s];
         double dj[W > 0 ? W : 1];
 #pragma unroll
         for (int j = 0; j < W; ++j) dj[j] = j == c ? 0.0 : static_cast<double>(dF[j * NS + s]);
@@ -1694,7 +1697,7 @@ __device__ __forceinline__ void accel_cols_rows(const DeviceView &v, const WorkI
                 sb[j] += d * f;
             }
         }
-        a.fprev[s] = f;
+        static_cast<T *>(a.fprev)[s] = static_cast<T>(f);
         a.Gprev[s] = gv;
     }
 }
@@ -1781,12 +1784,14 @@ __global__ void __launch_bounds__(256) k_accel_solve(const DeviceView *__restric
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    double gam[kAccelMaxDepth];
+    // thread 0's small dense algebra works in LDS: its loops index these
+    // arrays with run-time indices, which would otherwise place them in
+    // scratch memory (a global-memory round trip per access)
+    __shared__ double gam[kAccelMaxDepth], L[kAccelMaxDepth][kAccelMaxDepth], y[kAccelMaxDepth];
+    __shared__ int ord[kAccelMaxDepth];
     for (int j = 0; j < kAccelMaxDepth; ++j) gam[j] = 0.0;
     if (k > 0) {
-        int ord[kAccelMaxDepth];
         for (int p = 0; p < w; ++p) ord[p] = ((c - p) % m + m) % m;   // newest first
-        double L[kAccelMaxDepth][kAccelMaxDepth], y[kAccelMaxDepth];
         int used = 0;
         for (int p = 0; p < w; ++p) {
             const double hpp = H[ord[p] * m + ord[p]];

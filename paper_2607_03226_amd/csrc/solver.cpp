@@ -422,7 +422,7 @@ int64_t nbte_problem::state_bytes(int prec, int ord) const {
     int64_t acc = 0;
     if (accel_m() > 0) {
         const int64_t NR = accel_rows(), NS = N + NR;
-        acc = (2 * NR + 2 * NS) * 8 + 2 * (int64_t)accel_m() * NS * es + 1024 * 2 * kAccelMaxDepth * 8 + 1024;
+        acc = (2 * NR + NS) * 8 + NS * es + 2 * (int64_t)accel_m() * NS * es + 1024 * 2 * kAccelMaxDepth * 8 + 1024;
     }
     // plane layout: the reductions' band sums and the boundary rows
     const int64_t pl = planes() ? D * N * (24 + 4) + std::max<int64_t>(boundary_owners(), 1) * D * B * es : 0;
@@ -528,7 +528,7 @@ void nbte_problem::allocate_state(int prec) {
         const int64_t NR = accel_rows(), NS = N + NR;
         d_acc_x.alloc(NR * 8);
         d_acc_G.alloc(NR * 8);
-        d_acc_fprev.alloc(NS * 8);
+        d_acc_fprev.alloc(NS * es);
         d_acc_Gprev.alloc(NS * 8);
         d_acc_dF.alloc((size_t)accel_m() * NS * es);
         d_acc_dG.alloc((size_t)accel_m() * NS * es);
@@ -647,7 +647,7 @@ void nbte_problem::make_view() {
     a.NR = a.m > 0 ? accel_rows() : 0;
     a.ain_x = d_acc_x.as<double>();
     a.ain_G = d_acc_G.as<double>();
-    a.fprev = d_acc_fprev.as<double>();
+    a.fprev = d_acc_fprev.ptr;
     a.Gprev = d_acc_Gprev.as<double>();
     a.dF = d_acc_dF.ptr;
     a.dG = d_acc_dG.ptr;
