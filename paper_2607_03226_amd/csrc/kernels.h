@@ -77,11 +77,15 @@ struct PcgWork {
 struct AccelWork {
     int32_t m;                   // depth (columns kept); 0 = off
     int32_t nblk;                // workgroups of the state-length launches
-    int64_t NR;                  // inflow entries: ghost rows x bands
+    // inflow entries: the incoming (face, direction) rows of the faces whose
+    // inflow depends on the distribution (a thermalizing face's is fixed: its
+    // entries would be exact zeros in every column) x bands
+    int64_t NR;
+    const int32_t NBTE_G *in;    // NBF*D: row in the inflow entries of an incoming (face, direction), else -1
     double NBTE_G *ain_x;        // NR: inflow of the current iterate x (temperature units)
-    double NBTE_G *ain_G;        // NR: inflow of its image G(x)
+    double NBTE_G *ain_G;        // 2 NR: inflow of its image G(x), step k's in half k mod 2 (the previous step's is kept)
     void NBTE_G *fprev;          // N + NR: f of the previous step, in the storage type (a residual: no cancellation)
-    double NBTE_G *Gprev;        // N + NR: G of the previous step (then of this step)
+    double NBTE_G *Gprev;        // N: the temperature part of G of the previous step (then of this step)
     void NBTE_G *dF, *dG;        // m (N + NR) each, in the storage type: column j at j (N + NR)
     double NBTE_G *part;         // nblk x 2m partial sums of a step
     double NBTE_G *scal;         // [0] steps done; [1..m*m] Gram matrix dF_i . dF_j; then m gammas

@@ -163,11 +163,26 @@ __device__ void bc_face_mixed(const DeviceView &v, int64_t bf) {
     const double *sd = v.sdotS + bf * D;
     const int32_t *row = v.in_row + bf * D;
     const double thc = theta_cur(v)[c];
-    const double *ax = v.acc.ain_x;
-    const bool refl = v.bf_kind[bf] != NBTE_BC_THERMALIZING;
     const int BL = B < 64 ? B : 64;
     const int JG = 64 / BL;
     const int jg = lane / BL, ml = lane - jg * BL;
+    if (v.bf_kind[bf] == NBTE_BC_THERMALIZING) {
+        // fixed inflow, not part of the state (and no net flow kept)
+        const double thw = v.bf_thw[bf];
+        for (int l0 = 0; l0 < B; l0 += BL) {
+            const int lam = l0 + ml;
+            if (jg >= JG || lam >= B) continue;
+            const T val = static_cast<T>(v.Cw[lam] * (thw - thc));
+#pragma unroll 8
+            for (int i = jg; i < D; i += JG) {
+                const int r = row[i];
+                if (r >= 0) gv[(int64_t)r * B + lam] = val;
+            }
+        }
+        return;
+    }
+    const double *ax = v.acc.ain_x;
+    const int32_t *arow = v.acc.in + bf * D;   // the state's rows (independent of the ghost rows' load)
     double jin = 0.0;
     for (int l0 = 0; l0 < B; l0 += BL) {
         const int lam = l0 + ml;
@@ -178,7 +193,7 @@ __device__ void bc_face_mixed(const DeviceView &v, int64_t bf) {
         for (int i = jg; i < D; i += JG) {
             const int r = row[i];
             if (r >= 0) {
-                const double t = ax[(int64_t)r * B + lam];
+                const double t = ax[(int64_t)arow[i] * B + lam];
                 gv[(int64_t)r * B + lam] = static_cast<T>(cw * (t - thc));
                 acc += v.w[i] * sd[i] * t;
             }
@@ -186,38 +201,28 @@ __device__ void bc_face_mixed(const DeviceView &v, int64_t bf) {
         jin += v.vel[lam] * cw * acc;
     }
     jin = wave_sum(jin);
-    if (lane == 0 && refl) v.Jin[bf] = jin;
+    if (lane == 0) v.Jin[bf] = jin;
 }
 
 // The inflow a boundary face's incoming rows receive from the distribution of
 // the last sweep (the boundary conditions above applied to it), in
 // temperature units (e W / C_l), into dst (acc.ain_G: the image of an
-// accelerated step; acc.ain_x: the initial state at prepare).  Runs after the
+// accelerated step; acc.ain_x: the initial state at prepare), at the rows
+// acc.in gives (a thermalizing face's fixed inflow is not part of the
+// state: nothing is written for it).  Runs after the
 // iteration's rotation, so theta[prev] is the last sweep's temperature and
 // bsum holds the outgoing sums of its distribution.
 template <class T>
 __device__ void bc_face_abs(const DeviceView &v, int64_t bf, double *dst) {
     const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
-    const int64_t N = v.N;
     const int c = v.bf_owner[bf];
     const OwnerRows<T> og = owner_rows<T>(v, bf);   // the owner's distribution
-    const int32_t *row = v.in_row + bf * D;
     const int BL = B < 64 ? B : 64;
     const int JG = 64 / BL;
     const int jg = lane / BL, ml = lane - jg * BL;
-    if (v.bf_kind[bf] == NBTE_BC_THERMALIZING) {
-        const double thw = v.bf_thw[bf];
-        for (int l0 = 0; l0 < B; l0 += BL) {
-            const int lam = l0 + ml;
-            if (jg >= JG || lam >= B) continue;
-            for (int i = jg; i < D; i += JG) {
-                const int r = row[i];
-                if (r >= 0) dst[(int64_t)r * B + lam] = thw;
-            }
-        }
-        return;
-    }
+    if (v.bf_kind[bf] == NBTE_BC_THERMALIZING) return;   // fixed inflow: not part of the state
+    const int32_t *arow = v.acc.in + bf * D;
     const double thp = theta_prev(v)[c];
     const double p = v.bf_p[bf];
     const double iw = 1.0 / v.win[bf];
@@ -229,7 +234,7 @@ __device__ void bc_face_abs(const DeviceView &v, int64_t bf, double *dst) {
         const double diff = p < 1.0 ? v.bsum[bf * B + lam] * iw / cw : 0.0;
 #pragma unroll 8
         for (int i = jg; i < D; i += JG) {
-            const int r = row[i];
+            const int r = arow[i];
             if (r < 0) continue;
             double t = (1.0 - p) * diff;
             if (p > 0.0) t += p * (ld(og.p, (int64_t)mir[i] * og.stride + lam) / cw + thp);
@@ -246,7 +251,6 @@ __device__ void bc_face(const DeviceView &v, int64_t bf, double *red) {
     }
     const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
-    const int64_t N = v.N;
     const int c = v.bf_owner[bf];
     T *gv = static_cast<T *>(v.gval);
     const double *sd = v.sdotS + bf * D;
@@ -361,7 +365,6 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
         // lagged faces: the upwind cell's value of the previous iterate, as the
         // deviation from the downwind cell's equilibrium at the coming theta
         const int B = v.B;
-        const int64_t N = v.N;
         const T *g = static_cast<const T *>(v.g);
         T *gv = static_cast<T *>(v.gval);
         const double *thp = theta_prev(v), *thc = theta_cur(v);
@@ -372,7 +375,9 @@ __global__ void __launch_bounds__(256) k_stage(const DeviceView *__restrict__ vs
             gv[(int64_t)L[0] * B + lam] = static_cast<T>(e - v.Cw[lam] * thc[L[2]]);
         }
     } else if (it.a >= 2) {
-        double *dst = it.a == 2 ? v.acc.ain_G : v.acc.ain_x;
+        // kind 2: the image of step k (steps done) into half k mod 2 of ain_G
+        const AccelWork &a = v.acc;
+        double *dst = it.a == 2 ? a.ain_G + (int64_t)((int)a.scal[0] & 1) * a.NR : a.ain_x;
         const int wv = threadIdx.x >> 6;
         for (int64_t bf = (int64_t)it.b * 4 + wv; bf < v.NBF; bf += (int64_t)it.c * 4) bc_face_abs<T>(v, bf, dst);
     } else {
@@ -1232,7 +1237,6 @@ __device__ void flux_face(const DeviceView &v, int64_t bf, int mode) {
     if (mode != 1 && v.bf_kind[bf] == NBTE_BC_THERMALIZING) return;
     const int lane = threadIdx.x & 63;
     const int D = v.D, B = v.B;
-    const int64_t N = v.N;
     const int c = v.bf_owner[bf];
     const double th = (mode == 0 ? theta_cur(v) : theta_prev(v))[c];
     const OwnerRows<T> og = owner_rows<T>(v, bf);   // the owner's distribution
@@ -1416,7 +1420,7 @@ __device__ __forceinline__ void band_sums(const DeviceView &v, int64_t i, int64_
     // the descriptor's fields in registers: the stores below could otherwise
     // alias the descriptor in memory and force a reload of every pointer
     const int64_t N = v.N;
-    const int B = v.B, bpb = v.bpb, D = v.D;
+    const int B = v.B, bpb = v.bpb;
     const bool so2 = v.order == 2;
     const double NBTE_C *itau = (const double NBTE_C *)v.inv_tau;
     const double NBTE_C *vel = (const double NBTE_C *)v.vel;
@@ -1675,12 +1679,16 @@ __device__ __forceinline__ void accel_cols_rows(const DeviceView &v, const WorkI
     const AccelWork &a = v.acc;
     const int64_t N = v.N, NS = N + a.NR;
     const double *tx = theta_prev(v), *tg = theta_cur(v);
+    // this step's inflow image and the previous step's (the other half; read
+    // but unused at k = 0)
+    const double *Gk = a.ain_G + (int64_t)(k & 1) * a.NR, *Gp = a.ain_G + (int64_t)((k + 1) & 1) * a.NR;
     T *dF = static_cast<T *>(a.dF);
     T *dG = static_cast<T *>(a.dG);
     for (int64_t s = (int64_t)it.b * blockDim.x + threadIdx.x; s < NS; s += (int64_t)it.c * blockDim.x) {
         const double xv = s < N ? tx[s] : a.ain_x[s - N];
-        const double gv = s < N ? tg[s] : a.ain_G[s - N];
-        const double fp = static_cast<double>(static_cast<const T *>(a.fprev)[s]), gp = a.Gprev[s];
+        const double gv = s < N ? tg[s] : Gk[s - N];
+        const double fp = static_cast<double>(static_cast<const T *>(a.fprev)[s]);
+        const double gp = s < N ? a.Gprev[s] : Gp[s - N];
         double dj[W > 0 ? W : 1];
 #pragma unroll
         for (int j = 0; j < W; ++j) dj[j] = j == c ? 0.0 : static_cast<double>(dF[j * NS + s]);
@@ -1698,7 +1706,7 @@ __device__ __forceinline__ void accel_cols_rows(const DeviceView &v, const WorkI
             }
         }
         static_cast<T *>(a.fprev)[s] = static_cast<T>(f);
-        a.Gprev[s] = gv;
+        if (s < N) a.Gprev[s] = gv;
     }
 }
 
@@ -1827,9 +1835,11 @@ __global__ void __launch_bounds__(256) k_accel_solve(const DeviceView *__restric
     a.scal[0] = k + 1;
 }
 
-// x_next = G - sum_j gamma_j dG_j into theta[cur] and ain_x.
+// x_next = G - sum_j gamma_j dG_j into theta[cur] and ain_x (Gin: the
+// step's inflow image).
 template <class T, int W>
-__device__ __forceinline__ void accel_mix_rows(const DeviceView &v, const WorkItem &it, const double *gam) {
+__device__ __forceinline__ void accel_mix_rows(const DeviceView &v, const WorkItem &it, const double *gam,
+                                               const double *Gin) {
     const AccelWork &a = v.acc;
     const int64_t N = v.N, NS = N + a.NR;
     const T *dG = static_cast<const T *>(a.dG);
@@ -1838,7 +1848,7 @@ __device__ __forceinline__ void accel_mix_rows(const DeviceView &v, const WorkIt
         double d[W > 0 ? W : 1];
 #pragma unroll
         for (int j = 0; j < W; ++j) d[j] = static_cast<double>(dG[j * NS + s]);
-        double x = a.Gprev[s];
+        double x = s < N ? a.Gprev[s] : Gin[s - N];
 #pragma unroll
         for (int j = 0; j < W; ++j) x -= gam[j] * d[j];
         if (s < N) tn[s] = x;
@@ -1858,16 +1868,17 @@ __global__ void __launch_bounds__(256) k_accel_mix(const DeviceView *__restrict_
     double gam[kAccelMaxDepth];
 #pragma unroll
     for (int j = 0; j < kAccelMaxDepth; ++j) gam[j] = j < m ? a.scal[1 + m * m + j] : 0.0;
+    const double *Gin = a.ain_G + (int64_t)((k - 1) & 1) * a.NR;   // this step's (k - 1) image
     switch (w) {
-        case 0: accel_mix_rows<T, 0>(v, it, gam); break;
-        case 1: accel_mix_rows<T, 1>(v, it, gam); break;
-        case 2: accel_mix_rows<T, 2>(v, it, gam); break;
-        case 3: accel_mix_rows<T, 3>(v, it, gam); break;
-        case 4: accel_mix_rows<T, 4>(v, it, gam); break;
-        case 5: accel_mix_rows<T, 5>(v, it, gam); break;
-        case 6: accel_mix_rows<T, 6>(v, it, gam); break;
-        case 7: accel_mix_rows<T, 7>(v, it, gam); break;
-        default: accel_mix_rows<T, 8>(v, it, gam); break;
+        case 0: accel_mix_rows<T, 0>(v, it, gam, Gin); break;
+        case 1: accel_mix_rows<T, 1>(v, it, gam, Gin); break;
+        case 2: accel_mix_rows<T, 2>(v, it, gam, Gin); break;
+        case 3: accel_mix_rows<T, 3>(v, it, gam, Gin); break;
+        case 4: accel_mix_rows<T, 4>(v, it, gam, Gin); break;
+        case 5: accel_mix_rows<T, 5>(v, it, gam, Gin); break;
+        case 6: accel_mix_rows<T, 6>(v, it, gam, Gin); break;
+        case 7: accel_mix_rows<T, 7>(v, it, gam, Gin); break;
+        default: accel_mix_rows<T, 8>(v, it, gam, Gin); break;
     }
 }
 

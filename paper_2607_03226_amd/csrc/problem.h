@@ -165,6 +165,8 @@ struct nbte_problem {
     nbte::DevBuf d_view, d_state, d_self_work;
     // Anderson acceleration of the outer iteration (tuning.accel_depth > 0)
     nbte::DevBuf d_acc_x, d_acc_G, d_acc_fprev, d_acc_Gprev, d_acc_dF, d_acc_dG, d_acc_part, d_acc_scal;
+    nbte::DevBuf d_acc_in;    // NBF*D: row of the state's inflow part of an incoming (face, direction), else -1
+    int64_t acc_NR = 0;       // inflow entries of the state (rows of non-thermalizing faces x bands)
     int acc_nblk = 1;
     int self_acc = 0, n_self_acc = 0;   // offsets in d_self_work: initial inflow state (face waves)
     int accel_m() const { return tuning.accel_depth; }
@@ -178,7 +180,7 @@ struct nbte_problem {
     nbte::DevBuf d_lsq, d_Sv, d_xf, d_xc, d_bf_local, d_grad, d_corr, d_bdelta;
     int so2_nblk = 1, so2_nblk_b = 1;   // workgroups of the gradient / correction and of the boundary launches
     int self_so2 = 0;                    // offset in d_self_work: [grad items][corr items][boundary items]
-    int64_t accel_rows() const;         // NR: ghost rows x bands
+    int64_t accel_rows() const;         // bound on NR: ghost rows x bands
     int pcg_nblk = 1;
     int ell_w = 0;                   // ELL width of the correction's matrix
 

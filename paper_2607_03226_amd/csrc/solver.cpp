@@ -422,7 +422,10 @@ int64_t nbte_problem::state_bytes(int prec, int ord) const {
     int64_t acc = 0;
     if (accel_m() > 0) {
         const int64_t NR = accel_rows(), NS = N + NR;
-        acc = (2 * NR + NS) * 8 + NS * es + 2 * (int64_t)accel_m() * NS * es + 1024 * 2 * kAccelMaxDepth * 8 + 1024;
+        // inflow of x and two images, theta part of G, previous f, columns, partials, row index (NR bounds
+        // the state's inflow entries: thermalizing faces' rows are left out)
+        acc = 3 * NR * 8 + N * 8 + NS * es + 2 * (int64_t)accel_m() * NS * es + 1024 * 2 * kAccelMaxDepth * 8 + 1024 +
+              NBF * D * 4;
     }
     // plane layout: the reductions' band sums and the boundary rows
     const int64_t pl = planes() ? D * N * (24 + 4) + std::max<int64_t>(boundary_owners(), 1) * D * B * es : 0;
@@ -525,19 +528,35 @@ void nbte_problem::allocate_state(int prec) {
         for (DevBuf *b : {&d_grad, &d_corr, &d_bdelta}) b->release();
     }
     if (accel_m() > 0) {
-        const int64_t NR = accel_rows(), NS = N + NR;
+        // the state's inflow part: the incoming rows of the faces whose inflow
+        // depends on the distribution, numbered face by face
+        if ((int64_t)plan.kind.size() != NBF || (int64_t)prog.in_row.size() != NBF * D)
+            throw Error(NBTE_ERR_STATE, "boundary plan or sweep program out of date");
+        std::vector<int32_t> ain(std::max<int64_t>(NBF * D, 1), -1);
+        int64_t rows = 0;
+        for (int64_t bf = 0; bf < NBF; ++bf) {
+            if (plan.kind[bf] == NBTE_BC_THERMALIZING) continue;
+            for (int64_t i = 0; i < D; ++i)
+                if (prog.in_row[bf * D + i] >= 0) ain[bf * D + i] = (int32_t)rows++;
+        }
+        acc_NR = std::max<int64_t>(rows, 1) * B;
+        upload(d_acc_in, ain, stream);
+        NBTE_HIP(hipStreamSynchronize(stream));   // the host copy goes out of scope
+        const int64_t NR = acc_NR, NS = N + NR;
         d_acc_x.alloc(NR * 8);
-        d_acc_G.alloc(NR * 8);
+        d_acc_G.alloc(2 * NR * 8);
         d_acc_fprev.alloc(NS * es);
-        d_acc_Gprev.alloc(NS * 8);
+        d_acc_Gprev.alloc(N * 8);
         d_acc_dF.alloc((size_t)accel_m() * NS * es);
         d_acc_dG.alloc((size_t)accel_m() * NS * es);
         acc_nblk = (int)std::min<int64_t>(1024, cdiv(NS, 256));
         d_acc_part.alloc((size_t)acc_nblk * 2 * kAccelMaxDepth * 8);
         d_acc_scal.alloc((1 + kAccelMaxDepth * kAccelMaxDepth + kAccelMaxDepth) * 8);
     } else {
-        for (DevBuf *b : {&d_acc_x, &d_acc_G, &d_acc_fprev, &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal})
+        for (DevBuf *b :
+             {&d_acc_x, &d_acc_G, &d_acc_fprev, &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal, &d_acc_in})
             b->release();
+        acc_NR = 0;
     }
 }
 
@@ -548,7 +567,7 @@ int64_t nbte_problem::device_bytes() const {
           &d_mirror, &d_wall, &d_wall_ptr, &d_wslot, &d_wallJ, &d_bf_thw, &d_bf_p, &d_sdotS, &d_win, &d_Lrow, &d_Lcol, &d_Lval, &d_Ldinv, &d_Ecol, &d_Eval, &d_g, &d_gval,
           &d_Jw, &d_Jin, &d_bsum, &d_Q, &d_theta[0], &d_theta[1], &d_theta[2], &d_theta_seq, &d_thetaE, &d_q, &d_rhs, &d_delta,
           &d_pcg_vec, &d_pcg_part, &d_pcg_scal, &d_view, &d_state, &d_self_work, &d_acc_x, &d_acc_G, &d_acc_fprev,
-          &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal, &d_lsq, &d_Sv, &d_xf, &d_xc, &d_bf_local,
+          &d_acc_Gprev, &d_acc_dF, &d_acc_dG, &d_acc_part, &d_acc_scal, &d_acc_in, &d_lsq, &d_Sv, &d_xf, &d_xc, &d_bf_local,
           &d_grad, &d_corr, &d_bdelta, &d_bicg, &d_pos, &d_bf_brow, &d_brow, &d_mom, &d_pbrow})
         s += (int64_t)b->bytes;
     return s;
@@ -644,7 +663,8 @@ void nbte_problem::make_view() {
     AccelWork &a = v.acc;
     a.m = accel_m();
     a.nblk = acc_nblk;
-    a.NR = a.m > 0 ? accel_rows() : 0;
+    a.NR = a.m > 0 ? acc_NR : 0;
+    a.in = d_acc_in.as<int32_t>();
     a.ain_x = d_acc_x.as<double>();
     a.ain_G = d_acc_G.as<double>();
     a.fprev = d_acc_fprev.ptr;
