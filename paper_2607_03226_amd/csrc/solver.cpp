@@ -810,8 +810,12 @@ void nbte_problem::prepare(const double *Q_cell, const nbte_solve_opts &o) {
     // the first boundary stage's diffuse sums, from the initial distribution
     launch_flux(d_view.as<DeviceView>(), d_self_work.as<WorkItem>() + self_flux, n_self_flux, fp32(), 2, stream);
     if (accel_m() > 0) {
-        // the accelerated iteration starts from the initial state's inflow, with no history
+        // the accelerated iteration starts from the initial state's inflow, with no
+        // history; the inflow buffers start at zero (with only thermalizing faces
+        // the state keeps one placeholder row that no stage writes)
         launch_fill_zero(d_acc_scal.ptr, d_acc_scal.bytes, stream);
+        launch_fill_zero(d_acc_x.ptr, d_acc_x.bytes, stream);
+        launch_fill_zero(d_acc_G.ptr, d_acc_G.bytes, stream);
         launch_stage(d_view.as<DeviceView>(), d_self_work.as<WorkItem>() + self_acc, n_self_acc, fp32(), stream);
     }
     NBTE_HIP(hipGetLastError());

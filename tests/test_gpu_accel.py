@@ -101,6 +101,30 @@ def test_accelerated_solve_reaches_the_oracle_fixed_point(name, maker, scheme, p
         assert acc["iterations"] <= plain["iterations"], rec
 
 
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-9), ("mixed", 1e-6)])
+def test_accelerated_solve_with_only_thermalizing_walls(precision, bar):
+    """Every wall thermalizing: the state's inflow part holds no boundary row
+    at all (a fixed inflow is left out), so the acceleration works on the
+    temperatures alone; the fixed point is still the oracle's."""
+    import dataclasses
+    from workloads.problem import Boundary
+    N = _N()
+    base = C.config1()
+    walls = [Boundary(b.tag, "thermalizing", b.T_wall if b.kind == "thermalizing" else 300.5) for b in base.boundaries]
+    p = dataclasses.replace(base, boundaries=walls)
+    r = oracle.solve(p, tol=1e-13, max_iter=20000, defect_tol=1e-11)
+    tol = 1e-12 if precision == "fp64" else 1e-8
+    acc = N.solve(p, precision=precision, scheme="sequential", tol=tol, max_iter=5000, allow_not_converged=True,
+                  accel=5)
+    s = np.max(np.abs(r.T_lattice - p.T_ref))
+    err = float(np.max(np.abs(acc["T_lattice"] - r.T_lattice)) / s)
+    errq = float(np.max(np.linalg.norm(acc["q"] - r.q, axis=1)) / np.max(np.linalg.norm(r.q, axis=1)))
+    print(f"thermalizing_walls/{precision}", json.dumps({"err_TL": err, "err_q": errq, "iterations": acc["iterations"]}),
+          flush=True)
+    assert acc["residual"] <= tol
+    assert err < bar and errq < bar
+
+
 def test_accelerated_batch_member_equals_its_standalone_solve():
     N = _N()
     probs = C.config4_small()[:3] + [C.config3_small()]
