@@ -302,7 +302,8 @@ typedef struct {
                                  eagerly) */
     int32_t accel_depth;      /* Anderson acceleration of the outer iteration (0 = off, at most 8):
                                  the iterate (lattice temperature and the boundary inflow of every
-                                 incoming face row and band) is replaced after each iteration by
+                                 incoming row and band of the non-thermalizing faces, whose inflow
+                                 depends on the distribution) is replaced after each iteration by
                                  G(x) - dG gamma, gamma the least-squares fit of the residual
                                  f = G(x) - x by the differences dF of the last accel_depth steps
                                  (D. G. Anderson 1965; Walker & Ni 2011).  An addition to the
@@ -310,7 +311,7 @@ typedef struct {
                                  image's residual) and the results at convergence are those of the
                                  plain iteration.  Holds about (2 accel_depth + 4) state vectors of
                                  n_cells + n_rows x n_bands values on the device (counted by
-                                 nbte_problem_footprint). */
+                                 nbte_problem_footprint, with every incoming row as the bound). */
     int32_t inner_solver;     /* transport solve of each (band, direction) system in an iteration:
                                  0 (default) the exact upwind sweep in level order; 1 matrix-free
                                  BiCGSTAB with the Jacobi (diagonal) preconditioner (the paper's
