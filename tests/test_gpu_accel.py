@@ -125,6 +125,33 @@ def test_accelerated_solve_with_only_thermalizing_walls(precision, bar):
     assert err < bar and errq < bar
 
 
+@pytest.mark.parametrize("name,maker,scheme", [("config1", C.config1, "sequential"),
+                                               ("config3_small", C.config3_small, "synthetic")])
+def test_stalled_accelerated_mixed_solve_continues_in_fp64(name, maker, scheme):
+    """A tolerance below the FP32 floor: the accelerated mixed iteration
+    stalls, the solve switches to FP64 (columns widened, history restarted
+    from the last plain image, the inflow state rebuilt) and reaches the
+    oracle's fixed point."""
+    N = _N()
+    p = maker()
+    if name not in _REF:
+        _REF[name] = oracle.solve(p, tol=1e-13, max_iter=20000, defect_tol=1e-11)
+    r = _REF[name]
+    mesh, h = N.build_problem(p)
+    N.nbte_set_tuning(h, accel_depth=5)
+    out = N.nbte_solve_steady(h, p.Q, N.make_opts(scheme=scheme, precision="mixed", T_ref=p.T_ref, tol=1e-11,
+                                                   max_iter=20000))
+    st = N.nbte_get_stats(h)
+    s = np.max(np.abs(r.T_lattice - p.T_ref))
+    err = float(np.max(np.abs(out["T_lattice"] - r.T_lattice)) / s)
+    errq = float(np.max(np.linalg.norm(out["q"] - r.q, axis=1)) / np.max(np.linalg.norm(r.q, axis=1)))
+    print(f"{name}/mixed_accel_refined", json.dumps({"err_TL": err, "err_q": errq, "iterations": out["iterations"],
+                                                      "refined_at": st["refined_at"]}), flush=True)
+    assert st["refined_at"] > 0
+    assert out["residual"] <= 1e-11
+    assert err < 1e-9 and errq < 1e-9
+
+
 def test_accelerated_batch_member_equals_its_standalone_solve():
     N = _N()
     probs = C.config4_small()[:3] + [C.config3_small()]
