@@ -1621,7 +1621,21 @@ __global__ void __launch_bounds__(256) k_update(const DeviceView *__restrict__ v
         md = fmax(md, __shfl_xor(md, off));
         mt = fmax(mt, __shfl_xor(mt, off));
     }
+    // the waves' maxima combined in LDS, then one pair of atomics per
+    // workgroup (per-wave atomics on the same two words serialise in L2:
+    // config 3's 565 workgroups took 32 us, nearly all of it in the atomics)
+    __shared__ double wmax[2][4];
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        wmax[0][wv] = md;
+        wmax[1][wv] = mt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+            md = fmax(md, wmax[0][q]);
+            mt = fmax(mt, wmax[1][q]);
+        }
         atomicMax(&v.state->maxbuf[0], dbits(md));
         atomicMax(&v.state->maxbuf[1], dbits(mt));
     }
