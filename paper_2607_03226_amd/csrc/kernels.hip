@@ -102,6 +102,14 @@ __device__ __forceinline__ unsigned long long dbits(double x) {
     return static_cast<unsigned long long>(__double_as_longlong(x));
 }
 
+// atomic maximum into a word that only grows within a launch: the atomic is
+// skipped when the word already holds at least x (a read first), so the
+// many waves below the running maximum do not queue on the one word
+__device__ __forceinline__ void max_into(unsigned long long NBTE_G *word, double x) {
+    const unsigned long long b = dbits(x);
+    if (b > *reinterpret_cast<volatile unsigned long long NBTE_G *>(word)) atomicMax(word, b);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
     return x;
@@ -1379,7 +1387,7 @@ __device__ __forceinline__ void moments_block(const DeviceView &v, int64_t blk) 
     if (v.order == 2) {
         if (!(gmax <= 1e300)) gmax = INFINITY;
         for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
-        if ((threadIdx.x & 63) == 0) atomicMax(&v.state->maxbuf[2], dbits(gmax));
+        if ((threadIdx.x & 63) == 0) max_into(&v.state->maxbuf[2], gmax);
     }
     if (c < N && lane == 0) {
         const double th = theta_cur(v)[c];
@@ -1488,7 +1496,7 @@ __device__ __forceinline__ void band_sums(const DeviceView &v, int64_t i, int64_
     if (so2) {
         if (!(gmax <= 1e300)) gmax = INFINITY;
         for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, off));
-        if ((threadIdx.x & 63) == 0) atomicMax(&v.state->maxbuf[2], dbits(gmax));
+        if ((threadIdx.x & 63) == 0) max_into(&v.state->maxbuf[2], gmax);
     }
 }
 
