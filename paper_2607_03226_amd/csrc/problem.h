@@ -155,7 +155,8 @@ struct nbte_problem {
     int64_t boundary_owners() const;
     // distribution layout: band-block planes in stream order (large problems,
     // where the sweep's stores dominate) or cell-major (tuning.layout)
-    bool planes() const;
+    bool planes() const { return planes_for(order); }
+    bool planes_for(int ord) const;   // the layout a solve of spatial order ord takes
     int mom_lpc() const;
     nbte::DevBuf d_theta[3], d_theta_seq, d_thetaE, d_q, d_rhs, d_delta;
     nbte::DevBuf d_pcg_vec, d_pcg_part, d_pcg_scal;

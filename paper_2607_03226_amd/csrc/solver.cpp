@@ -108,9 +108,12 @@ int nbte_problem::mom_lpc() const {
 // kernels then permute (measured: config 3, 444M values, 5 % faster per
 // iteration; config 2, 28M values, cache resident, 30 % slower).  Chosen by
 // the element count, so the layout does not change with the precision.
-bool nbte_problem::planes() const {
+bool nbte_problem::planes_for(int ord) const {
     if (tuning.layout != 0) return tuning.layout == 2;
-    return (int64_t)mesh->N * quad.D * bands.B >= kPlanesMinValues;
+    // second order keeps the cell-major layout: its gradient pass gathers
+    // every neighbour's whole row (config 3 at order 2: 22.8 ms per mixed
+    // iteration cell-major against 24.9 ms in planes)
+    return ord == 1 && (int64_t)mesh->N * quad.D * bands.B >= kPlanesMinValues;
 }
 
 // cells that own at least one boundary face (rows of the boundary copy)
@@ -428,7 +431,7 @@ int64_t nbte_problem::state_bytes(int prec, int ord) const {
               NBF * D * 4;
     }
     // plane layout: the reductions' band sums and the boundary rows
-    const int64_t pl = planes() ? D * N * (24 + 4) + std::max<int64_t>(boundary_owners(), 1) * D * B * es : 0;
+    const int64_t pl = planes_for(ord) ? D * N * (24 + 4) + std::max<int64_t>(boundary_owners(), 1) * D * B * es : 0;
     return D * N * B * es + std::max<int64_t>(ghosts, 1) * B * es + 2 * D * N * es + pl + NBF * (B + 3) * 8 +
            N * 8 * 10 + 1024 + acc + so2;
 }

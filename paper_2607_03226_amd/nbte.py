@@ -172,7 +172,9 @@ class Mesh:
         self.handle = handle
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be gone: the
+        # process's end then releases the handle
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.nbte_mesh_destroy(self.handle)
             self.handle = None
 
@@ -185,7 +187,9 @@ class ProblemHandle:
         self.n_cells = n_cells
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be gone: the
+        # process's end then releases the handle
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.nbte_problem_destroy(self.handle)
             self.handle = None
 
@@ -408,7 +412,9 @@ class Batch:
         self.members = {}
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module's globals may already be gone: the
+        # process's end then releases the handle
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.nbte_batch_destroy(self.handle)
             self.handle = None
 
